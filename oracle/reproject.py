@@ -1,0 +1,117 @@
+"""ORACLE -- test infrastructure only.  numpy wrapper over ``reproject.c``.
+
+The C file carries the statement of what is computed and the passages it
+follows (Section 5 O1/O2, Section 6 reprojection equation and Algorithms 1-2,
+Section 7 Algorithm 3 and the Patcher figure, Section 9 PSNR).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(_HERE, "reproject.c")
+LIB = os.path.join(_HERE, "liboracle_reproject.so")
+
+TARGET_RIGHT, TARGET_LEFT = 0, 1
+FILL_NONE, FILL_NEAREST_BG, FILL_SIDE_ONLY = 0, 1, 101
+
+CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared"]
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (no FMA contraction, no fast-math)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        subprocess.check_call(["gcc", *CFLAGS, SRC, "-o", LIB + ".tmp", "-lm"])
+        os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(LIB)
+        L.oracle_reproject.restype = ctypes.c_int
+        L.oracle_reproject.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_float, ctypes.c_float, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
+        L.oracle_fill_holes.restype = ctypes.c_int
+        L.oracle_fill_holes.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                        ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+        L.oracle_disparity.restype = ctypes.c_int
+        L.oracle_disparity.argtypes = [ctypes.c_float, ctypes.c_float, ctypes.c_int32,
+                                       ctypes.POINTER(ctypes.c_int32)]
+        L.oracle_hole_sse.restype = None
+        L.oracle_hole_sse.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                      ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]
+        _lib = L
+    return _lib
+
+
+def disparity(z: float, baseline_m: float, focal_px: float, width: int):
+    """Rounded disparity of one depth, or None when the pixel is not splatted."""
+    bf = np.float32(np.float32(baseline_m) * np.float32(focal_px))
+    d = ctypes.c_int32(0)
+    rc = lib().oracle_disparity(float(np.float32(z)), float(bf), width, ctypes.byref(d))
+    return None if rc != 0 else int(d.value)
+
+
+def reproject(src_rgba: np.ndarray, src_depth: np.ndarray, baseline_m: float, focal_px: float,
+              target_eye: int = TARGET_RIGHT, fill_mode: int = FILL_NEAREST_BG, nthreads: int = 1):
+    """(dst_rgba [H,W,4] u8, dst_depth [H,W] f32, dst_mask [H,W] u8)."""
+    src_rgba = np.ascontiguousarray(src_rgba, dtype=np.uint8)
+    src_depth = np.ascontiguousarray(src_depth, dtype=np.float32)
+    H, W = src_depth.shape
+    assert src_rgba.shape == (H, W, 4)
+    dst = np.empty_like(src_rgba)
+    dz = np.empty_like(src_depth)
+    mk = np.empty((H, W), dtype=np.uint8)
+    rc = lib().oracle_reproject(src_rgba.ctypes.data, src_depth.ctypes.data, W, H,
+                                float(np.float32(baseline_m)), float(np.float32(focal_px)),
+                                target_eye, fill_mode, dst.ctypes.data, dz.ctypes.data, mk.ctypes.data,
+                                nthreads)
+    if rc != 0:
+        raise ValueError("oracle_reproject: bad arguments")
+    return dst, dz, mk
+
+
+def fill_holes(rgba: np.ndarray, depth: np.ndarray, mask: np.ndarray, target_eye: int = TARGET_RIGHT,
+               fill_mode: int = FILL_NEAREST_BG):
+    """Copies of (rgba, depth, mask) with holes (mask != 0) refilled from hits."""
+    rgba = np.ascontiguousarray(rgba, dtype=np.uint8).copy()
+    depth = np.ascontiguousarray(depth, dtype=np.float32).copy()
+    mask = np.ascontiguousarray(mask, dtype=np.uint8).copy()
+    H, W = depth.shape
+    rc = lib().oracle_fill_holes(rgba.ctypes.data, depth.ctypes.data, mask.ctypes.data, W, H, target_eye,
+                                 fill_mode)
+    if rc != 0:
+        raise ValueError("oracle_fill_holes: bad arguments")
+    return rgba, depth, mask
+
+
+def hole_sse(rgba: np.ndarray, ref: np.ndarray, mask: np.ndarray | None):
+    """(sum of squared RGB errors over mask != 0 pixels, pixel count)."""
+    rgba = np.ascontiguousarray(rgba, dtype=np.uint8)
+    ref = np.ascontiguousarray(ref, dtype=np.uint8)
+    n = rgba.shape[0] * rgba.shape[1]
+    sse, cnt = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    mp = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8).ctypes.data
+    lib().oracle_hole_sse(rgba.ctypes.data, ref.ctypes.data, mp, n, ctypes.byref(sse), ctypes.byref(cnt))
+    return int(sse.value), int(cnt.value)
+
+
+def psnr_from_sse(sse: int, count_pixels: int, peak: float = 255.0) -> float:
+    """PSNR = 10 log10(peak^2 / MSE) over RGB (Section 9, PSNR); MSE 0 gives +inf."""
+    if count_pixels == 0:
+        return float("nan")
+    mse = sse / (3.0 * count_pixels)
+    if mse == 0:
+        return float("inf")
+    return 10.0 * np.log10(peak * peak / mse)
