@@ -1,0 +1,186 @@
+/*
+ * yoro.h -- C-ABI of libyoro.so: synthesise the second eye of a stereo pair
+ * from one rendered eye (colour + per-pixel depth) on an AMD Instinct
+ * MI355X (gfx950).
+ *
+ * Method: "You Only Render Once" (arXiv 2506.15183).  The rendered
+ * (dominant) eye's G-buffer (Section 3.2) is reprojected to the other eye
+ * (Section 6: reprojection equation M = (VP_left)^-1 VP_right, Algorithms 1
+ * and 2) and its disocclusions are filled from the background (Section 5
+ * Observation O2, Section 7 Patcher).  For two pinhole eyes that differ only
+ * by a shift B along x (parallel stereo) the matrix transform reduces to a
+ * per-pixel horizontal shift of d = round(B*f/z) pixels, one-signed by
+ * Observation O1, so every row is independent.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All image pointers are caller-owned DEVICE pointers.  The library never
+ *   allocates, frees or synchronises inside these calls and launches only on
+ *   the stream passed (hipStream_t given as void*; NULL = the null stream).
+ *   Every call returns as soon as its kernels are queued.
+ * - RGBA8: row-major H x W x 4 bytes, byte order R, G, B, A, contiguous,
+ *   4-byte aligned.  Depth: row-major H x W FP32, linear eye-space depth in
+ *   metres (planar z, not ray length), 4-byte aligned.  Depth > 0 is
+ *   geometry (+inf is "at infinity"); NaN, +-0 and negative depths carry no
+ *   geometry and are not splatted (not an error).
+ * - Mask: u8 per pixel, 0 = hit, 1 = disocclusion (filled, or left empty
+ *   with YORO_FILL_NONE), 2 = disocclusion with no hit anywhere in its row
+ *   (left as RGBA 0, depth +inf).
+ * - Sizes: 1 <= width <= YORO_MAX_WIDTH, 1 <= height <= YORO_MAX_HEIGHT.
+ * - Errors: arguments are checked on the host before anything is queued; a
+ *   bad argument returns YORO_ERR_INVALID_ARG (or YORO_ERR_UNSUPPORTED) and
+ *   queues nothing.  A failed launch returns YORO_ERR_DEVICE.  Faults inside
+ *   kernels surface at the caller's next synchronisation of the stream.
+ *   yoro_last_error() returns this thread's message for the last non-OK
+ *   status.  No C++ exception crosses this interface.
+ * - Determinism: collisions are resolved by a 64-bit atomicMin on
+ *   (depth bits << 32 | source column); equal depths in one row never
+ *   collide, so every output bit is independent of thread order.
+ */
+#ifndef YORO_H
+#define YORO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define YORO_VERSION 1
+#define YORO_MAX_WIDTH 8192
+#define YORO_MAX_HEIGHT 16384
+
+typedef enum yoro_target_eye {
+  /* Source = left eye, target = right eye (right camera at +B on x):
+   * target column = source column - d. */
+  YORO_TARGET_RIGHT = 0,
+  /* Source = right eye, target = left eye: target column = source column + d. */
+  YORO_TARGET_LEFT = 1
+} yoro_target_eye;
+
+typedef enum yoro_fill_mode {
+  /* Leave disocclusions empty: RGBA 0, depth +inf, mask 1. */
+  YORO_FILL_NONE = 0,
+  /* Row-wise nearest background: of the nearest hit to the left and the
+   * nearest hit to the right (in the resolved row, never a filled pixel),
+   * take the one with the larger depth; on equal depth the one on the side
+   * opposite the shift (right for YORO_TARGET_RIGHT, left for
+   * YORO_TARGET_LEFT); with one neighbour take it (Section 5 O2; Section 7,
+   * Patcher figure). */
+  YORO_FILL_NEAREST_BG = 1
+} yoro_fill_mode;
+
+typedef enum yoro_status {
+  YORO_OK = 0,
+  YORO_ERR_INVALID_ARG = 1,
+  YORO_ERR_UNSUPPORTED = 2,
+  YORO_ERR_WORKSPACE_TOO_SMALL = 3,
+  YORO_ERR_DEVICE = 4
+} yoro_status;
+
+/*
+ * yoro_reproject -- warp one frame to the other eye and (optionally) fill
+ * its disocclusions (Section 6, Algorithms 1-2; Section 7).
+ *
+ * Per source pixel (x, y) with depth z > 0:
+ *   bf = baseline_m * focal_px              (one FP32 multiply)
+ *   q  = bf / z                             (correctly rounded FP32 division)
+ *   skip unless q < width; d = roundf(q)    (halfway away from zero)
+ *   xt = x - d (TARGET_RIGHT) or x + d (TARGET_LEFT); skip unless 0 <= xt < W
+ *   the nearest depth wins target (xt, y).
+ * Hit targets take the winning source pixel's RGBA (all four bytes) and
+ * depth; the rest are disocclusions, handled per fill_mode.
+ *
+ * src_rgba, src_depth: inputs (not modified).  dst_rgba: output, required.
+ * dst_depth, dst_mask: optional outputs (NULL to skip).  Outputs must not
+ * overlap the inputs or each other.  baseline_m and focal_px: finite, > 0.
+ */
+int32_t yoro_reproject(const uint8_t* src_rgba, const float* src_depth, int32_t width, int32_t height,
+                       float baseline_m, float focal_px, int32_t target_eye, int32_t fill_mode,
+                       uint8_t* dst_rgba, float* dst_depth, uint8_t* dst_mask, void* hip_stream);
+
+/*
+ * yoro_fill_holes -- fill the disocclusions of an already warped frame in
+ * place (Section 7; Section 5 O2).  Pixels with mask == 0 are hits and are
+ * left unchanged; every other pixel is a hole and is refilled per fill_mode
+ * from the hits of its row only (so the result does not depend on order).
+ * rgba, depth, mask: in/out, all required.  YORO_FILL_NONE is a no-op.
+ */
+int32_t yoro_fill_holes(uint8_t* rgba, float* depth, uint8_t* mask, int32_t width, int32_t height,
+                        int32_t target_eye, int32_t fill_mode, void* hip_stream);
+
+/*
+ * Batched stereo synthesis: many frames of mixed sizes in one persistent
+ * launch.  Each job is one yoro_reproject call.  Rows of all jobs form one
+ * flat index space that the workgroups stride over.
+ */
+typedef struct yoro_job {
+  const uint8_t* src_rgba;
+  const float* src_depth;
+  uint8_t* dst_rgba;
+  float* dst_depth; /* nullable */
+  uint8_t* dst_mask; /* nullable */
+  int32_t width;
+  int32_t height;
+  float baseline_m;
+  float focal_px;
+  int32_t target_eye;
+  int32_t fill_mode;
+} yoro_job;
+
+/* Device workspace bytes needed for n_jobs jobs (a header plus one record
+ * per job).  Returns 0 for n_jobs <= 0 or n_jobs > YORO_MAX_BATCH_JOBS. */
+#define YORO_MAX_BATCH_JOBS 65536
+size_t yoro_stereo_batch_workspace_bytes(int32_t n_jobs);
+
+/*
+ * yoro_stereo_batch_prepare -- validate jobs_host[0..n_jobs) on the host
+ * (same rules as yoro_reproject, plus: no job's outputs may overlap any
+ * job's inputs or outputs) and queue the upload of the job table into
+ * dev_workspace (device memory, >= yoro_stereo_batch_workspace_bytes,
+ * 16-byte aligned) on hip_stream.  The upload is done by small kernels that
+ * carry the table in their arguments, so jobs_host may be freed on return
+ * and the call may be captured into a HIP graph.
+ */
+int32_t yoro_stereo_batch_prepare(const yoro_job* jobs_host, int32_t n_jobs, void* dev_workspace,
+                                  size_t workspace_bytes, void* hip_stream);
+
+/*
+ * yoro_stereo_batch_launch -- run the jobs that the last prepare on this
+ * workspace uploaded, as one persistent kernel.  max_width must be >= every
+ * job's width (it sizes the per-row scratch in LDS); rows of a wider job are
+ * skipped and counted in the workspace's error counter (see
+ * yoro_stereo_batch_errors).  Capture-safe: no allocation, copy or sync.
+ */
+int32_t yoro_stereo_batch_launch(const void* dev_workspace, int32_t max_width, void* hip_stream);
+
+/* prepare + launch. */
+int32_t yoro_stereo_batch(const yoro_job* jobs_host, int32_t n_jobs, void* dev_workspace,
+                          size_t workspace_bytes, void* hip_stream);
+
+/* Device address of the workspace's u32 error counter (rows skipped by the
+ * last launch because max_width was too small); reset by prepare. */
+const uint32_t* yoro_stereo_batch_errors(const void* dev_workspace);
+
+/*
+ * yoro_hole_sse -- hole error of a synthesised eye against a reference image
+ * (Section 9, PSNR = 10 log10(255^2 / MSE)).  Writes to dev_out[0] the sum
+ * of squared R, G, B differences over pixels with mask != 0 (over all
+ * pixels if mask is NULL) and to dev_out[1] the number of such pixels; both
+ * u64, exact.  dev_out: device, 2 x u64, 8-byte aligned; overwritten.
+ */
+int32_t yoro_hole_sse(const uint8_t* rgba, const uint8_t* ref_rgba, const uint8_t* mask, int32_t width,
+                      int32_t height, uint64_t* dev_out, void* hip_stream);
+
+/* This thread's message for the last non-OK status ("" if none). */
+const char* yoro_last_error(void);
+
+/* YORO_VERSION of the built library. */
+int32_t yoro_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* YORO_H */

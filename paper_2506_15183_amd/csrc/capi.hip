@@ -1,0 +1,328 @@
+// C-ABI of libyoro.so (declared in include/yoro.h): host-side validation,
+// launch geometry, and the batch job table.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "yoro.h"
+#include "yoro_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int32_t fail(int32_t status, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return status;
+}
+
+int32_t ok() { return YORO_OK; }
+
+// Per-device facts, queried once per device.
+struct DeviceFacts {
+  int cus = 0;
+  bool valid = false;
+};
+std::mutex g_dev_mu;
+std::vector<DeviceFacts> g_dev;
+
+bool device_facts(DeviceFacts* out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  std::lock_guard<std::mutex> lk(g_dev_mu);
+  if ((int)g_dev.size() <= dev) g_dev.resize(dev + 1);
+  if (!g_dev[dev].valid) {
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) != hipSuccess) return false;
+    g_dev[dev].cus = p.multiProcessorCount;
+    g_dev[dev].valid = true;
+  }
+  *out = g_dev[dev];
+  return true;
+}
+
+// Pixels per thread for a row of the given width: the smallest instantiated
+// value with kThreads * ppt >= width.
+int pick_ppt(int width) {
+  static const int kPPT[] = {1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 16, 20, 24, 28, 32};
+  const int need = (width + yoro::kThreads - 1) / yoro::kThreads;
+  for (int p : kPPT)
+    if (p >= need) return p;
+  return -1;
+}
+
+bool aligned4(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }
+
+struct Range {
+  uintptr_t lo, hi;  // [lo, hi)
+  bool out;
+};
+
+bool overlaps(const Range& a, const Range& b) { return a.lo < b.hi && b.lo < a.hi; }
+
+int32_t check_frame(const void* src_rgba, const void* src_depth, int32_t width, int32_t height, float baseline_m,
+                    float focal_px, int32_t target_eye, int32_t fill_mode, const void* dst_rgba,
+                    const void* dst_depth, const void* dst_mask, const char* who) {
+  if (!src_rgba || !src_depth || !dst_rgba)
+    return fail(YORO_ERR_INVALID_ARG, "%s: src_rgba, src_depth and dst_rgba are required", who);
+  if (width <= 0 || height <= 0)
+    return fail(YORO_ERR_INVALID_ARG, "%s: width %d and height %d must be positive", who, width, height);
+  if (width > YORO_MAX_WIDTH || height > YORO_MAX_HEIGHT)
+    return fail(YORO_ERR_UNSUPPORTED, "%s: %dx%d exceeds the supported %dx%d", who, width, height, YORO_MAX_WIDTH,
+                YORO_MAX_HEIGHT);
+  if (!std::isfinite(baseline_m) || !(baseline_m > 0.0f) || !std::isfinite(focal_px) || !(focal_px > 0.0f))
+    return fail(YORO_ERR_INVALID_ARG, "%s: baseline %g and focal %g must be finite and positive", who,
+                (double)baseline_m, (double)focal_px);
+  if (target_eye != YORO_TARGET_RIGHT && target_eye != YORO_TARGET_LEFT)
+    return fail(YORO_ERR_INVALID_ARG, "%s: unknown target eye %d", who, target_eye);
+  if (fill_mode != YORO_FILL_NONE && fill_mode != YORO_FILL_NEAREST_BG)
+    return fail(YORO_ERR_INVALID_ARG, "%s: unknown fill mode %d", who, fill_mode);
+  if (!aligned4(src_rgba) || !aligned4(src_depth) || !aligned4(dst_rgba) || (dst_depth && !aligned4(dst_depth)))
+    return fail(YORO_ERR_INVALID_ARG, "%s: RGBA and depth pointers must be 4-byte aligned", who);
+  const uintptr_t n = (uintptr_t)width * (uintptr_t)height;
+  std::vector<Range> r = {{(uintptr_t)src_rgba, (uintptr_t)src_rgba + 4 * n, false},
+                          {(uintptr_t)src_depth, (uintptr_t)src_depth + 4 * n, false},
+                          {(uintptr_t)dst_rgba, (uintptr_t)dst_rgba + 4 * n, true}};
+  if (dst_depth) r.push_back({(uintptr_t)dst_depth, (uintptr_t)dst_depth + 4 * n, true});
+  if (dst_mask) r.push_back({(uintptr_t)dst_mask, (uintptr_t)dst_mask + n, true});
+  for (size_t i = 0; i < r.size(); ++i)
+    for (size_t j = i + 1; j < r.size(); ++j)
+      if ((r[i].out || r[j].out) && overlaps(r[i], r[j]))
+        return fail(YORO_ERR_INVALID_ARG, "%s: an output buffer overlaps another buffer", who);
+  return YORO_OK;
+}
+
+yoro::DevJob make_job(const yoro_job& j, uint32_t row_start) {
+  yoro::DevJob d;
+  d.src_rgba = reinterpret_cast<const uint32_t*>(j.src_rgba);
+  d.src_depth = j.src_depth;
+  d.dst_rgba = reinterpret_cast<uint32_t*>(j.dst_rgba);
+  d.dst_depth = j.dst_depth;
+  d.dst_mask = j.dst_mask;
+  d.width = j.width;
+  d.height = j.height;
+  d.baseline_m = j.baseline_m;
+  d.focal_px = j.focal_px;
+  d.target_eye = j.target_eye;
+  d.fill_mode = j.fill_mode;
+  d.row_start = row_start;
+  d.pad_ = 0;
+  return d;
+}
+
+int grid_for(int rows, int blocks_per_cu) {
+  DeviceFacts f;
+  const int cus = device_facts(&f) ? f.cus : 256;
+  const long long g = (long long)cus * blocks_per_cu;
+  return (int)std::max<long long>(1, std::min<long long>(rows, g));
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t yoro_version(void) { return YORO_VERSION; }
+
+const char* yoro_last_error(void) { return g_err.c_str(); }
+
+int32_t yoro_reproject(const uint8_t* src_rgba, const float* src_depth, int32_t width, int32_t height,
+                       float baseline_m, float focal_px, int32_t target_eye, int32_t fill_mode, uint8_t* dst_rgba,
+                       float* dst_depth, uint8_t* dst_mask, void* hip_stream) {
+  try {
+    int32_t st = check_frame(src_rgba, src_depth, width, height, baseline_m, focal_px, target_eye, fill_mode,
+                             dst_rgba, dst_depth, dst_mask, "yoro_reproject");
+    if (st != YORO_OK) return st;
+    yoro_job j{src_rgba, src_depth, dst_rgba, dst_depth, dst_mask, width, height, baseline_m, focal_px,
+               target_eye, fill_mode};
+    const int ppt = pick_ppt(width);
+    if (ppt < 0) return fail(YORO_ERR_UNSUPPORTED, "yoro_reproject: width %d too wide", width);
+    const int grid = grid_for(height, yoro::warp_blocks_per_cu(ppt, false));
+    hipError_t e = yoro::launch_warp_single(make_job(j, 0), ppt, grid, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return fail(YORO_ERR_DEVICE, "yoro_reproject: launch failed: %s", hipGetErrorString(e));
+    return ok();
+  } catch (...) {
+    return fail(YORO_ERR_DEVICE, "yoro_reproject: internal error");
+  }
+}
+
+int32_t yoro_fill_holes(uint8_t* rgba, float* depth, uint8_t* mask, int32_t width, int32_t height,
+                        int32_t target_eye, int32_t fill_mode, void* hip_stream) {
+  try {
+    if (!rgba || !depth || !mask) return fail(YORO_ERR_INVALID_ARG, "yoro_fill_holes: rgba, depth, mask required");
+    if (width <= 0 || height <= 0)
+      return fail(YORO_ERR_INVALID_ARG, "yoro_fill_holes: width %d and height %d must be positive", width, height);
+    if (width > YORO_MAX_WIDTH || height > YORO_MAX_HEIGHT)
+      return fail(YORO_ERR_UNSUPPORTED, "yoro_fill_holes: %dx%d exceeds the supported size", width, height);
+    if (target_eye != YORO_TARGET_RIGHT && target_eye != YORO_TARGET_LEFT)
+      return fail(YORO_ERR_INVALID_ARG, "yoro_fill_holes: unknown target eye %d", target_eye);
+    if (fill_mode != YORO_FILL_NONE && fill_mode != YORO_FILL_NEAREST_BG)
+      return fail(YORO_ERR_INVALID_ARG, "yoro_fill_holes: unknown fill mode %d", fill_mode);
+    if (!aligned4(rgba) || !aligned4(depth))
+      return fail(YORO_ERR_INVALID_ARG, "yoro_fill_holes: rgba and depth must be 4-byte aligned");
+    const uintptr_t n = (uintptr_t)width * (uintptr_t)height;
+    Range a{(uintptr_t)rgba, (uintptr_t)rgba + 4 * n, true}, b{(uintptr_t)depth, (uintptr_t)depth + 4 * n, true},
+        c{(uintptr_t)mask, (uintptr_t)mask + n, true};
+    if (overlaps(a, b) || overlaps(a, c) || overlaps(b, c))
+      return fail(YORO_ERR_INVALID_ARG, "yoro_fill_holes: buffers overlap");
+    if (fill_mode == YORO_FILL_NONE) return ok();
+    const int ppt = pick_ppt(width);
+    const int grid = grid_for(height, yoro::fill_blocks_per_cu(ppt));
+    hipError_t e = yoro::launch_fill(reinterpret_cast<uint32_t*>(rgba), depth, mask, width, height, target_eye,
+                                     fill_mode, ppt, grid, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return fail(YORO_ERR_DEVICE, "yoro_fill_holes: launch failed: %s", hipGetErrorString(e));
+    return ok();
+  } catch (...) {
+    return fail(YORO_ERR_DEVICE, "yoro_fill_holes: internal error");
+  }
+}
+
+size_t yoro_stereo_batch_workspace_bytes(int32_t n_jobs) {
+  if (n_jobs <= 0 || n_jobs > YORO_MAX_BATCH_JOBS) return 0;
+  return sizeof(yoro::BatchHeader) + (size_t)n_jobs * sizeof(yoro::DevJob);
+}
+
+int32_t yoro_stereo_batch_prepare(const yoro_job* jobs, int32_t n_jobs, void* dev_workspace, size_t workspace_bytes,
+                                  void* hip_stream) {
+  try {
+    if (!jobs || n_jobs <= 0 || n_jobs > YORO_MAX_BATCH_JOBS)
+      return fail(YORO_ERR_INVALID_ARG, "yoro_stereo_batch_prepare: need 1..%d jobs", YORO_MAX_BATCH_JOBS);
+    if (!dev_workspace || (reinterpret_cast<uintptr_t>(dev_workspace) & 15u))
+      return fail(YORO_ERR_INVALID_ARG, "yoro_stereo_batch_prepare: workspace must be non-null and 16-byte aligned");
+    if (workspace_bytes < yoro_stereo_batch_workspace_bytes(n_jobs))
+      return fail(YORO_ERR_WORKSPACE_TOO_SMALL, "yoro_stereo_batch_prepare: workspace %zu < %zu bytes",
+                  workspace_bytes, yoro_stereo_batch_workspace_bytes(n_jobs));
+    std::vector<Range> ranges;
+    ranges.reserve((size_t)n_jobs * 5);
+    uint64_t rows = 0;
+    int32_t max_w = 0;
+    for (int32_t i = 0; i < n_jobs; ++i) {
+      const yoro_job& j = jobs[i];
+      char who[64];
+      snprintf(who, sizeof(who), "yoro_stereo_batch_prepare: job %d", i);
+      int32_t st = check_frame(j.src_rgba, j.src_depth, j.width, j.height, j.baseline_m, j.focal_px, j.target_eye,
+                               j.fill_mode, j.dst_rgba, j.dst_depth, j.dst_mask, who);
+      if (st != YORO_OK) return st;
+      const uintptr_t n = (uintptr_t)j.width * (uintptr_t)j.height;
+      ranges.push_back({(uintptr_t)j.src_rgba, (uintptr_t)j.src_rgba + 4 * n, false});
+      ranges.push_back({(uintptr_t)j.src_depth, (uintptr_t)j.src_depth + 4 * n, false});
+      ranges.push_back({(uintptr_t)j.dst_rgba, (uintptr_t)j.dst_rgba + 4 * n, true});
+      if (j.dst_depth) ranges.push_back({(uintptr_t)j.dst_depth, (uintptr_t)j.dst_depth + 4 * n, true});
+      if (j.dst_mask) ranges.push_back({(uintptr_t)j.dst_mask, (uintptr_t)j.dst_mask + n, true});
+      rows += (uint64_t)j.height;
+      max_w = std::max(max_w, j.width);
+    }
+    if (rows > 0xFFFFFFFFull) return fail(YORO_ERR_UNSUPPORTED, "yoro_stereo_batch_prepare: too many rows");
+    // No output may overlap anything else: sort by start; an output must not
+    // overlap its sorted neighbours' spans (track the furthest end so far).
+    std::sort(ranges.begin(), ranges.end(), [](const Range& a, const Range& b) { return a.lo < b.lo; });
+    uintptr_t far_hi = 0;
+    bool far_out = false;
+    for (size_t i = 0; i < ranges.size(); ++i) {
+      if (i > 0 && ranges[i].lo < far_hi && (ranges[i].out || far_out))
+        return fail(YORO_ERR_INVALID_ARG, "yoro_stereo_batch_prepare: an output buffer overlaps another buffer");
+      if (ranges[i].hi > far_hi) {
+        far_hi = ranges[i].hi;
+        far_out = ranges[i].out;
+      } else if (ranges[i].out) {
+        far_out = true;
+      }
+    }
+    hipStream_t s = (hipStream_t)hip_stream;
+    auto* hdr = reinterpret_cast<yoro::BatchHeader*>(dev_workspace);
+    auto* dj = reinterpret_cast<yoro::DevJob*>(hdr + 1);
+    yoro::BatchHeader h{};
+    h.n_jobs = (uint32_t)n_jobs;
+    h.total_rows = (uint32_t)rows;
+    h.max_width = (uint32_t)max_w;
+    h.errors = 0;
+    hipError_t e = yoro::launch_header(h, hdr, s);
+    uint32_t row = 0;
+    for (int32_t first = 0; e == hipSuccess && first < n_jobs; first += yoro::kUploadChunk) {
+      yoro::UploadChunk c{};
+      c.first = (uint32_t)first;
+      c.count = (uint32_t)std::min(yoro::kUploadChunk, n_jobs - first);
+      for (uint32_t k = 0; k < c.count; ++k) {
+        c.jobs[k] = make_job(jobs[first + k], row);
+        row += (uint32_t)jobs[first + k].height;
+      }
+      e = yoro::launch_upload(c, dj, s);
+    }
+    if (e != hipSuccess)
+      return fail(YORO_ERR_DEVICE, "yoro_stereo_batch_prepare: upload failed: %s", hipGetErrorString(e));
+    return ok();
+  } catch (...) {
+    return fail(YORO_ERR_DEVICE, "yoro_stereo_batch_prepare: internal error");
+  }
+}
+
+int32_t yoro_stereo_batch_launch(const void* dev_workspace, int32_t max_width, void* hip_stream) {
+  try {
+    if (!dev_workspace) return fail(YORO_ERR_INVALID_ARG, "yoro_stereo_batch_launch: null workspace");
+    if (max_width <= 0 || max_width > YORO_MAX_WIDTH)
+      return fail(YORO_ERR_INVALID_ARG, "yoro_stereo_batch_launch: max_width %d out of range", max_width);
+    const int ppt = pick_ppt(max_width);
+    const auto* hdr = reinterpret_cast<const yoro::BatchHeader*>(dev_workspace);
+    const auto* dj = reinterpret_cast<const yoro::DevJob*>(hdr + 1);
+    // Persistent grid: as many workgroups as fit on the chip at once.
+    DeviceFacts f;
+    const int cus = device_facts(&f) ? f.cus : 256;
+    const int grid = cus * yoro::warp_blocks_per_cu(ppt, true);
+    hipError_t e = yoro::launch_warp_batch(hdr, dj, ppt, grid, (hipStream_t)hip_stream);
+    if (e != hipSuccess)
+      return fail(YORO_ERR_DEVICE, "yoro_stereo_batch_launch: launch failed: %s", hipGetErrorString(e));
+    return ok();
+  } catch (...) {
+    return fail(YORO_ERR_DEVICE, "yoro_stereo_batch_launch: internal error");
+  }
+}
+
+int32_t yoro_stereo_batch(const yoro_job* jobs, int32_t n_jobs, void* dev_workspace, size_t workspace_bytes,
+                          void* hip_stream) {
+  int32_t st = yoro_stereo_batch_prepare(jobs, n_jobs, dev_workspace, workspace_bytes, hip_stream);
+  if (st != YORO_OK) return st;
+  int32_t max_w = 0;
+  for (int32_t i = 0; i < n_jobs; ++i) max_w = std::max(max_w, jobs[i].width);
+  return yoro_stereo_batch_launch(dev_workspace, max_w, hip_stream);
+}
+
+const uint32_t* yoro_stereo_batch_errors(const void* dev_workspace) {
+  if (!dev_workspace) return nullptr;
+  return &reinterpret_cast<const yoro::BatchHeader*>(dev_workspace)->errors;
+}
+
+int32_t yoro_hole_sse(const uint8_t* rgba, const uint8_t* ref_rgba, const uint8_t* mask, int32_t width,
+                      int32_t height, uint64_t* dev_out, void* hip_stream) {
+  try {
+    if (!rgba || !ref_rgba || !dev_out) return fail(YORO_ERR_INVALID_ARG, "yoro_hole_sse: null pointer");
+    if (width <= 0 || height <= 0) return fail(YORO_ERR_INVALID_ARG, "yoro_hole_sse: bad size");
+    if (!aligned4(rgba) || !aligned4(ref_rgba) || (reinterpret_cast<uintptr_t>(dev_out) & 7u))
+      return fail(YORO_ERR_INVALID_ARG, "yoro_hole_sse: misaligned pointer");
+    const int64_t n = (int64_t)width * (int64_t)height;
+    DeviceFacts f;
+    const int cus = device_facts(&f) ? f.cus : 256;
+    const int64_t want = (n + yoro::kThreads - 1) / yoro::kThreads;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)cus * 8));
+    hipError_t e = yoro::launch_hole_sse(reinterpret_cast<const uint32_t*>(rgba),
+                                         reinterpret_cast<const uint32_t*>(ref_rgba), mask, n,
+                                         reinterpret_cast<unsigned long long*>(dev_out), grid,
+                                         (hipStream_t)hip_stream);
+    if (e != hipSuccess) return fail(YORO_ERR_DEVICE, "yoro_hole_sse: launch failed: %s", hipGetErrorString(e));
+    return ok();
+  } catch (...) {
+    return fail(YORO_ERR_DEVICE, "yoro_hole_sse: internal error");
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,75 @@
+// Internal definitions shared by the HIP kernels and the C-ABI host code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace yoro {
+
+// One frame of work as the kernels see it.  RGBA8 pixels are moved as one
+// 32-bit word each (byte order preserved).
+struct DevJob {
+  const uint32_t* src_rgba;
+  const float* src_depth;
+  uint32_t* dst_rgba;
+  float* dst_depth;  // nullable
+  uint8_t* dst_mask; // nullable
+  int32_t width;
+  int32_t height;
+  float baseline_m;
+  float focal_px;
+  int32_t target_eye;  // 0: target right (x_t = x - d); 1: target left (x_t = x + d)
+  int32_t fill_mode;   // 0: none; 1: nearest background
+  uint32_t row_start;  // first row of this job in the batch's flat row space
+  uint32_t pad_;
+};
+static_assert(sizeof(DevJob) == 72, "DevJob layout");
+
+// Header at the start of a batch workspace.
+struct BatchHeader {
+  uint32_t n_jobs;
+  uint32_t total_rows;
+  uint32_t max_width;
+  uint32_t errors;  // rows skipped because they did not fit the launch's LDS
+  uint32_t pad_[12];
+};
+static_assert(sizeof(BatchHeader) == 64, "BatchHeader layout");
+
+// Jobs carried in one upload kernel's arguments.
+constexpr int kUploadChunk = 24;
+struct UploadChunk {
+  DevJob jobs[kUploadChunk];
+  uint32_t first;
+  uint32_t count;
+};
+
+constexpr int kThreads = 256;      // threads per workgroup (4 waves of 64)
+constexpr int kMaxPPT = 32;        // pixels per thread: width <= kThreads * kMaxPPT = 8192
+
+// Dynamic LDS bytes for a row kernel whose rows are at most kThreads*ppt wide.
+inline size_t warp_lds_bytes(int ppt) {
+  const size_t wcap = (size_t)kThreads * ppt;
+  const size_t words = (wcap + 63) / 64;
+  return wcap * 8 + wcap * 4 + words * 8 + words * 4 * 2;
+}
+inline size_t fill_lds_bytes(int ppt) {
+  const size_t wcap = (size_t)kThreads * ppt;
+  const size_t words = (wcap + 63) / 64;
+  return wcap * 4 + wcap * 4 + words * 8 + words * 4 * 2;
+}
+
+// Launchers (defined in warp_fill.hip).  They return hipSuccess or the launch error.
+hipError_t launch_warp_single(const DevJob& job, int ppt, int grid, hipStream_t stream);
+hipError_t launch_warp_batch(const BatchHeader* hdr, const DevJob* jobs, int ppt, int grid,
+                             hipStream_t stream);
+hipError_t launch_upload(const UploadChunk& chunk, DevJob* dst, hipStream_t stream);
+hipError_t launch_header(BatchHeader hdr, BatchHeader* dst, hipStream_t stream);
+hipError_t launch_fill(uint32_t* rgba, float* depth, uint8_t* mask, int32_t width, int32_t height,
+                       int32_t target_eye, int32_t fill_mode, int ppt, int grid, hipStream_t stream);
+hipError_t launch_hole_sse(const uint32_t* rgba, const uint32_t* ref, const uint8_t* mask, int64_t n,
+                           unsigned long long* out, int grid, hipStream_t stream);
+// Occupancy-derived workgroups per CU for the row kernels at a given ppt.
+int warp_blocks_per_cu(int ppt, bool batch);
+int fill_blocks_per_cu(int ppt);
+
+}  // namespace yoro

@@ -1,0 +1,206 @@
+"""Thin Python binding of libyoro.so (include/yoro.h).
+
+Argument marshalling only: torch CUDA tensors in, their device pointers and
+torch's current HIP stream out to the C-ABI.  Every step of the method runs
+in the library's HIP kernels; there is no CPU fallback, and loading fails
+loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libyoro.so")
+
+TARGET_RIGHT, TARGET_LEFT = 0, 1
+FILL_NONE, FILL_NEAREST_BG = 0, 1
+OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE_TOO_SMALL, ERR_DEVICE = 0, 1, 2, 3, 4
+MAX_WIDTH, MAX_HEIGHT = 8192, 16384
+
+# Every symbol include/yoro.h declares.
+EXPORTS = (
+    "yoro_reproject",
+    "yoro_fill_holes",
+    "yoro_stereo_batch_workspace_bytes",
+    "yoro_stereo_batch_prepare",
+    "yoro_stereo_batch_launch",
+    "yoro_stereo_batch",
+    "yoro_stereo_batch_errors",
+    "yoro_hole_sse",
+    "yoro_last_error",
+    "yoro_version",
+)
+
+
+class YoroError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"yoro status {status}: {message}")
+        self.status = status
+
+
+class Job(ctypes.Structure):
+    """yoro_job."""
+
+    _fields_ = [
+        ("src_rgba", ctypes.c_void_p),
+        ("src_depth", ctypes.c_void_p),
+        ("dst_rgba", ctypes.c_void_p),
+        ("dst_depth", ctypes.c_void_p),
+        ("dst_mask", ctypes.c_void_p),
+        ("width", ctypes.c_int32),
+        ("height", ctypes.c_int32),
+        ("baseline_m", ctypes.c_float),
+        ("focal_px", ctypes.c_float),
+        ("target_eye", ctypes.c_int32),
+        ("fill_mode", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+
+def load():
+    """Load libyoro.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libyoro.so not built ({LIB_PATH}); run __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_float
+    L.yoro_reproject.argtypes = [vp, vp, i32, i32, f32, f32, i32, i32, vp, vp, vp, vp]
+    L.yoro_reproject.restype = i32
+    L.yoro_fill_holes.argtypes = [vp, vp, vp, i32, i32, i32, i32, vp]
+    L.yoro_fill_holes.restype = i32
+    L.yoro_stereo_batch_workspace_bytes.argtypes = [i32]
+    L.yoro_stereo_batch_workspace_bytes.restype = ctypes.c_size_t
+    L.yoro_stereo_batch_prepare.argtypes = [ctypes.POINTER(Job), i32, vp, ctypes.c_size_t, vp]
+    L.yoro_stereo_batch_prepare.restype = i32
+    L.yoro_stereo_batch_launch.argtypes = [vp, i32, vp]
+    L.yoro_stereo_batch_launch.restype = i32
+    L.yoro_stereo_batch.argtypes = [ctypes.POINTER(Job), i32, vp, ctypes.c_size_t, vp]
+    L.yoro_stereo_batch.restype = i32
+    L.yoro_stereo_batch_errors.argtypes = [vp]
+    L.yoro_stereo_batch_errors.restype = vp
+    L.yoro_hole_sse.argtypes = [vp, vp, vp, i32, i32, vp, vp]
+    L.yoro_hole_sse.restype = i32
+    L.yoro_last_error.argtypes = []
+    L.yoro_last_error.restype = ctypes.c_char_p
+    L.yoro_version.argtypes = []
+    L.yoro_version.restype = i32
+    _lib = L
+    return L
+
+
+def _check(status: int):
+    if status != OK:
+        raise YoroError(status, load().yoro_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _need(t, dtype, shape, name):
+    if t.dtype != dtype or tuple(t.shape) != tuple(shape) or not t.is_contiguous() or not t.is_cuda:
+        raise ValueError(f"{name}: want contiguous CUDA {dtype} {tuple(shape)}, got {t.dtype} "
+                         f"{tuple(t.shape)} on {t.device}")
+
+
+def reproject(src_rgba, src_depth, baseline_m: float, focal_px: float, target_eye: int = TARGET_RIGHT,
+              fill_mode: int = FILL_NEAREST_BG, out=None, with_depth: bool = True, with_mask: bool = True,
+              stream=None):
+    """Warp one frame to the other eye.  Returns (rgba, depth or None, mask or None)."""
+    H, W = src_depth.shape
+    _need(src_rgba, torch.uint8, (H, W, 4), "src_rgba")
+    _need(src_depth, torch.float32, (H, W), "src_depth")
+    if out is None:
+        dev = src_depth.device
+        out = (torch.empty((H, W, 4), dtype=torch.uint8, device=dev),
+               torch.empty((H, W), dtype=torch.float32, device=dev) if with_depth else None,
+               torch.empty((H, W), dtype=torch.uint8, device=dev) if with_mask else None)
+    rgba, depth, mask = out
+    _check(load().yoro_reproject(_ptr(src_rgba), _ptr(src_depth), W, H, float(baseline_m), float(focal_px),
+                                 int(target_eye), int(fill_mode), _ptr(rgba), _ptr(depth), _ptr(mask),
+                                 _stream(stream)))
+    return rgba, depth, mask
+
+
+def fill_holes(rgba, depth, mask, target_eye: int = TARGET_RIGHT, fill_mode: int = FILL_NEAREST_BG, stream=None):
+    """Fill holes (mask != 0) of a warped frame in place."""
+    H, W = depth.shape
+    _need(rgba, torch.uint8, (H, W, 4), "rgba")
+    _need(depth, torch.float32, (H, W), "depth")
+    _need(mask, torch.uint8, (H, W), "mask")
+    _check(load().yoro_fill_holes(_ptr(rgba), _ptr(depth), _ptr(mask), W, H, int(target_eye), int(fill_mode),
+                                  _stream(stream)))
+    return rgba, depth, mask
+
+
+def make_job(src_rgba, src_depth, dst_rgba, dst_depth, dst_mask, baseline_m, focal_px,
+             target_eye=TARGET_RIGHT, fill_mode=FILL_NEAREST_BG) -> Job:
+    H, W = src_depth.shape
+    return Job(src_rgba.data_ptr(), src_depth.data_ptr(), dst_rgba.data_ptr(),
+               None if dst_depth is None else dst_depth.data_ptr(),
+               None if dst_mask is None else dst_mask.data_ptr(), W, H, float(baseline_m), float(focal_px),
+               int(target_eye), int(fill_mode))
+
+
+class StereoBatch:
+    """A device-resident job table plus the persistent batched launch.
+
+    ``prepare`` validates the jobs and queues the table upload; ``launch``
+    runs them (capture-safe).  Tensors referenced by the jobs must stay alive
+    while launches that use them are in flight.
+    """
+
+    def __init__(self, jobs, device=None):
+        L = load()
+        self.n = len(jobs)
+        self.jobs = (Job * self.n)(*jobs)
+        nbytes = L.yoro_stereo_batch_workspace_bytes(self.n)
+        if nbytes == 0:
+            raise ValueError("bad job count")
+        self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=device or "cuda")
+        self.max_width = max(j.width for j in jobs)
+
+    def prepare(self, stream=None):
+        _check(load().yoro_stereo_batch_prepare(self.jobs, self.n, _ptr(self.workspace), self.workspace.numel(),
+                                                _stream(stream)))
+
+    def launch(self, stream=None, max_width=None):
+        _check(load().yoro_stereo_batch_launch(_ptr(self.workspace), int(max_width or self.max_width),
+                                               _stream(stream)))
+
+    def run(self, stream=None):
+        _check(load().yoro_stereo_batch(self.jobs, self.n, _ptr(self.workspace), self.workspace.numel(),
+                                        _stream(stream)))
+
+    def errors(self) -> int:
+        """Rows the last launch skipped (reads the device counter; synchronises)."""
+        return int(self.workspace[12:16].view(torch.int32).item())
+
+
+def hole_sse(rgba, ref_rgba, mask=None, out=None, stream=None):
+    """(device u64[2]: sum of squared RGB errors over mask != 0, pixel count)."""
+    H, W = rgba.shape[:2]
+    _need(rgba, torch.uint8, (H, W, 4), "rgba")
+    _need(ref_rgba, torch.uint8, (H, W, 4), "ref_rgba")
+    if mask is not None:
+        _need(mask, torch.uint8, (H, W), "mask")
+    if out is None:
+        out = torch.empty(2, dtype=torch.int64, device=rgba.device)
+    _check(load().yoro_hole_sse(_ptr(rgba), _ptr(ref_rgba), _ptr(mask), W, H, _ptr(out), _stream(stream)))
+    return out
+
+
+def version() -> int:
+    return int(load().yoro_version())

@@ -1,0 +1,76 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol the header
+declares, and rejects bad arguments on the host before touching a device."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "yoro.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(yoro_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    fns = header_functions()
+    for name in ("yoro_reproject", "yoro_fill_holes", "yoro_stereo_batch"):
+        assert name in fns
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2506_15183_amd import yoro
+
+    lib = yoro.load()
+    for name in header_functions():
+        assert hasattr(lib, name), name
+    assert set(header_functions()) == set(yoro.EXPORTS)
+    assert yoro.version() == 1
+
+
+def test_host_validation_rejects_without_launching():
+    from paper_2506_15183_amd import yoro
+
+    L = yoro.load()
+    fake = ctypes.c_void_p(0x10000)
+    fake2 = ctypes.c_void_p(0x20000000)
+    fake3 = ctypes.c_void_p(0x40000000)
+    # null required pointer
+    assert L.yoro_reproject(None, fake, 8, 8, 0.06, 900.0, 0, 1, fake2, None, None, None) == yoro.ERR_INVALID_ARG
+    assert b"required" in L.yoro_last_error()
+    # sizes
+    assert L.yoro_reproject(fake, fake2, 0, 8, 0.06, 900.0, 0, 1, fake3, None, None, None) == yoro.ERR_INVALID_ARG
+    assert L.yoro_reproject(fake, fake2, 8193, 8, 0.06, 900.0, 0, 1, fake3, None, None, None) == yoro.ERR_UNSUPPORTED
+    # camera
+    for B, f in [(0.0, 900.0), (-0.06, 900.0), (float("inf"), 900.0), (0.06, float("nan"))]:
+        assert L.yoro_reproject(fake, fake2, 8, 8, B, f, 0, 1, fake3, None, None, None) == yoro.ERR_INVALID_ARG
+    # eye / mode
+    assert L.yoro_reproject(fake, fake2, 8, 8, 0.06, 900.0, 2, 1, fake3, None, None, None) == yoro.ERR_INVALID_ARG
+    assert L.yoro_reproject(fake, fake2, 8, 8, 0.06, 900.0, 0, 7, fake3, None, None, None) == yoro.ERR_INVALID_ARG
+    # alignment
+    odd = ctypes.c_void_p(0x10001)
+    assert L.yoro_reproject(odd, fake2, 8, 8, 0.06, 900.0, 0, 1, fake3, None, None, None) == yoro.ERR_INVALID_ARG
+    # overlap: output inside the source colour
+    inside = ctypes.c_void_p(0x10000 + 16)
+    assert L.yoro_reproject(fake, fake2, 8, 8, 0.06, 900.0, 0, 1, inside, None, None, None) == yoro.ERR_INVALID_ARG
+    assert b"overlap" in L.yoro_last_error()
+    # fill_holes
+    assert L.yoro_fill_holes(None, fake2, fake3, 8, 8, 0, 1, None) == yoro.ERR_INVALID_ARG
+    # batch
+    assert L.yoro_stereo_batch_workspace_bytes(0) == 0
+    assert L.yoro_stereo_batch_workspace_bytes(64) == 64 + 64 * 72
+    jobs = (yoro.Job * 2)()
+    for j in jobs:
+        j.src_rgba, j.src_depth, j.dst_rgba = 0x10000, 0x20000000, 0x40000000
+        j.width, j.height, j.baseline_m, j.focal_px, j.target_eye, j.fill_mode = 8, 8, 0.06, 900.0, 0, 1
+    ws = ctypes.c_void_p(0x7000000)
+    # both jobs write the same output
+    assert L.yoro_stereo_batch_prepare(jobs, 2, ws, 4096, None) == yoro.ERR_INVALID_ARG
+    assert b"overlap" in L.yoro_last_error()
+    assert L.yoro_stereo_batch_prepare(jobs, 2, ws, 8, None) == yoro.ERR_WORKSPACE_TOO_SMALL
+    assert L.yoro_stereo_batch_launch(ws, 0, None) == yoro.ERR_INVALID_ARG
