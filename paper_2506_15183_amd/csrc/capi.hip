@@ -53,15 +53,7 @@ bool device_facts(DeviceFacts* out) {
   return true;
 }
 
-// Pixels per thread for a row of the given width: the smallest instantiated
-// value with kThreads * ppt >= width.
-int pick_ppt(int width) {
-  static const int kPPT[] = {1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 16, 20, 24, 28, 32};
-  const int need = (width + yoro::kThreads - 1) / yoro::kThreads;
-  for (int p : kPPT)
-    if (p >= need) return p;
-  return -1;
-}
+int pick_ppt(int width) { return yoro::ppt_for(width); }
 
 bool aligned4(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }
 
@@ -148,7 +140,7 @@ int32_t yoro_reproject(const uint8_t* src_rgba, const float* src_depth, int32_t 
                target_eye, fill_mode};
     const int ppt = pick_ppt(width);
     if (ppt < 0) return fail(YORO_ERR_UNSUPPORTED, "yoro_reproject: width %d too wide", width);
-    const int grid = grid_for(height, yoro::warp_blocks_per_cu(ppt, false));
+    const int grid = grid_for(height, yoro::warp_blocks_per_cu(width, false));
     hipError_t e = yoro::launch_warp_single(make_job(j, 0), ppt, grid, (hipStream_t)hip_stream);
     if (e != hipSuccess) return fail(YORO_ERR_DEVICE, "yoro_reproject: launch failed: %s", hipGetErrorString(e));
     return ok();
@@ -178,7 +170,7 @@ int32_t yoro_fill_holes(uint8_t* rgba, float* depth, uint8_t* mask, int32_t widt
       return fail(YORO_ERR_INVALID_ARG, "yoro_fill_holes: buffers overlap");
     if (fill_mode == YORO_FILL_NONE) return ok();
     const int ppt = pick_ppt(width);
-    const int grid = grid_for(height, yoro::fill_blocks_per_cu(ppt));
+    const int grid = grid_for(height, yoro::fill_blocks_per_cu(width));
     hipError_t e = yoro::launch_fill(reinterpret_cast<uint32_t*>(rgba), depth, mask, width, height, target_eye,
                                      fill_mode, ppt, grid, (hipStream_t)hip_stream);
     if (e != hipSuccess) return fail(YORO_ERR_DEVICE, "yoro_fill_holes: launch failed: %s", hipGetErrorString(e));
@@ -272,14 +264,13 @@ int32_t yoro_stereo_batch_launch(const void* dev_workspace, int32_t max_width, v
     if (!dev_workspace) return fail(YORO_ERR_INVALID_ARG, "yoro_stereo_batch_launch: null workspace");
     if (max_width <= 0 || max_width > YORO_MAX_WIDTH)
       return fail(YORO_ERR_INVALID_ARG, "yoro_stereo_batch_launch: max_width %d out of range", max_width);
-    const int ppt = pick_ppt(max_width);
     const auto* hdr = reinterpret_cast<const yoro::BatchHeader*>(dev_workspace);
     const auto* dj = reinterpret_cast<const yoro::DevJob*>(hdr + 1);
     // Persistent grid: as many workgroups as fit on the chip at once.
     DeviceFacts f;
     const int cus = device_facts(&f) ? f.cus : 256;
-    const int grid = cus * yoro::warp_blocks_per_cu(ppt, true);
-    hipError_t e = yoro::launch_warp_batch(hdr, dj, ppt, grid, (hipStream_t)hip_stream);
+    const int grid = cus * yoro::warp_blocks_per_cu(max_width, true);
+    hipError_t e = yoro::launch_warp_batch(hdr, dj, max_width, grid, (hipStream_t)hip_stream);
     if (e != hipSuccess)
       return fail(YORO_ERR_DEVICE, "yoro_stereo_batch_launch: launch failed: %s", hipGetErrorString(e));
     return ok();

@@ -1,245 +1,377 @@
 // Fused per-row warp + resolve + nearest-background fill for gfx950.
 //
 // One workgroup (256 threads, 4 wave64s) owns one image row at a time
-// (Observation O1, Section 5: the shift is horizontal, so rows are
-// independent).  A row goes through five phases, all in LDS:
+// (Observation O1, Section 5: the shift is horizontal and one-signed, so
+// rows are independent).  Rows are software-pipelined: the next row's depth
+// and colour loads are in flight while the current row is processed.
 //
-//   A  coalesced loads: the row's depth into registers, its RGBA into LDS,
-//      and the row's 64-bit target keys set to EMPTY;
-//   B  scatter with the depth test (Section 6, Algorithms 1-2; the lowest
-//      depth is kept): per source pixel d = roundf((B*f)/z) in FP32,
-//      target column x -+ d, and an LDS atomicMin of
-//      (float bits of z) << 32 | source column;
-//   C  per wave64 a ballot of "target reached" -> one 64-bit mask per 64
-//      columns;
-//   D  wave 0 scans the masks: for every 64-column word the last hit at or
-//      before it and the first hit at or after it;
-//   E  resolve (Algorithm 3, non-disocclusion branch: gather the source
-//      colour) and, for holes, the nearest hit on each side from the masks
-//      plus the word scan, keeping the farther one (Section 5 O2), ties to
-//      the side opposite the shift; coalesced stores.
+// Per row, all in LDS:
+//   A  clear the row's 64-bit target keys;
+//   B  scatter with the depth test (Section 6, reprojection equation and
+//      Algorithms 1-2; the lowest depth is kept): per source pixel
+//      d = roundf((B*f)/z) in FP32, target column x -+ d, and an LDS
+//      atomicMin of (float bits of z) << 32 | source RGBA.  Equal depths in
+//      one row have equal disparity and so never meet on one target: the
+//      minimum is decided by the depth alone, and the low word simply
+//      carries the winner's colour (Algorithm 3's gather of the source
+//      colour, done by the scatter itself);
+//   C  every column is stored (a hole provisionally as RGBA 0, depth +inf);
+//      per wave64 a ballot of "target reached" gives one 64-bit hit mask per
+//      64 columns, and the holes are appended to a compact per-row list (one
+//      LDS atomic per wave);
+//   E  each wave scans the hit masks word by word in registers; each listed
+//      hole then finds its nearest hit on either side in O(1) and takes the
+//      farther one (Section 5 O2; Section 7 Patcher figure: on equal depth,
+//      the side opposite the shift), overwriting its provisional value.
+//
+// The code avoids divergent branches where it can: on CDNA the scalar unit
+// issues at the same per-SIMD rate as the vector ALU, so exec-mask juggling
+// costs as much as arithmetic.
 //
 // HBM traffic per target pixel: 4 B depth + 4 B RGBA read, 4 B RGBA written
-// (+4 B depth, +1 B mask when asked for).  Everything else stays in LDS.
+// (+4 B depth, +1 B mask when asked for).
 #include "yoro_internal.h"
 
 namespace yoro {
 namespace {
 
 constexpr uint64_t kEmpty = ~0ull;
-constexpr int kNone = 0x7fffffff;
 
-template <int PPT>
+#define YORO_GLOBAL __attribute__((address_space(1)))
+
+template <class T>
+__device__ __forceinline__ YORO_GLOBAL T* gmem(T* p) {
+  return (YORO_GLOBAL T*)p;
+}
+
+// Per-row LDS of the warp kernel, laid out for rows up to wl columns (wl: a
+// multiple of 64, uniform for the launch).
 struct RowLds {
-  uint64_t* key;   // [wcap]   target keys
-  uint32_t* col;   // [wcap]   source RGBA of the row
-  uint64_t* mask;  // [words]  hit masks, one per 64 columns
-  int32_t* lastc;  // [words]  last hit column in words <= w, or -1
-  int32_t* firstc; // [words]  first hit column in words >= w, or kNone
-  __device__ explicit RowLds(unsigned char* base) {
-    constexpr int wcap = kThreads * PPT;
-    constexpr int words = (wcap + 63) / 64;
+  uint64_t* key;     // [wl + 64] target keys: depth bits << 32 | RGBA; the
+                     //           last 64 are per-lane sinks for lanes with
+                     //           nothing to splat
+  uint64_t* mask;    // [wl/64]   hit masks, one per 64 columns
+  uint32_t* nholes;  // [4]
+  uint16_t* holes;   // [wl]      columns of the row's holes (unordered)
+  __device__ RowLds(unsigned char* base, int wl) {
     key = reinterpret_cast<uint64_t*>(base);
-    mask = key + wcap;
-    col = reinterpret_cast<uint32_t*>(mask + words);
-    lastc = reinterpret_cast<int32_t*>(col + wcap);
-    firstc = lastc + words;
+    mask = key + wl + 64;
+    nholes = reinterpret_cast<uint32_t*>(mask + (wl >> 6));
+    holes = reinterpret_cast<uint16_t*>(nholes + 4);
   }
 };
 
-// Phase D: for every word w < nw, lastc[w] = the largest hit column in words
-// 0..w (or -1) and firstc[w] = the smallest hit column in words w..nw-1 (or
-// kNone).  Run by wave 0 only; each lane takes a contiguous block of words.
-template <int PPT>
-__device__ __forceinline__ void scan_words(const uint64_t* mask, int32_t* lastc, int32_t* firstc, int nw) {
-  constexpr int kWordsMax = (kThreads * PPT + 63) / 64;
-  constexpr int kPer = (kWordsMax + 63) / 64;  // words per lane (1 or 2)
-  const int lane = threadIdx.x;
-  const int w0 = lane * kPer;
-  int fwd[kPer], bwd[kPer];
-  int run = -1;
+// Runs body(i, x) for every column x = threadIdx.x + i*kThreads < W.  Chunks
+// that lie wholly inside the row take a uniform (scalar) branch with no
+// per-lane test; only the one ragged chunk tests x < W per lane.
+template <int PPT, class F>
+__device__ __forceinline__ void for_cols(int W, F&& body) {
+  const int nfull = W / kThreads;
+  const int x0 = threadIdx.x;
 #pragma unroll
-  for (int j = 0; j < kPer; ++j) {
-    const int w = w0 + j;
-    int v = -1;
-    if (w < nw) {
-      const uint64_t m = mask[w];
-      if (m) v = w * 64 + 63 - __clzll((long long)m);
-    }
-    run = max(run, v);
-    fwd[j] = run;
-  }
-  int run_b = kNone;
-#pragma unroll
-  for (int j = kPer - 1; j >= 0; --j) {
-    const int w = w0 + j;
-    int v = kNone;
-    if (w < nw) {
-      const uint64_t m = mask[w];
-      if (m) v = w * 64 + __ffsll((long long)m) - 1;
-    }
-    run_b = min(run_b, v);
-    bwd[j] = run_b;
-  }
-  // Exclusive scans across lanes: max from the left, min from the right.
-  int inc = run;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const int t = __shfl_up(inc, off);
-    if (lane >= off) inc = max(inc, t);
-  }
-  int exc = __shfl_up(inc, 1);
-  if (lane == 0) exc = -1;
-  int incb = run_b;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const int t = __shfl_down(incb, off);
-    if (lane + off < 64) incb = min(incb, t);
-  }
-  int excb = __shfl_down(incb, 1);
-  if (lane == 63) excb = kNone;
-#pragma unroll
-  for (int j = 0; j < kPer; ++j) {
-    const int w = w0 + j;
-    if (w < nw) {
-      lastc[w] = max(fwd[j], exc);
-      firstc[w] = min(bwd[j], excb);
+  for (int i = 0; i < PPT; ++i) {
+    if (i < nfull) {
+      body(i, x0 + i * kThreads);
+    } else if (i == nfull) {
+      if (x0 + i * kThreads < W) body(i, x0 + i * kThreads);
     }
   }
 }
 
-// Nearest hit strictly left (L) and strictly right (R) of column x.
-__device__ __forceinline__ void neighbours(const uint64_t* mask, const int32_t* lastc, const int32_t* firstc,
-                                           int nw, int x, int& L, int& R) {
+// Word-level scan of the hit masks, held in registers by every wave: lane l
+// covers words l and l + 64.  last[k] = the largest hit column in words
+// <= k (or -1); first[k] = the smallest hit column in words >= k (or W).
+struct WordScan {
+  int last0, last1, first0, first1;
+};
+
+__device__ __forceinline__ WordScan scan_words(const uint64_t* mask, int nw, int W) {
+  const int l = threadIdx.x & 63;
+  const uint64_t m0 = l < nw ? mask[l] : 0ull;
+  const uint64_t m1 = l + 64 < nw ? mask[l + 64] : 0ull;
+  WordScan r;
+  r.last0 = m0 ? l * 64 + 63 - __clzll((long long)m0) : -1;
+  r.last1 = m1 ? (l + 64) * 64 + 63 - __clzll((long long)m1) : -1;
+  r.first0 = m0 ? l * 64 + __ffsll((long long)m0) - 1 : W;
+  r.first1 = m1 ? (l + 64) * 64 + __ffsll((long long)m1) - 1 : W;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int a0 = __shfl_up(r.last0, off), a1 = __shfl_up(r.last1, off);
+    const int b0 = __shfl_down(r.first0, off), b1 = __shfl_down(r.first1, off);
+    if (l >= off) {
+      r.last0 = max(r.last0, a0);
+      r.last1 = max(r.last1, a1);
+    }
+    if (l + off < 64) {
+      r.first0 = min(r.first0, b0);
+      r.first1 = min(r.first1, b1);
+    }
+  }
+  // Carry the first 64 words into the second 64 (and back for first).
+  const int carry_last = __shfl(r.last0, 63), carry_first = __shfl(r.first1, 0);
+  r.last1 = max(r.last1, carry_last);
+  r.first0 = min(r.first0, carry_first);
+  return r;
+}
+
+// last[k] / first[k] of the scan for a word index k (uniform or not); every
+// lane of the wave must call it (cross-lane reads).
+__device__ __forceinline__ int scan_last(const WordScan& s, int k) {
+  const int a = __shfl(s.last0, k & 63), b = __shfl(s.last1, k & 63);
+  return k < 0 ? -1 : (k < 64 ? a : b);
+}
+__device__ __forceinline__ int scan_first(const WordScan& s, int k, int nw, int W) {
+  const int a = __shfl(s.first0, k & 63), b = __shfl(s.first1, k & 63);
+  return k >= nw ? W : (k < 64 ? a : b);
+}
+
+// Nearest hit strictly left (L, or -1) and strictly right (R, or W) of
+// column x: inside x's own word from its mask, beyond it from the scan.
+__device__ __forceinline__ void nearest_hits(const uint64_t* mask, const WordScan& sc, int nw, int W, int x, int& L,
+                                             int& R) {
   const int w = x >> 6, b = x & 63;
   const uint64_t m = mask[w];
   const uint64_t lo = m & ((1ull << b) - 1ull);
-  const uint64_t hi = (b == 63) ? 0ull : (m >> (b + 1));
-  L = lo ? (w * 64 + 63 - __clzll((long long)lo)) : (w > 0 ? lastc[w - 1] : -1);
-  R = hi ? (x + __ffsll((long long)hi)) : (w + 1 < nw ? firstc[w + 1] : kNone);
+  const uint64_t hi = (b == 63) ? 0ull : (m >> (b + 1)) << (b + 1);
+  const int Lw = scan_last(sc, w - 1);
+  const int Rw = scan_first(sc, w + 1, nw, W);
+  L = lo ? (w * 64 + 63 - __clzll((long long)lo)) : Lw;
+  R = hi ? (w * 64 + __ffsll((long long)hi) - 1) : Rw;
 }
 
+// Nearest hits by walking the masks word by word (stand-alone fill).
+__device__ __forceinline__ void nearest_hits_walk(const uint64_t* mask, int nw, int W, int x, int& L, int& R) {
+  const int w0 = x >> 6, b = x & 63;
+  int w = w0;
+  uint64_t m = mask[w] & ((1ull << b) - 1ull);
+  while (m == 0 && w > 0) m = mask[--w];
+  L = m ? (w * 64 + 63 - __clzll((long long)m)) : -1;
+  w = w0;
+  m = (b == 63) ? 0ull : (mask[w] >> (b + 1)) << (b + 1);
+  while (m == 0 && w + 1 < nw) m = mask[++w];
+  R = m ? (w * 64 + __ffsll((long long)m) - 1) : W;
+}
+
+// Which of the nearest hits fills a hole: the farther one; on equal depth
+// the one opposite the shift (right when synthesising the right eye).
+// zl, zr: depth bits of the hits (depths in (0, +inf] order like their bits).
+__device__ __forceinline__ int pick_side(int L, int R, int W, uint32_t zl, uint32_t zr, bool target_right) {
+  if (L < 0) return R < W ? R : -1;
+  if (R >= W) return L;
+  return zl > zr ? L : (zr > zl ? R : (target_right ? R : L));
+}
+
+// One row's inputs held in registers: thread t owns columns t + i*kThreads.
 template <int PPT>
-__device__ __forceinline__ void warp_fill_row(const DevJob& J, int y, unsigned char* smem) {
-  RowLds<PPT> s(smem);
+struct RowIn {
+  float z[PPT];
+  uint32_t c[PPT];
+};
+
+template <int PPT>
+__device__ __forceinline__ void load_row(const DevJob& J, int y, RowIn<PPT>& in) {
+  const int W = J.width;
+  const size_t row = (size_t)y * (size_t)W;
+  YORO_GLOBAL const float* zp = gmem(J.src_depth) + row;
+  YORO_GLOBAL const uint32_t* cp = gmem(J.src_rgba) + row;
+#pragma unroll
+  for (int i = 0; i < PPT; ++i) {  // columns past the row's end stay defined
+    in.z[i] = 0.0f;
+    in.c[i] = 0u;
+  }
+  for_cols<PPT>(W, [&](int i, int x) {
+    in.z[i] = __builtin_nontemporal_load(&zp[x]);
+    in.c[i] = __builtin_nontemporal_load(&cp[x]);
+  });
+}
+
+// roundf(q) for 0 <= q < 2^23 without a float-to-int conversion (whose result
+// is undefined for the lanes that do not splat): adding 2^23 rounds q to the
+// nearest integer, ties to even, in the low mantissa bits; a tie that went
+// down (q - r == 0.5 exactly) is then moved up, giving ties away from zero.
+// Any other q gives an unspecified but harmless value.
+__device__ __forceinline__ int round_half_away(float q) {
+  const float y = q + 0x1p23f;
+  const float r = y - 0x1p23f;
+  return (__float_as_int(y) - 0x4B000000) + ((q - r) == 0.5f ? 1 : 0);
+}
+
+// Phases A-E for row y of job J, whose inputs are in registers.
+template <int PPT>
+__device__ __forceinline__ void warp_fill_row(const DevJob& J, int y, const RowIn<PPT>& in, unsigned char* smem,
+                                              int wl) {
+  RowLds s(smem, wl);
   const int W = J.width;
   const int tid = threadIdx.x;
-  const size_t row = (size_t)y * (size_t)W;
+  const int lane = tid & 63;
   const float bf = J.baseline_m * J.focal_px;
-  const int sgn = (J.target_eye == 0) ? -1 : 1;
+  const float Wf = (float)W;
+  const bool target_right = J.target_eye == 0;
+  // x_t = x - d (target right) or x + d (target left), as x + ((d ^ m) - m).
+  const int m = target_right ? -1 : 0;
   const int nw = (W + 63) >> 6;
+  const bool fill = J.fill_mode != 0;
+  const int nfull = W / kThreads;
+  const size_t row = (size_t)y * (size_t)W;
+  YORO_GLOBAL uint32_t* orow = gmem(J.dst_rgba) + row;
+  YORO_GLOBAL float* zrow = J.dst_depth ? gmem(J.dst_depth) + row : nullptr;
+  YORO_GLOBAL uint8_t* mrow = J.dst_mask ? gmem(J.dst_mask) + row : nullptr;
 
-  // A: loads.
-  float z[PPT];
-#pragma unroll
-  for (int i = 0; i < PPT; ++i) {
-    const int x = tid + i * kThreads;
-    if (x < W) {
-      z[i] = __builtin_nontemporal_load(&J.src_depth[row + x]);
-      s.col[x] = __builtin_nontemporal_load(&J.src_rgba[row + x]);
-      s.key[x] = kEmpty;
-    }
-  }
+  // A: clear keys.
+  for_cols<PPT>(W, [&](int, int x) { s.key[x] = kEmpty; });
+  if (tid == 0) *s.nholes = 0u;
   __syncthreads();
 
-  // B: scatter with the depth test.
+  // B: scatter with the depth test.  Lanes with nothing to splat (no
+  // geometry, a shift of a full row or more, a target off the row, a column
+  // past the row's end) hit their own sink slot instead of branching.
 #pragma unroll
   for (int i = 0; i < PPT; ++i) {
-    const int x = tid + i * kThreads;
-    if (x < W) {
-      const float zz = z[i];
-      if (zz > 0.0f) {
-        const float q = bf / zz;
-        if (q < (float)W) {
-          const int d = (int)roundf(q);
-          const int xt = x + sgn * d;
-          if ((unsigned)xt < (unsigned)W)
-            atomicMin(&s.key[xt], ((uint64_t)__float_as_uint(zz) << 32) | (uint32_t)x);
-        }
-      }
-    }
-  }
-  __syncthreads();
-
-  // C: hit masks.
-  if (J.fill_mode != 0) {
-#pragma unroll
-    for (int i = 0; i < PPT; ++i) {
+    if (i <= nfull && i * kThreads < W) {
       const int x = tid + i * kThreads;
-      const bool hit = (x < W) && (s.key[x] != kEmpty);
-      const uint64_t m = __ballot(hit);
-      if ((tid & 63) == 0 && x < W) s.mask[x >> 6] = m;
+      const float z = in.z[i];
+      const float q = bf / z;
+      const int d = round_half_away(q);
+      const int xt = x + ((d ^ m) - m);
+      const bool ok = (z > 0.0f) & (q < Wf) & ((unsigned)xt < (unsigned)W) & (x < W);
+      atomicMin(&s.key[ok ? xt : wl + lane], ((uint64_t)__float_as_uint(z) << 32) | in.c[i]);
     }
-    __syncthreads();
-    // D: word scan.
-    if (tid < 64) scan_words<PPT>(s.mask, s.lastc, s.firstc, nw);
-    __syncthreads();
   }
+  __syncthreads();
 
-  // E: resolve + fill + store.
+  // C: store every column (holes get RGBA 0 / +inf / mask 1 for now), build
+  // the hit masks, count holes.  A hit's high word holds the bits of a depth
+  // in (0, +inf], never the all-ones of EMPTY.
+  uint32_t cnt = 0;
+  uint64_t mword = 0;  // lane i: hit mask of chunk i's 64 columns of this wave
 #pragma unroll
   for (int i = 0; i < PPT; ++i) {
-    const int x = tid + i * kThreads;
-    if (x < W) {
-      uint64_t k = s.key[x];
-      uint8_t mk = 0;
-      if (k == kEmpty) {
-        mk = 1;
-        if (J.fill_mode != 0) {
-          int L, R;
-          neighbours(s.mask, s.lastc, s.firstc, nw, x, L, R);
-          int p;
-          if (L < 0 && R >= W) {
-            p = -1;
-          } else if (L < 0) {
-            p = R;
-          } else if (R >= W) {
-            p = L;
-          } else {
-            const uint32_t zl = (uint32_t)(s.key[L] >> 32), zr = (uint32_t)(s.key[R] >> 32);
-            p = zl > zr ? L : (zr > zl ? R : (sgn < 0 ? R : L));
+    if (i <= nfull && i * kThreads < W) {
+      const int x = tid + i * kThreads;
+      const uint64_t k = s.key[min(x, W - 1)];
+      const bool inrow = x < W;
+      const bool hit = inrow & ((uint32_t)(k >> 32) != 0xFFFFFFFFu);
+      const uint32_t c = hit ? (uint32_t)k : 0u;
+      const float zo = hit ? __uint_as_float((uint32_t)(k >> 32)) : __builtin_inff();
+      if (i < nfull) {
+        orow[x] = c;
+        if (zrow) zrow[x] = zo;
+        if (mrow) mrow[x] = hit ? 0 : 1;
+      } else if (inrow) {
+        orow[x] = c;
+        if (zrow) zrow[x] = zo;
+        if (mrow) mrow[x] = hit ? 0 : 1;
+      }
+      const uint64_t hm = __ballot(hit);
+      const uint64_t valid = (i < nfull) ? ~0ull : __ballot(inrow);
+      cnt += (uint32_t)__popcll(valid & ~hm);
+      // Park this chunk's mask in lane i (lo/hi halves) for one store below.
+      mword = (lane == i) ? hm : mword;
+    }
+  }
+  if (fill) {
+    // One LDS store per lane that parked a mask: word (i*4 + wave) holds
+    // chunk i's columns of this wave.
+    const int wave = tid >> 6;
+    const int nchunks = (W + kThreads - 1) / kThreads;
+    const int word = lane * (kThreads / 64) + wave;
+    if (lane < nchunks && word < nw) s.mask[word] = mword;
+    if (cnt) {
+      uint32_t base = 0;
+      if (lane == 0) base = atomicAdd(s.nholes, cnt);
+      base = __builtin_amdgcn_readfirstlane(base);
+#pragma unroll
+      for (int i = 0; i < PPT; ++i) {
+        if (i <= nfull && i * kThreads < W) {
+          const int x = tid + i * kThreads;
+          // readlane returns a signed int: widen through uint32_t, never sign-extend.
+          const uint64_t hm = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mword, i) |
+                              ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(mword >> 32), i) << 32);
+          const uint64_t valid = (i < nfull) ? ~0ull : __ballot(x < W);
+          const uint64_t om = valid & ~hm;
+          if ((om >> lane) & 1ull) {
+            const uint32_t below =
+                __builtin_amdgcn_mbcnt_hi((uint32_t)(om >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)om, 0u));
+            s.holes[base + below] = (uint16_t)x;
           }
-          if (p >= 0) {
-            k = s.key[p];
-          } else {
-            mk = 2;
-          }
+          base += (uint32_t)__popcll(om);
         }
       }
-      uint32_t c = 0;
-      float zo = __builtin_inff();
-      if (k != kEmpty) {
-        c = s.col[(uint32_t)k];
-        zo = __uint_as_float((uint32_t)(k >> 32));
+    }
+    __syncthreads();
+    // E: fill the listed holes.  Only hits are read, only holes written.
+    const WordScan sc = scan_words(s.mask, nw, W);
+    const int nh = (int)*s.nholes;
+    for (int h0 = tid - lane; h0 < nh; h0 += kThreads) {  // whole waves: the scan reads need every lane
+      const int h = h0 + lane;
+      int x = h < nh ? (int)s.holes[h] : 0;
+      const bool act = (h < nh) & (x < W);  // every listed column is < W; guard the store anyway
+      x = act ? x : 0;
+      int L, R;
+      nearest_hits(s.mask, sc, nw, W, x, L, R);
+      const uint32_t zl = (uint32_t)(s.key[max(L, 0)] >> 32);
+      const uint32_t zr = (uint32_t)(s.key[min(R, W - 1)] >> 32);
+      const int p = pick_side(L, R, W, zl, zr, target_right);
+      const uint64_t k = s.key[max(p, 0)];
+      if (act) {
+        orow[x] = p >= 0 ? (uint32_t)k : 0u;
+        if (zrow) zrow[x] = p >= 0 ? __uint_as_float((uint32_t)(k >> 32)) : __builtin_inff();
+        if (mrow) mrow[x] = p >= 0 ? 1 : 2;
       }
-      __builtin_nontemporal_store(c, &J.dst_rgba[row + x]);
-      if (J.dst_depth) __builtin_nontemporal_store(zo, &J.dst_depth[row + x]);
-      if (J.dst_mask) J.dst_mask[row + x] = mk;
     }
   }
   __syncthreads();  // the next row reuses the LDS
 }
 
 template <int PPT>
-__global__ __launch_bounds__(kThreads) void warp_single_kernel(DevJob J) {
+__global__ __launch_bounds__(kThreads) void warp_single_kernel(DevJob J, int wl) {
   extern __shared__ __align__(16) unsigned char smem[];
-  for (int y = blockIdx.x; y < J.height; y += gridDim.x) warp_fill_row<PPT>(J, y, smem);
+  RowIn<PPT> in;
+  int y = blockIdx.x;
+  if (y < J.height) load_row<PPT>(J, y, in);
+  for (; y < J.height; y += gridDim.x) {
+    const RowIn<PPT> cur = in;
+    const int yn = y + gridDim.x;
+    if (yn < J.height) load_row<PPT>(J, yn, in);
+    warp_fill_row<PPT>(J, y, cur, smem, wl);
+  }
 }
 
 template <int PPT>
-__global__ __launch_bounds__(kThreads) void warp_batch_kernel(BatchHeader* hdr, const DevJob* __restrict__ jobs) {
+__global__ __launch_bounds__(kThreads) void warp_batch_kernel(BatchHeader* hdr, const DevJob* __restrict__ jobs,
+                                                              int wl) {
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t n = hdr->n_jobs, total = hdr->total_rows;
-  uint32_t j = 0;
-  for (uint32_t r = blockIdx.x; r < total; r += gridDim.x) {
-    // Rows only grow, so the job index only moves forward.
+  // Rows only grow, so the job index only moves forward.
+  auto job_of = [&](uint32_t r, uint32_t j) {
     while (j + 1 < n && jobs[j + 1].row_start <= r) ++j;
+    return j;
+  };
+  RowIn<PPT> in;
+  uint32_t r = blockIdx.x;
+  uint32_t j = 0;
+  if (r < total) {
+    j = job_of(r, 0);
     const DevJob J = jobs[j];
-    if (J.width > kThreads * PPT) {
-      if (threadIdx.x == 0) atomicAdd(&hdr->errors, 1u);
-      continue;
+    if (J.width <= wl) load_row<PPT>(J, (int)(r - J.row_start), in);
+  }
+  while (r < total) {
+    const DevJob J = jobs[j];
+    const uint32_t rn = r + gridDim.x;
+    uint32_t jn = j;
+    const RowIn<PPT> cur = in;
+    if (rn < total) {
+      jn = job_of(rn, j);
+      const DevJob Jn = jobs[jn];
+      if (Jn.width <= wl) load_row<PPT>(Jn, (int)(rn - Jn.row_start), in);
     }
-    warp_fill_row<PPT>(J, (int)(r - J.row_start), smem);
+    if (J.width <= wl) {
+      warp_fill_row<PPT>(J, (int)(r - J.row_start), cur, smem, wl);
+    } else if (threadIdx.x == 0) {
+      atomicAdd(&hdr->errors, 1u);  // rows wider than the LDS layout are skipped
+    }
+    r = rn;
+    j = jn;
   }
 }
 
@@ -248,17 +380,13 @@ __global__ __launch_bounds__(kThreads) void warp_batch_kernel(BatchHeader* hdr, 
 // never written; holes read only hits, so in-place is safe.
 template <int PPT>
 __global__ __launch_bounds__(kThreads) void fill_kernel(uint32_t* rgba, float* depth, uint8_t* mask, int W, int H,
-                                                        int target_eye) {
+                                                        int target_eye, int wl) {
   extern __shared__ __align__(16) unsigned char smem[];
-  constexpr int wcap = kThreads * PPT;
-  constexpr int words = (wcap + 63) / 64;
   uint32_t* col = reinterpret_cast<uint32_t*>(smem);
-  float* zs = reinterpret_cast<float*>(col + wcap);
-  uint64_t* hm = reinterpret_cast<uint64_t*>(zs + wcap);
-  int32_t* lastc = reinterpret_cast<int32_t*>(hm + words);
-  int32_t* firstc = lastc + words;
+  uint32_t* zs = col + wl;  // depth bits
+  uint64_t* hm = reinterpret_cast<uint64_t*>(zs + wl);
   const int tid = threadIdx.x;
-  const int sgn = (target_eye == 0) ? -1 : 1;
+  const bool target_right = target_eye == 0;
   const int nw = (W + 63) >> 6;
   for (int y = blockIdx.x; y < H; y += gridDim.x) {
     const size_t row = (size_t)y * (size_t)W;
@@ -270,7 +398,7 @@ __global__ __launch_bounds__(kThreads) void fill_kernel(uint32_t* rgba, float* d
       if (x < W) {
         m8[i] = mask[row + x];
         col[x] = rgba[row + x];
-        zs[x] = depth[row + x];
+        zs[x] = __float_as_uint(depth[row + x]);
       }
     }
 #pragma unroll
@@ -280,35 +408,16 @@ __global__ __launch_bounds__(kThreads) void fill_kernel(uint32_t* rgba, float* d
       if ((tid & 63) == 0 && x < W) hm[x >> 6] = m;
     }
     __syncthreads();
-    if (tid < 64) scan_words<PPT>(hm, lastc, firstc, nw);
-    __syncthreads();
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
       const int x = tid + i * kThreads;
       if (x < W && m8[i] != 0) {
         int L, R;
-        neighbours(hm, lastc, firstc, nw, x, L, R);
-        int p;
-        if (L < 0 && R >= W) {
-          p = -1;
-        } else if (L < 0) {
-          p = R;
-        } else if (R >= W) {
-          p = L;
-        } else {
-          const uint32_t zl = __float_as_uint(zs[L]), zr = __float_as_uint(zs[R]);
-          // Hits carry depth > 0 or +inf, so the bit patterns order like the values.
-          p = zl > zr ? L : (zr > zl ? R : (sgn < 0 ? R : L));
-        }
-        if (p >= 0) {
-          rgba[row + x] = col[p];
-          depth[row + x] = zs[p];
-          mask[row + x] = 1;
-        } else {
-          rgba[row + x] = 0u;
-          depth[row + x] = __builtin_inff();
-          mask[row + x] = 2;
-        }
+        nearest_hits_walk(hm, nw, W, x, L, R);
+        const int p = pick_side(L, R, W, L >= 0 ? zs[L] : 0u, R < W ? zs[R] : 0u, target_right);
+        rgba[row + x] = p >= 0 ? col[p] : 0u;
+        depth[row + x] = p >= 0 ? __uint_as_float(zs[p]) : __builtin_inff();
+        mask[row + x] = p >= 0 ? 1 : 2;
       }
     }
     __syncthreads();
@@ -359,7 +468,6 @@ __global__ void header_kernel(BatchHeader h, BatchHeader* dst) {
 }
 
 // ---------------------------------------------------------------------------
-template <int PPT>
 hipError_t set_lds_limit(const void* fn, size_t bytes) {
   if (bytes > 65536) return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   return hipSuccess;
@@ -370,14 +478,15 @@ hipError_t set_lds_limit(const void* fn, size_t bytes) {
 }  // namespace
 
 hipError_t launch_warp_single(const DevJob& job, int ppt, int grid, hipStream_t stream) {
-  const size_t lds = warp_lds_bytes(ppt);
+  const int wl = lds_width(job.width);
+  const size_t lds = warp_lds_bytes(wl);
   switch (ppt) {
-#define X(P)                                                                                   \
-  case P: {                                                                                    \
-    hipError_t e = set_lds_limit<P>((const void*)warp_single_kernel<P>, lds);                  \
-    if (e != hipSuccess) return e;                                                             \
-    hipLaunchKernelGGL(warp_single_kernel<P>, dim3(grid), dim3(kThreads), lds, stream, job);   \
-    return hipGetLastError();                                                                  \
+#define X(P)                                                                                     \
+  case P: {                                                                                      \
+    hipError_t e = set_lds_limit((const void*)warp_single_kernel<P>, lds);                       \
+    if (e != hipSuccess) return e;                                                               \
+    hipLaunchKernelGGL(warp_single_kernel<P>, dim3(grid), dim3(kThreads), lds, stream, job, wl); \
+    return hipGetLastError();                                                                    \
   }
     YORO_PPT_CASES(X)
 #undef X
@@ -386,16 +495,19 @@ hipError_t launch_warp_single(const DevJob& job, int ppt, int grid, hipStream_t 
   }
 }
 
-hipError_t launch_warp_batch(const BatchHeader* hdr, const DevJob* jobs, int ppt, int grid, hipStream_t stream) {
-  const size_t lds = warp_lds_bytes(ppt);
+hipError_t launch_warp_batch(const BatchHeader* hdr, const DevJob* jobs, int max_width, int grid,
+                             hipStream_t stream) {
+  const int ppt = ppt_for(max_width);
+  const int wl = lds_width(max_width);
+  const size_t lds = warp_lds_bytes(wl);
   BatchHeader* h = const_cast<BatchHeader*>(hdr);
   switch (ppt) {
-#define X(P)                                                                                      \
-  case P: {                                                                                       \
-    hipError_t e = set_lds_limit<P>((const void*)warp_batch_kernel<P>, lds);                      \
-    if (e != hipSuccess) return e;                                                                \
-    hipLaunchKernelGGL(warp_batch_kernel<P>, dim3(grid), dim3(kThreads), lds, stream, h, jobs);   \
-    return hipGetLastError();                                                                     \
+#define X(P)                                                                                        \
+  case P: {                                                                                         \
+    hipError_t e = set_lds_limit((const void*)warp_batch_kernel<P>, lds);                           \
+    if (e != hipSuccess) return e;                                                                  \
+    hipLaunchKernelGGL(warp_batch_kernel<P>, dim3(grid), dim3(kThreads), lds, stream, h, jobs, wl); \
+    return hipGetLastError();                                                                       \
   }
     YORO_PPT_CASES(X)
 #undef X
@@ -407,15 +519,16 @@ hipError_t launch_warp_batch(const BatchHeader* hdr, const DevJob* jobs, int ppt
 hipError_t launch_fill(uint32_t* rgba, float* depth, uint8_t* mask, int32_t width, int32_t height, int32_t target_eye,
                        int32_t fill_mode, int ppt, int grid, hipStream_t stream) {
   (void)fill_mode;
-  const size_t lds = fill_lds_bytes(ppt);
+  const int wl = lds_width(width);
+  const size_t lds = fill_lds_bytes(wl);
   switch (ppt) {
-#define X(P)                                                                                            \
-  case P: {                                                                                             \
-    hipError_t e = set_lds_limit<P>((const void*)fill_kernel<P>, lds);                                  \
-    if (e != hipSuccess) return e;                                                                      \
+#define X(P)                                                                                              \
+  case P: {                                                                                               \
+    hipError_t e = set_lds_limit((const void*)fill_kernel<P>, lds);                                       \
+    if (e != hipSuccess) return e;                                                                        \
     hipLaunchKernelGGL(fill_kernel<P>, dim3(grid), dim3(kThreads), lds, stream, rgba, depth, mask, width, \
-                       height, target_eye);                                                             \
-    return hipGetLastError();                                                                           \
+                       height, target_eye, wl);                                                           \
+    return hipGetLastError();                                                                             \
   }
     YORO_PPT_CASES(X)
 #undef X
@@ -443,16 +556,17 @@ hipError_t launch_header(BatchHeader hdr, BatchHeader* dst, hipStream_t stream) 
   return hipGetLastError();
 }
 
-int warp_blocks_per_cu(int ppt, bool batch) {
+int warp_blocks_per_cu(int max_width, bool batch) {
   int nb = 0;
-  const size_t lds = warp_lds_bytes(ppt);
+  const int ppt = ppt_for(max_width);
+  const size_t lds = warp_lds_bytes(lds_width(max_width));
   hipError_t e = hipErrorInvalidValue;
   switch (ppt) {
-#define X(P)                                                                                                       \
-  case P:                                                                                                          \
-    (void)set_lds_limit<P>(batch ? (const void*)warp_batch_kernel<P> : (const void*)warp_single_kernel<P>, lds);          \
-    e = batch ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, warp_batch_kernel<P>, kThreads, lds)             \
-              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, warp_single_kernel<P>, kThreads, lds);           \
+#define X(P)                                                                                                      \
+  case P:                                                                                                         \
+    (void)set_lds_limit(batch ? (const void*)warp_batch_kernel<P> : (const void*)warp_single_kernel<P>, lds);      \
+    e = batch ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, warp_batch_kernel<P>, kThreads, lds)            \
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, warp_single_kernel<P>, kThreads, lds);          \
     break;
     YORO_PPT_CASES(X)
 #undef X
@@ -462,14 +576,15 @@ int warp_blocks_per_cu(int ppt, bool batch) {
   return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
-int fill_blocks_per_cu(int ppt) {
+int fill_blocks_per_cu(int width) {
   int nb = 0;
-  const size_t lds = fill_lds_bytes(ppt);
+  const int ppt = ppt_for(width);
+  const size_t lds = fill_lds_bytes(lds_width(width));
   hipError_t e = hipErrorInvalidValue;
   switch (ppt) {
 #define X(P)                                                                              \
   case P:                                                                                 \
-    (void)set_lds_limit<P>((const void*)fill_kernel<P>, lds);                                   \
+    (void)set_lds_limit((const void*)fill_kernel<P>, lds);                                \
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fill_kernel<P>, kThreads, lds); \
     break;
     YORO_PPT_CASES(X)

@@ -46,21 +46,32 @@ struct UploadChunk {
 constexpr int kThreads = 256;      // threads per workgroup (4 waves of 64)
 constexpr int kMaxPPT = 32;        // pixels per thread: width <= kThreads * kMaxPPT = 8192
 
-// Dynamic LDS bytes for a row kernel whose rows are at most kThreads*ppt wide.
-inline size_t warp_lds_bytes(int ppt) {
-  const size_t wcap = (size_t)kThreads * ppt;
-  const size_t words = (wcap + 63) / 64;
-  return wcap * 8 + wcap * 4 + words * 8 + words * 4 * 2;
+// Pixels per thread for rows up to max_width columns: the smallest
+// instantiated value with kThreads * ppt >= max_width (-1 if too wide).
+inline int ppt_for(int max_width) {
+  static const int kPPT[] = {1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 16, 20, 24, 28, 32};
+  const int need = (max_width + kThreads - 1) / kThreads;
+  for (int p : kPPT)
+    if (p >= need) return p;
+  return -1;
 }
-inline size_t fill_lds_bytes(int ppt) {
-  const size_t wcap = (size_t)kThreads * ppt;
-  const size_t words = (wcap + 63) / 64;
-  return wcap * 4 + wcap * 4 + words * 8 + words * 4 * 2;
+// Width the row kernel's LDS is laid out for: max_width rounded up to 64.
+inline int lds_width(int max_width) { return (max_width + 63) & ~63; }
+// Dynamic LDS bytes of the warp kernel laid out for wl columns: 64-bit keys
+// (plus 64 sinks), hit masks, the hole counter and the u16 hole list.
+inline size_t warp_lds_bytes(int wl) {
+  const size_t w = (size_t)wl;
+  return (w + 64) * 8 + (w / 64) * 8 + 16 + w * 2;
+}
+// Dynamic LDS bytes of the stand-alone fill kernel: colours, depths, masks.
+inline size_t fill_lds_bytes(int wl) {
+  const size_t w = (size_t)wl;
+  return w * 4 + w * 4 + (w / 64) * 8;
 }
 
 // Launchers (defined in warp_fill.hip).  They return hipSuccess or the launch error.
 hipError_t launch_warp_single(const DevJob& job, int ppt, int grid, hipStream_t stream);
-hipError_t launch_warp_batch(const BatchHeader* hdr, const DevJob* jobs, int ppt, int grid,
+hipError_t launch_warp_batch(const BatchHeader* hdr, const DevJob* jobs, int max_width, int grid,
                              hipStream_t stream);
 hipError_t launch_upload(const UploadChunk& chunk, DevJob* dst, hipStream_t stream);
 hipError_t launch_header(BatchHeader hdr, BatchHeader* dst, hipStream_t stream);
@@ -68,8 +79,8 @@ hipError_t launch_fill(uint32_t* rgba, float* depth, uint8_t* mask, int32_t widt
                        int32_t target_eye, int32_t fill_mode, int ppt, int grid, hipStream_t stream);
 hipError_t launch_hole_sse(const uint32_t* rgba, const uint32_t* ref, const uint8_t* mask, int64_t n,
                            unsigned long long* out, int grid, hipStream_t stream);
-// Occupancy-derived workgroups per CU for the row kernels at a given ppt.
-int warp_blocks_per_cu(int ppt, bool batch);
-int fill_blocks_per_cu(int ppt);
+// Occupancy-derived workgroups per CU for the row kernels.
+int warp_blocks_per_cu(int max_width, bool batch);
+int fill_blocks_per_cu(int width);
 
 }  // namespace yoro

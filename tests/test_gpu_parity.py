@@ -72,6 +72,33 @@ def test_random_frames_all_widths(cuda, W):
             assert_same(g, o, f"W={W} case={k} eye={eye}")
 
 
+def test_disparity_at_and_near_half_integers(cuda):
+    """Depths whose quotient B*f/z sits exactly on, or a few ulps either side
+    of, k + 0.5 (the rounding boundary) and of the row width."""
+    B, f, W = 0.063, 900.0, 1832
+    bf = np.float32(np.float32(B) * np.float32(f))
+    zs = []
+    for k in list(range(0, 300)) + [W - 1, W]:
+        z0 = np.float32(bf / np.float32(k + 0.5))
+        z = z0
+        for _ in range(6):
+            z = np.nextafter(z, np.float32(0))
+        for _ in range(13):
+            zs.append(z)
+            z = np.nextafter(z, np.float32(np.inf))
+    zs = np.array(zs, dtype=np.float32)
+    H = (len(zs) + W - 1) // W
+    depth = np.full(H * W, 3.0, dtype=np.float32)
+    rng = np.random.default_rng(0)
+    depth[:len(zs)] = zs[rng.permutation(len(zs))]
+    depth = depth.reshape(H, W)
+    rgba, _ = synth.random_frame(77, W, H)
+    for eye in (R, L):
+        g = run_gpu(rgba, depth, B, f, eye, orc.FILL_NEAREST_BG)
+        o = orc.reproject(rgba, depth, B, f, eye, orc.FILL_NEAREST_BG)
+        assert_same(g, o, f"eye={eye}")
+
+
 def test_optional_outputs_absent(cuda):
     rgba, depth = synth.random_frame(5, 300, 7, depth_levels=4, zmin=0.3, zmax=3.0)
     g = run_gpu(rgba, depth, 0.064, 200.0, R, orc.FILL_NEAREST_BG, with_depth=False, with_mask=False)
