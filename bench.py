@@ -162,6 +162,14 @@ def main():
         parity = all(np.array_equal(o, g.cpu().numpy()) for o, g in zip(outs, dst))
         log(f"cpu oracle: {cpu}; GPU output bit-exact vs oracle: {parity}")
 
+    # HBM bytes per launch from the committed rocprofv3 counter summary, valid
+    # only for the kernel source those counters were taken on.
+    from paper_2506_15183_amd import profiling
+
+    traffic, sha = profiling.read_summary(os.path.join(ROOT, "profiles", "warp_batch_kernel_64frames.md"))
+    if traffic is None or sha != profiling.kernel_source_sha():
+        traffic = None
+
     value = pixels * args.steps / wall / 1e6
     result = {
         "metric": "stereo Mpix/s + %HBM peak vs plain fill; p99 frame latency; hole PSNR vs ray-cast",
@@ -190,7 +198,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": traffic,
             "kernel": "warp_batch_kernel<9>",
             "launch_ms_avg": round(float(per_launch_ms.mean()), 4),
         },

@@ -1,0 +1,174 @@
+"""Profiling helpers: counter runs and rocprofv3 summaries.
+
+Workflow (each step its own process; the GPU steps under rocprofv3):
+
+  1. rocprofv3 --kernel-trace --stats -d OUT/trace -o t -- python bench.py --steps 20 --warmup 5 --no-cpu-baseline
+  2. rocprofv3 --pmc FETCH_SIZE -d OUT/fetch -o f -- python -m paper_2506_15183_amd.profiling counters
+  3. rocprofv3 --pmc WRITE_SIZE -d OUT/write -o w -- python -m paper_2506_15183_amd.profiling counters
+  4. python -m paper_2506_15183_amd.profiling summarize OUT > profiles/<kernel>_<workload>.md
+
+The ``counters`` workload launches the batched warp kernel a few times on the
+64-frame batch and, for calibration, a plain elementwise kernel that reads
+and writes a known number of bytes: each counter is scaled by (bytes the copy moves) /
+(what the counter reports for the copy), so ``traffic`` is in real bytes.
+"""
+from __future__ import annotations
+
+import glob
+import hashlib
+import os
+import re
+import sqlite3
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCE = os.path.join(HERE, "csrc", "warp_fill.hip")
+WARP_KERNEL = "warp_batch_kernel"
+COPY_BYTES = 1 << 30
+
+
+def kernel_source_sha() -> str:
+    """Short hash of the kernel source the counters were taken on."""
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def counters_workload(launches: int = 5) -> None:
+    import torch
+
+    from . import yoro
+    from .scenes import config3_frames
+
+    dev = torch.device("cuda:0")
+    specs = config3_frames()
+    frames = [s.render_source() for s in specs]
+    src = [(torch.from_numpy(r).to(dev), torch.from_numpy(d).to(dev)) for r, d in frames]
+    dst = [torch.empty((s.height, s.width, 4), dtype=torch.uint8, device=dev) for s in specs]
+    jobs = [yoro.make_job(a, b, o, None, None, s.baseline_m, s.focal_px, s.target_eye, yoro.FILL_NEAREST_BG)
+            for s, (a, b), o in zip(specs, src, dst)]
+    batch = yoro.StereoBatch(jobs, device=dev)
+    batch.prepare()
+    for _ in range(launches):
+        batch.launch()
+    # The calibration kernel: an elementwise pass that reads and writes
+    # COPY_BYTES each (torch's bitwise_not on int32).
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.int32, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(launches):
+        torch.bitwise_not(a, out=b)
+    torch.cuda.synchronize()
+    print(f"counters workload done: {launches} warp launches, {launches} copies of {COPY_BYTES} B", flush=True)
+
+
+def _db(path_dir: str) -> sqlite3.Connection:
+    files = glob.glob(os.path.join(path_dir, "**", "*_results.db"), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no rocpd database under {path_dir}")
+    return sqlite3.connect(files[0])
+
+
+def _counter_means(path_dir: str, counter: str):
+    """(mean counter value per dispatch of the warp kernel, of the copy kernel)."""
+    c = _db(path_dir)
+    warp, copy = [], []
+    for name, cname, val in c.execute("select kernel_name, counter_name, value from counters_collection"):
+        if cname != counter:
+            continue
+        if WARP_KERNEL in name:
+            warp.append(val)
+        elif "bitwise_not" in name.lower() or "bitwisenot" in name.lower():
+            copy.append(val)
+    if not warp or not copy:
+        raise RuntimeError(f"{counter}: found {len(warp)} warp and {len(copy)} copy dispatches")
+    return sum(warp) / len(warp), sum(copy) / len(copy)
+
+
+def _trace_stats(path_dir: str):
+    """[(kernel name, calls, median ns, mean ns, min ns)] from the per-dispatch trace, longest first."""
+    c = _db(path_dir)
+    per = {}
+    for name, dur in c.execute("select name, duration from kernels"):
+        per.setdefault(name, []).append(float(dur))
+    rows = []
+    for name, d in per.items():
+        d = sorted(d)
+        rows.append((name, len(d), d[len(d) // 2], sum(d) / len(d), d[0]))
+    rows.sort(key=lambda r: -r[1] * r[3])
+    return rows
+
+
+def summarize(out_dir: str, pixels: int, algo_bytes_per_px: int = 12) -> str:
+    trace = _trace_stats(os.path.join(out_dir, "trace"))
+    fw, fc = _counter_means(os.path.join(out_dir, "fetch"), "FETCH_SIZE")
+    ww, wc = _counter_means(os.path.join(out_dir, "write"), "WRITE_SIZE")
+    fetch_scale = COPY_BYTES / (fc * 1024.0)
+    write_scale = COPY_BYTES / (wc * 1024.0)
+    fetch_bytes = fw * 1024.0 * fetch_scale
+    write_bytes = ww * 1024.0 * write_scale
+    traffic = fetch_bytes + write_bytes
+    algo = algo_bytes_per_px * pixels
+    warp_rows = [r for r in trace if WARP_KERNEL in r[0]]
+    lines = [
+        "# warp_batch_kernel on the 64-frame mixed-resolution batch",
+        "",
+        "Commands (from the repository root, on one MI355X; OUT=gpurun_out/prof):",
+        "",
+        "```",
+        "rocprofv3 --kernel-trace --stats -d $OUT/trace -o t -- python bench.py --steps 20 --warmup 5 --no-cpu-baseline",
+        "rocprofv3 --pmc FETCH_SIZE -d $OUT/fetch -o f -- python -m paper_2506_15183_amd.profiling counters",
+        "rocprofv3 --pmc WRITE_SIZE -d $OUT/write -o w -- python -m paper_2506_15183_amd.profiling counters",
+        "python -m paper_2506_15183_amd.profiling summarize $OUT",
+        "```",
+        "",
+        "## Kernel trace (top kernels)",
+        "",
+        "| kernel | calls | median ns | mean ns | min ns |",
+        "|---|---|---|---|---|",
+    ]
+    for name, calls, med, mean, mn in trace[:8]:
+        short = name if len(name) < 90 else name[:87] + "..."
+        lines.append(f"| `{short}` | {calls} | {med:.0f} | {mean:.0f} | {mn:.0f} |")
+    lines += [
+        "",
+        "## HBM traffic per launch (FETCH_SIZE, WRITE_SIZE)",
+        "",
+        f"Calibration: an elementwise pass reading and writing {COPY_BYTES} B reports FETCH_SIZE = {fc:.0f} KiB and WRITE_SIZE = "
+        f"{wc:.0f} KiB per dispatch, so the scale factors are fetch x{fetch_scale:.4f}, write x{write_scale:.4f}.",
+        "",
+        f"- warp kernel FETCH_SIZE {fw:.0f} KiB -> {fetch_bytes / 1e9:.4f} GB read",
+        f"- warp kernel WRITE_SIZE {ww:.0f} KiB -> {write_bytes / 1e9:.4f} GB written",
+        f"- algorithmic bytes per launch: {algo_bytes_per_px} B x {pixels} px = {algo / 1e9:.4f} GB",
+        f"- measured / algorithmic: {traffic / algo:.4f}",
+        "",
+        "Machine-readable (read by bench.py):",
+        "",
+        f"traffic_bytes_per_launch: {traffic:.0f}",
+        f"kernel_median_ns: {warp_rows[0][2]:.0f}" if warp_rows else "kernel_median_ns: nan",
+        f"kernel_source_sha: {kernel_source_sha()}",
+        "",
+    ]
+    return "\n".join(lines)
+
+
+def read_summary(path: str):
+    """(traffic bytes per launch, kernel source sha) from a committed summary, or (None, None)."""
+    if not os.path.exists(path):
+        return None, None
+    text = open(path).read()
+    t = re.search(r"^traffic_bytes_per_launch: (\d+)", text, re.M)
+    h = re.search(r"^kernel_source_sha: (\w+)", text, re.M)
+    return (int(t.group(1)) if t else None), (h.group(1) if h else None)
+
+
+if __name__ == "__main__":
+    if len(sys.argv) >= 2 and sys.argv[1] == "counters":
+        counters_workload()
+    elif len(sys.argv) >= 3 and sys.argv[1] == "summarize":
+        sys.path.insert(0, os.path.dirname(HERE))
+        from paper_2506_15183_amd.scenes import config3_frames
+
+        px = sum(s.pixels for s in config3_frames())
+        print(summarize(sys.argv[2], px))
+    else:
+        print(__doc__)
+        sys.exit(2)
