@@ -123,6 +123,10 @@ int grid_for(int rows, int blocks_per_cu) {
 
 }  // namespace
 
+namespace yoro {
+void set_last_error(const char* msg) { g_err = msg; }
+}  // namespace yoro
+
 extern "C" {
 
 int32_t yoro_version(void) { return YORO_VERSION; }

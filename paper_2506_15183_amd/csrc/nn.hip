@@ -1,0 +1,546 @@
+// Kernels of the learned hole filler (a 4-level convolutional
+// encoder-decoder, BF16 storage, FP32 accumulation on the MFMA units).
+//
+// Tensors are NHWC: a pixel's channels are contiguous; "ld" is the element
+// stride between consecutive pixels (>= the channel count, so a convolution
+// can read or write a channel slice of a wider concatenation buffer).
+// Activations and weight copies are bfloat16 (raw 16-bit words here), master
+// weights, their gradients and the network's residual output are FP32.
+//
+// conv3x3: implicit GEMM.  M = pixels, N = output channels, K = 9 taps x
+// input channels, on v_mfma_f32_16x16x32_bf16 (A: 16 pixels x 32 channels,
+// B: 32 channels x 16 outputs, D: 16 x 16 FP32).  Lane l of a wave holds A
+// row (l % 16) with k = 8*(l/16) .. +7, B column (l % 16) with the same k,
+// and D column (l % 16) with rows 4*(l/16) .. +3.  The same kernel computes
+// the input gradient with the weights flipped and transposed.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "yoro_internal.h"
+
+namespace yoro {
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
+typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4;
+
+// float -> bfloat16 bits, round to nearest, ties to even (no NaN inputs here).
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
+
+constexpr int kConvThreads = 256;  // 4 waves; a workgroup covers 64 pixels
+
+// ---------------------------------------------------------------- conv3x3 --
+// Output tile: 64 pixels x CT channels; wave w takes pixels 16w..16w+15.
+// epi: 0 none, 1 ReLU, 2 multiply by (msrc > 0) (the ReLU derivative of the
+// forward activation at the same position).
+template <int CT>
+__global__ __launch_bounds__(kConvThreads) void conv3x3_kernel(const uint16_t* __restrict__ x, int ldx, int N, int H,
+                                                               int W, int Cin, const uint16_t* __restrict__ wgt,
+                                                               int Cout, void* __restrict__ y, int ldy, int y_fp32,
+                                                               int cout_store, int epi,
+                                                               const uint16_t* __restrict__ msrc, int ldm) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const long long P = (long long)N * H * W;
+  const long long p0 = (long long)blockIdx.x * 64 + wave * 16;
+  const int co0 = blockIdx.y * CT;
+  // This lane's A row: pixel p0 + lane%16; its k group: channels 8*(lane/16).
+  const long long pa = p0 + (lane & 15);
+  const int kg = (lane >> 4) * 8;
+  int ay = 0, ax = 0, an = 0;
+  const bool arow = pa < P;
+  if (arow) {
+    an = (int)(pa / ((long long)H * W));
+    const int rem = (int)(pa - (long long)an * H * W);
+    ay = rem / W;
+    ax = rem - ay * W;
+  }
+  floatx4 acc[CT / 16];
+#pragma unroll
+  for (int b = 0; b < CT / 16; ++b) acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  for (int t = 0; t < 9; ++t) {
+    const int yy = ay + t / 3 - 1, xx = ax + t % 3 - 1;
+    const bool in = arow && yy >= 0 && yy < H && xx >= 0 && xx < W;
+    const uint16_t* xrow = x + ((long long)an * H * W + (long long)(in ? yy : 0) * W + (in ? xx : 0)) * ldx + kg;
+    const uint16_t* wt = wgt + ((long long)t * Cout + co0 + (lane & 15)) * Cin + kg;
+    for (int ci = 0; ci < Cin; ci += 32) {
+      u32x4 av = {0u, 0u, 0u, 0u};
+      if (in) av = *reinterpret_cast<const u32x4*>(xrow + ci);
+#pragma unroll
+      for (int b = 0; b < CT / 16; ++b) {
+        const u32x4 bv = *reinterpret_cast<const u32x4*>(wt + (long long)b * 16 * Cin + ci);
+        acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(av), as_bf16x8(bv), acc[b], 0, 0, 0);
+      }
+    }
+  }
+  // Epilogue: lane holds column co0 + 16b + lane%16, rows 4*(lane/16) + r.
+#pragma unroll
+  for (int b = 0; b < CT / 16; ++b) {
+    const int co = co0 + b * 16 + (lane & 15);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const long long p = p0 + (lane >> 4) * 4 + r;
+      if (p >= P || co >= cout_store) continue;
+      float v = acc[b][r];
+      if (epi == 1) v = fmaxf(v, 0.0f);
+      if (epi == 2) v = (from_bf16(msrc[p * ldm + co]) > 0.0f) ? v : 0.0f;
+      if (y_fp32)
+        reinterpret_cast<float*>(y)[p * ldy + co] = v;
+      else
+        reinterpret_cast<uint16_t*>(y)[p * ldy + co] = to_bf16(v);
+    }
+  }
+}
+
+// ---------------------------------------------------------- weight grad --
+// dW[t][co][ci] = sum_p dy[p][co] * x[p + off(t)][ci].  GEMM with M = co,
+// N = ci, K = pixels.  A workgroup owns one tap, a TCO x TCI block and one
+// chunk of pixels; dy and x tiles of 32 pixels are staged in LDS transposed
+// (channel-major) so each lane reads its 8 consecutive pixels in one load.
+// Partial sums go to ws[chunk][t][co][ci]; a second kernel adds the chunks in
+// order, so the result does not depend on scheduling.
+constexpr int kWgPix = 32;
+constexpr int kWgPad = 8;  // LDS row pad (bf16 elements)
+
+template <int TCO, int TCI>
+__global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(const uint16_t* __restrict__ x, int ldx,
+                                                            const uint16_t* __restrict__ dy, int lddy, int N, int H,
+                                                            int W, int Cin, int Cout, int chunk_pix,
+                                                            float* __restrict__ ws) {
+  __shared__ __align__(16) uint16_t sa[TCO][kWgPix + kWgPad];
+  __shared__ __align__(16) uint16_t sb[TCI][kWgPix + kWgPad];
+  const int nco = Cout / TCO, nci = Cin / TCI;
+  int bid = blockIdx.x;
+  const int t = bid / (nco * nci);
+  bid -= t * nco * nci;
+  const int co0 = (bid / nci) * TCO, ci0 = (bid % nci) * TCI;
+  const int chunk = blockIdx.y;
+  const long long P = (long long)N * H * W;
+  const long long pbeg = (long long)chunk * chunk_pix;
+  const long long pend = pbeg + chunk_pix < P ? pbeg + chunk_pix : P;
+  const int dyo = t / 3 - 1, dxo = t % 3 - 1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  constexpr int WM = TCO / 32, WN = TCI / 32;  // waves used: WM x WN (each 32 x 32)
+  const int wm = wave / WN, wn = wave % WN;
+  const bool active = wave < WM * WN;
+  floatx4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  for (long long pk = pbeg; pk < pend; pk += kWgPix) {
+    // Stage dy[32 px][TCO] -> sa[co][px] and x(shifted)[32 px][TCI] -> sb[ci][px].
+    for (int e = threadIdx.x; e < kWgPix * (TCO / 8); e += 256) {
+      const int px = e / (TCO / 8), c8 = (e % (TCO / 8)) * 8;
+      const long long p = pk + px;
+      u32x4 v = {0u, 0u, 0u, 0u};
+      if (p < pend) v = *reinterpret_cast<const u32x4*>(dy + p * lddy + co0 + c8);
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        sa[c8 + 2 * j][px] = (uint16_t)(v[j] & 0xFFFFu);
+        sa[c8 + 2 * j + 1][px] = (uint16_t)(v[j] >> 16);
+      }
+    }
+    for (int e = threadIdx.x; e < kWgPix * (TCI / 8); e += 256) {
+      const int px = e / (TCI / 8), c8 = (e % (TCI / 8)) * 8;
+      const long long p = pk + px;
+      u32x4 v = {0u, 0u, 0u, 0u};
+      if (p < pend) {
+        const int n = (int)(p / ((long long)H * W));
+        const int rem = (int)(p - (long long)n * H * W);
+        const int yy = rem / W + dyo, xx = rem % W + dxo;
+        if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+          v = *reinterpret_cast<const u32x4*>(x + ((long long)n * H * W + (long long)yy * W + xx) * ldx + ci0 + c8);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        sb[c8 + 2 * j][px] = (uint16_t)(v[j] & 0xFFFFu);
+        sb[c8 + 2 * j + 1][px] = (uint16_t)(v[j] >> 16);
+      }
+    }
+    __syncthreads();
+    if (active) {
+      const int kg = (lane >> 4) * 8;
+      u32x4 a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const u32x4*>(&sa[wm * 32 + i * 16 + (lane & 15)][kg]);
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const u32x4*>(&sb[wn * 32 + j * 16 + (lane & 15)][kg]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a[i]), as_bf16x8(b[j]), acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  if (!active) return;
+  float* out = ws + ((long long)chunk * 9 + t) * Cout * Cin;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int co = co0 + wm * 32 + i * 16 + (lane >> 4) * 4 + r;
+        const int ci = ci0 + wn * 32 + j * 16 + (lane & 15);
+        out[(long long)co * Cin + ci] = acc[i][j][r];
+      }
+}
+
+__global__ void sum_chunks_kernel(const float* __restrict__ ws, int nchunks, long long n, float* __restrict__ out) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    float s = 0.0f;
+    for (int c = 0; c < nchunks; ++c) s += ws[(long long)c * n + i];  // fixed order: deterministic
+    out[i] = s;
+  }
+}
+
+// --------------------------------------------------------------- weights --
+// Master [9][cout][cin] FP32 -> bf16 forward copy (same layout) and backward
+// copy [9][cin][cout] with the taps flipped (tap 8 - t), which turns the input
+// gradient into a plain 3x3 convolution of the output gradient.
+__global__ void pack_weights_kernel(const float* __restrict__ w, int cin, int cout, uint16_t* __restrict__ wf,
+                                    uint16_t* __restrict__ wb) {
+  const long long n = 9LL * cin * cout;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const int t = (int)(i / ((long long)cin * cout));
+    const int rem = (int)(i - (long long)t * cin * cout);
+    const int co = rem / cin, ci = rem % cin;
+    const uint16_t h = to_bf16(w[i]);
+    wf[i] = h;
+    wb[((long long)(8 - t) * cin + ci) * cout + co] = h;
+  }
+}
+
+// ------------------------------------------------------- pool / upsample --
+// h, w: the full-resolution size (pool input / upsample output).
+__global__ void avgpool2_kernel(const uint16_t* __restrict__ x, int ldx, int N, int h, int w, int c,
+                                uint16_t* __restrict__ y, int ldy) {
+  const int ho = h / 2, wo = w / 2;
+  const long long n = (long long)N * ho * wo * c;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const int ch = (int)(i % c);
+    long long q = i / c;
+    const int j = (int)(q % wo);
+    q /= wo;
+    const int ii = (int)(q % ho);
+    const int nn = (int)(q / ho);
+    const long long b = ((long long)nn * h + 2 * ii) * w + 2 * j;
+    const float s = (from_bf16(x[b * ldx + ch]) + from_bf16(x[(b + 1) * ldx + ch])) +
+                    (from_bf16(x[(b + w) * ldx + ch]) + from_bf16(x[(b + w + 1) * ldx + ch]));
+    y[(((long long)nn * ho + ii) * wo + j) * ldy + ch] = to_bf16(s * 0.25f);
+  }
+}
+
+// dx = (pool-gradient of g + addend) * (msrc > 0), at full resolution h x w.
+__global__ void avgpool2_grad_kernel(const uint16_t* __restrict__ g, int ldg, const uint16_t* __restrict__ add, int lda,
+                                     const uint16_t* __restrict__ msrc, int ldm, int N, int h, int w, int c,
+                                     uint16_t* __restrict__ dx, int lddx) {
+  const long long n = (long long)N * h * w * c;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const int ch = (int)(i % c);
+    const long long p = i / c;
+    const int xx = (int)(p % w);
+    const long long q = p / w;
+    const int yy = (int)(q % h);
+    const int nn = (int)(q / h);
+    const long long pg = ((long long)nn * (h / 2) + yy / 2) * (w / 2) + xx / 2;
+    float v = from_bf16(g[pg * ldg + ch]) * 0.25f;
+    if (add) v += from_bf16(add[p * lda + ch]);
+    if (msrc && !(from_bf16(msrc[p * ldm + ch]) > 0.0f)) v = 0.0f;
+    dx[p * lddx + ch] = to_bf16(v);
+  }
+}
+
+// h, w: the half-resolution size (upsample input / gradient output).
+__global__ void upsample2_kernel(const uint16_t* __restrict__ x, int ldx, int N, int h, int w, int c,
+                                 uint16_t* __restrict__ y, int ldy) {
+  const long long n = (long long)N * 4 * h * w * c;
+  const int W2 = 2 * w;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const int ch = (int)(i % c);
+    const long long p = i / c;
+    const int xx = (int)(p % W2);
+    const long long q = p / W2;
+    const int yy = (int)(q % (2 * h));
+    const int nn = (int)(q / (2 * h));
+    y[p * ldy + ch] = x[(((long long)nn * h + yy / 2) * w + xx / 2) * ldx + ch];
+  }
+}
+
+__global__ void upsample2_grad_kernel(const uint16_t* __restrict__ g, int ldg, int N, int h, int w, int c,
+                                      uint16_t* __restrict__ dx, int lddx) {
+  const long long n = (long long)N * h * w * c;
+  const int W2 = 2 * w;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const int ch = (int)(i % c);
+    const long long p = i / c;
+    const int xx = (int)(p % w);
+    const long long q = p / w;
+    const int yy = (int)(q % h);
+    const int nn = (int)(q / h);
+    const long long b = ((long long)nn * 2 * h + 2 * yy) * W2 + 2 * xx;
+    const float s = (from_bf16(g[b * ldg + ch]) + from_bf16(g[(b + 1) * ldg + ch])) +
+                    (from_bf16(g[(b + W2) * ldg + ch]) + from_bf16(g[(b + W2 + 1) * ldg + ch]));
+    dx[p * lddx + ch] = to_bf16(s);
+  }
+}
+
+// --------------------------------------------------- input, loss, output --
+constexpr float kLogZmin = -1.2039728043259361f;  // log(0.3)
+constexpr float kLogZmax = 3.912023005428146f;    // log(50)
+
+// Network input, 32 channels: R, G, B / 255, hole (mask != 0), log-depth in
+// [log 0.3, log 50] -> [0, 1] (clamped; +inf and NaN -> 1), then zeros.
+__global__ void unet_input_kernel(const uint32_t* __restrict__ rgba, const float* __restrict__ depth,
+                                  const uint8_t* __restrict__ mask, long long npix, uint16_t* __restrict__ x) {
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += (long long)gridDim.x * blockDim.x) {
+    const uint32_t c = rgba[p];
+    const float z = depth[p];
+    float ld = (logf(z) - kLogZmin) / (kLogZmax - kLogZmin);
+    ld = (ld >= 0.0f) ? (ld <= 1.0f ? ld : 1.0f) : (ld < 0.0f ? 0.0f : 1.0f);  // NaN -> 1
+    uint16_t v[8];
+    v[0] = to_bf16((float)(c & 255u) / 255.0f);
+    v[1] = to_bf16((float)((c >> 8) & 255u) / 255.0f);
+    v[2] = to_bf16((float)((c >> 16) & 255u) / 255.0f);
+    v[3] = to_bf16(mask[p] != 0 ? 1.0f : 0.0f);
+    v[4] = to_bf16(ld);
+    v[5] = v[6] = v[7] = 0;
+    u32x4 w0 = {(uint32_t)v[0] | ((uint32_t)v[1] << 16), (uint32_t)v[2] | ((uint32_t)v[3] << 16), (uint32_t)v[4], 0u};
+    u32x4 zero = {0u, 0u, 0u, 0u};
+    u32x4* dst = reinterpret_cast<u32x4*>(x + p * 32);
+    dst[0] = w0;
+    dst[1] = zero;
+    dst[2] = zero;
+    dst[3] = zero;
+  }
+}
+
+__global__ void count_holes_kernel(const uint8_t* __restrict__ mask, long long npix, unsigned int* __restrict__ out) {
+  unsigned int c = 0;
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += (long long)gridDim.x * blockDim.x)
+    c += mask[p] != 0;
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off);
+  if ((threadIdx.x & 63) == 0) atomicAdd(out, c);
+}
+
+__global__ void zero_u32_kernel(unsigned int* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
+}
+
+// Masked L1: per-block partial sums of |plain/255 + res - target/255| over
+// hole pixels and RGB, and the gradient d(loss)/d(res) (bf16, 32 channels:
+// the head convolution is padded to 32 outputs).
+constexpr int kLossThreads = 256;
+__global__ __launch_bounds__(kLossThreads) void l1_grad_kernel(const float* __restrict__ res,
+                                                               const uint32_t* __restrict__ rgba,
+                                                               const uint8_t* __restrict__ mask,
+                                                               const uint32_t* __restrict__ target, long long npix,
+                                                               const unsigned int* __restrict__ nholes,
+                                                               uint16_t* __restrict__ g, float* __restrict__ partial) {
+  __shared__ float red[kLossThreads];
+  const unsigned int nh = *nholes;
+  const float scale = nh ? 1.0f / (3.0f * (float)nh) : 0.0f;
+  float acc = 0.0f;
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += (long long)gridDim.x * blockDim.x) {
+    uint16_t gv[3] = {0, 0, 0};
+    if (mask[p] != 0) {
+      const uint32_t c = rgba[p], tg = target[p];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const float pred = (float)((c >> (8 * k)) & 255u) / 255.0f + res[p * 3 + k];
+        const float d = pred - (float)((tg >> (8 * k)) & 255u) / 255.0f;
+        acc += fabsf(d);
+        gv[k] = to_bf16(d > 0.0f ? scale : (d < 0.0f ? -scale : 0.0f));
+      }
+    }
+    u32x4 w0 = {(uint32_t)gv[0] | ((uint32_t)gv[1] << 16), (uint32_t)gv[2], 0u, 0u};
+    u32x4 zero = {0u, 0u, 0u, 0u};
+    u32x4* dst = reinterpret_cast<u32x4*>(g + p * 32);
+    dst[0] = w0;
+    dst[1] = zero;
+    dst[2] = zero;
+    dst[3] = zero;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = kLossThreads / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ void l1_finish_kernel(const float* __restrict__ partial, int nblocks, const unsigned int* __restrict__ nholes,
+                                 float* __restrict__ loss) {
+  if (threadIdx.x == 0) {
+    float s = 0.0f;
+    for (int b = 0; b < nblocks; ++b) s += partial[b];  // fixed order
+    const unsigned int nh = *nholes;
+    *loss = nh ? s / (3.0f * (float)nh) : 0.0f;
+  }
+}
+
+// Hole pixels: u8 = clamp(rint(255 * (plain/255 + res))); others copied.
+__global__ void composite_kernel(const float* __restrict__ res, const uint32_t* __restrict__ rgba,
+                                 const uint8_t* __restrict__ mask, long long npix, uint32_t* __restrict__ out) {
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += (long long)gridDim.x * blockDim.x) {
+    const uint32_t c = rgba[p];
+    uint32_t o = c;
+    if (mask[p] != 0) {
+      o = c & 0xFF000000u;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        const float pred = (float)((c >> (8 * k)) & 255u) / 255.0f + res[p * 3 + k];
+        float q = rintf(255.0f * pred);
+        q = q < 0.0f ? 0.0f : (q > 255.0f ? 255.0f : q);
+        o |= (uint32_t)q << (8 * k);
+      }
+    }
+    out[p] = o;
+  }
+}
+
+// AdamW (decoupled weight decay, bias-corrected moments), FP32, elementwise.
+__global__ void adamw_kernel(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
+                             const float* __restrict__ g, long long n, float lr, float b1, float b2, float eps, float wd,
+                             float c1, float c2) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    float wi = w[i] * (1.0f - lr * wd);
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float mh = mi / c1, vh = vi / c2;
+    wi -= lr * mh / (sqrtf(vh) + eps);
+    w[i] = wi;
+  }
+}
+
+int grid_1d(long long n, int threads) {
+  const long long g = (n + threads - 1) / threads;
+  return (int)(g < 1 ? 1 : (g > 65536 ? 65536 : g));
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- launchers --
+hipError_t nn_conv3x3(const uint16_t* x, int ldx, int N, int H, int W, int Cin, const uint16_t* wgt, int Cout, void* y,
+                      int ldy, int y_fp32, int cout_store, int epi, const uint16_t* msrc, int ldm, hipStream_t s) {
+  const long long P = (long long)N * H * W;
+  const unsigned gx = (unsigned)((P + 63) / 64);
+  if (Cout % 64 == 0) {
+    hipLaunchKernelGGL(conv3x3_kernel<64>, dim3(gx, Cout / 64), dim3(kConvThreads), 0, s, x, ldx, N, H, W, Cin, wgt,
+                       Cout, y, ldy, y_fp32, cout_store, epi, msrc, ldm);
+  } else {
+    hipLaunchKernelGGL(conv3x3_kernel<32>, dim3(gx, Cout / 32), dim3(kConvThreads), 0, s, x, ldx, N, H, W, Cin, wgt,
+                       Cout, y, ldy, y_fp32, cout_store, epi, msrc, ldm);
+  }
+  return hipGetLastError();
+}
+
+size_t nn_wgrad_chunks(long long P) { return (size_t)((P + kWgradChunk - 1) / kWgradChunk); }
+
+hipError_t nn_conv3x3_wgrad(const uint16_t* x, int ldx, const uint16_t* dy, int lddy, int N, int H, int W, int Cin,
+                            int Cout, float* dw, float* ws, hipStream_t s) {
+  const long long P = (long long)N * H * W;
+  const int nchunks = (int)nn_wgrad_chunks(P);
+  const int tco = Cout % 64 == 0 ? 64 : 32, tci = Cin % 64 == 0 ? 64 : 32;
+  const dim3 grid(9 * (Cout / tco) * (Cin / tci), nchunks);
+  if (tco == 64 && tci == 64)
+    hipLaunchKernelGGL((conv3x3_wgrad_kernel<64, 64>), grid, dim3(256), 0, s, x, ldx, dy, lddy, N, H, W, Cin, Cout,
+                       kWgradChunk, ws);
+  else if (tco == 64)
+    hipLaunchKernelGGL((conv3x3_wgrad_kernel<64, 32>), grid, dim3(256), 0, s, x, ldx, dy, lddy, N, H, W, Cin, Cout,
+                       kWgradChunk, ws);
+  else if (tci == 64)
+    hipLaunchKernelGGL((conv3x3_wgrad_kernel<32, 64>), grid, dim3(256), 0, s, x, ldx, dy, lddy, N, H, W, Cin, Cout,
+                       kWgradChunk, ws);
+  else
+    hipLaunchKernelGGL((conv3x3_wgrad_kernel<32, 32>), grid, dim3(256), 0, s, x, ldx, dy, lddy, N, H, W, Cin, Cout,
+                       kWgradChunk, ws);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const long long n = 9LL * Cout * Cin;
+  hipLaunchKernelGGL(sum_chunks_kernel, dim3(grid_1d(n, 256)), dim3(256), 0, s, ws, nchunks, n, dw);
+  return hipGetLastError();
+}
+
+hipError_t nn_pack_weights(const float* w, int cin, int cout, uint16_t* wf, uint16_t* wb, hipStream_t s) {
+  hipLaunchKernelGGL(pack_weights_kernel, dim3(grid_1d(9LL * cin * cout, 256)), dim3(256), 0, s, w, cin, cout, wf, wb);
+  return hipGetLastError();
+}
+
+hipError_t nn_avgpool2(const uint16_t* x, int ldx, int N, int h, int w, int c, uint16_t* y, int ldy, hipStream_t s) {
+  hipLaunchKernelGGL(avgpool2_kernel, dim3(grid_1d((long long)N * (h / 2) * (w / 2) * c, 256)), dim3(256), 0, s, x, ldx,
+                     N, h, w, c, y, ldy);
+  return hipGetLastError();
+}
+
+hipError_t nn_avgpool2_grad(const uint16_t* g, int ldg, const uint16_t* add, int lda, const uint16_t* msrc, int ldm,
+                            int N, int h, int w, int c, uint16_t* dx, int lddx, hipStream_t s) {
+  hipLaunchKernelGGL(avgpool2_grad_kernel, dim3(grid_1d((long long)N * h * w * c, 256)), dim3(256), 0, s, g, ldg, add,
+                     lda, msrc, ldm, N, h, w, c, dx, lddx);
+  return hipGetLastError();
+}
+
+hipError_t nn_upsample2(const uint16_t* x, int ldx, int N, int h, int w, int c, uint16_t* y, int ldy, hipStream_t s) {
+  hipLaunchKernelGGL(upsample2_kernel, dim3(grid_1d((long long)N * 4 * h * w * c, 256)), dim3(256), 0, s, x, ldx, N, h,
+                     w, c, y, ldy);
+  return hipGetLastError();
+}
+
+hipError_t nn_upsample2_grad(const uint16_t* g, int ldg, int N, int h, int w, int c, uint16_t* dx, int lddx,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(upsample2_grad_kernel, dim3(grid_1d((long long)N * h * w * c, 256)), dim3(256), 0, s, g, ldg, N, h,
+                     w, c, dx, lddx);
+  return hipGetLastError();
+}
+
+hipError_t nn_input(const uint32_t* rgba, const float* depth, const uint8_t* mask, long long npix, uint16_t* x,
+                    hipStream_t s) {
+  hipLaunchKernelGGL(unet_input_kernel, dim3(grid_1d(npix, 256)), dim3(256), 0, s, rgba, depth, mask, npix, x);
+  return hipGetLastError();
+}
+
+hipError_t nn_l1_grad(const float* res, const uint32_t* rgba, const uint8_t* mask, const uint32_t* target,
+                      long long npix, uint16_t* g, float* loss, float* ws, hipStream_t s) {
+  // ws layout: [0] hole count (u32), [16 ..] per-block partial sums.
+  unsigned int* cnt = reinterpret_cast<unsigned int*>(ws);
+  float* partial = ws + 16;
+  hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, cnt, 1);
+  hipLaunchKernelGGL(count_holes_kernel, dim3(grid_1d(npix, 256) < 1024 ? grid_1d(npix, 256) : 1024), dim3(256), 0, s,
+                     mask, npix, cnt);
+  const int nb = kLossBlocks;
+  hipLaunchKernelGGL(l1_grad_kernel, dim3(nb), dim3(kLossThreads), 0, s, res, rgba, mask, target, npix, cnt, g,
+                     partial);
+  hipLaunchKernelGGL(l1_finish_kernel, dim3(1), dim3(64), 0, s, partial, nb, cnt, loss);
+  return hipGetLastError();
+}
+
+hipError_t nn_composite(const float* res, const uint32_t* rgba, const uint8_t* mask, long long npix, uint32_t* out,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(composite_kernel, dim3(grid_1d(npix, 256)), dim3(256), 0, s, res, rgba, mask, npix, out);
+  return hipGetLastError();
+}
+
+hipError_t nn_adamw(float* w, float* m, float* v, const float* g, long long n, float lr, float b1, float b2, float eps,
+                    float wd, int step, hipStream_t s) {
+  const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+  hipLaunchKernelGGL(adamw_kernel, dim3(grid_1d(n, 256)), dim3(256), 0, s, w, m, v, g, n, lr, b1, b2, eps, wd, c1, c2);
+  return hipGetLastError();
+}
+
+}  // namespace yoro

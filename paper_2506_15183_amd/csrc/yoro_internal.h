@@ -79,6 +79,33 @@ hipError_t launch_fill(uint32_t* rgba, float* depth, uint8_t* mask, int32_t widt
                        int32_t target_eye, int32_t fill_mode, int ppt, int grid, hipStream_t stream);
 hipError_t launch_hole_sse(const uint32_t* rgba, const uint32_t* ref, const uint8_t* mask, int64_t n,
                            unsigned long long* out, int grid, hipStream_t stream);
+// This thread's message for yoro_last_error() (defined in capi.hip).
+void set_last_error(const char* msg);
+
+// Learned-fill kernels (defined in nn.hip).  bf16 tensors are raw uint16_t.
+constexpr int kWgradChunk = 2048;  // pixels per split-K chunk of the weight gradient
+constexpr int kLossBlocks = 512;   // blocks (and partial sums) of the L1 loss
+size_t nn_wgrad_chunks(long long P);
+hipError_t nn_conv3x3(const uint16_t* x, int ldx, int N, int H, int W, int Cin, const uint16_t* wgt, int Cout, void* y,
+                      int ldy, int y_fp32, int cout_store, int epi, const uint16_t* msrc, int ldm, hipStream_t s);
+hipError_t nn_conv3x3_wgrad(const uint16_t* x, int ldx, const uint16_t* dy, int lddy, int N, int H, int W, int Cin,
+                            int Cout, float* dw, float* ws, hipStream_t s);
+hipError_t nn_pack_weights(const float* w, int cin, int cout, uint16_t* wf, uint16_t* wb, hipStream_t s);
+hipError_t nn_avgpool2(const uint16_t* x, int ldx, int N, int h, int w, int c, uint16_t* y, int ldy, hipStream_t s);
+hipError_t nn_avgpool2_grad(const uint16_t* g, int ldg, const uint16_t* add, int lda, const uint16_t* msrc, int ldm,
+                            int N, int h, int w, int c, uint16_t* dx, int lddx, hipStream_t s);
+hipError_t nn_upsample2(const uint16_t* x, int ldx, int N, int h, int w, int c, uint16_t* y, int ldy, hipStream_t s);
+hipError_t nn_upsample2_grad(const uint16_t* g, int ldg, int N, int h, int w, int c, uint16_t* dx, int lddx,
+                             hipStream_t s);
+hipError_t nn_input(const uint32_t* rgba, const float* depth, const uint8_t* mask, long long npix, uint16_t* x,
+                    hipStream_t s);
+hipError_t nn_l1_grad(const float* res, const uint32_t* rgba, const uint8_t* mask, const uint32_t* target,
+                      long long npix, uint16_t* g, float* loss, float* ws, hipStream_t s);
+hipError_t nn_composite(const float* res, const uint32_t* rgba, const uint8_t* mask, long long npix, uint32_t* out,
+                        hipStream_t s);
+hipError_t nn_adamw(float* w, float* m, float* v, const float* g, long long n, float lr, float b1, float b2, float eps,
+                    float wd, int step, hipStream_t s);
+
 // Occupancy-derived workgroups per CU for the row kernels.
 int warp_blocks_per_cu(int max_width, bool batch);
 int fill_blocks_per_cu(int width);

@@ -8,7 +8,7 @@ disparity (Section 6, reprojection equation, reduced to parallel stereo).
 
 * ``config1_frame``: one 256 x 256 frame, 8 objects, centre depth U[0.5, 20] m,
   B = 0.064 m, f = 200 px, source = left eye, target = right eye.
-* ``config2_frame``: one 1832 x 1920 frame (a Quest 2 eye, Section 10), 200
+* ``config2_frame``: one 1832 x 1920 frame (a Quest 2 eye, Section 12), 200
   objects, centre depth log-uniform on [0.3, 50] m, object-space checker of
   cell U{4..32} px at the object's depth, B = 0.063 m, f = 900 px.
 * ``config3_frames``: 64 frames, 16 each of 1024x1024, 1440x1600, 1832x1920

@@ -20,7 +20,8 @@ FILL_NONE, FILL_NEAREST_BG = 0, 1
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE_TOO_SMALL, ERR_DEVICE = 0, 1, 2, 3, 4
 MAX_WIDTH, MAX_HEIGHT = 8192, 16384
 
-# Every symbol include/yoro.h declares.
+# Every symbol include/yoro.h declares (the learned-fill layers of
+# include/yoro_nn.h are bound in unet.py).
 EXPORTS = (
     "yoro_reproject",
     "yoro_fill_holes",

@@ -11,8 +11,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def header_functions():
-    text = open(os.path.join(ROOT, "include", "yoro.h")).read()
+def header_functions(name="yoro.h"):
+    text = open(os.path.join(ROOT, "include", name)).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(yoro_[a-z0-9_]+)\s*\(", text)))
 
@@ -31,6 +31,28 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
     assert set(header_functions()) == set(yoro.EXPORTS)
     assert yoro.version() == 1
+    for name in header_functions("yoro_nn.h"):
+        assert hasattr(lib, name), name
+
+
+def test_nn_host_validation_rejects_without_launching():
+    from paper_2506_15183_amd import unet, yoro
+
+    L = unet.nnlib()
+    a = ctypes.c_void_p(0x100000)
+    b = ctypes.c_void_p(0x200000)
+    c = ctypes.c_void_p(0x300000)
+    # cin not a multiple of 32
+    assert L.yoro_nn_conv3x3(a, 40, 1, 8, 8, 40, b, 32, c, 32, 0, 32, 0, None, 0, None) == yoro.ERR_INVALID_ARG
+    # misaligned input
+    assert L.yoro_nn_conv3x3(ctypes.c_void_p(0x100002), 32, 1, 8, 8, 32, b, 32, c, 32, 0, 32, 0, None, 0,
+                             None) == yoro.ERR_INVALID_ARG
+    # ReLU-derivative epilogue without its source
+    assert L.yoro_nn_conv3x3(a, 32, 1, 8, 8, 32, b, 32, c, 32, 0, 32, 2, None, 0, None) == yoro.ERR_INVALID_ARG
+    # odd pool size, workspace too small
+    assert L.yoro_nn_avgpool2(a, 32, 1, 7, 8, 32, b, 32, None) == yoro.ERR_INVALID_ARG
+    assert L.yoro_nn_conv3x3_wgrad(a, 32, b, 32, 1, 8, 8, 32, 32, c, a, 16, None) == yoro.ERR_WORKSPACE_TOO_SMALL
+    assert L.yoro_nn_adamw(a, b, c, a, 10, 1e-3, 0.9, 0.999, 1e-8, 0.01, 0, None) == yoro.ERR_INVALID_ARG
 
 
 def test_host_validation_rejects_without_launching():
