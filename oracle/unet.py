@@ -127,9 +127,14 @@ def make_input(rgba: np.ndarray, depth: np.ndarray, mask: np.ndarray) -> np.ndar
 
 
 def composite(res: np.ndarray, rgba: np.ndarray, mask: np.ndarray) -> np.ndarray:
-    """Hole pixels: u8 = clamp(rint(255 * (plain/255 + residual))); others unchanged."""
-    pred = rgba[..., :3].astype(np.float64) / 255.0 + res
-    q = np.clip(np.rint(255.0 * pred), 0, 255).astype(np.uint8)
+    """Hole pixels: u8 = clamp(rint(255 * (plain/255 + residual))), alpha and
+    non-hole pixels unchanged.  The quantisation turns floating point into an
+    integer, so it is decided in the precision the device uses for it: FP32
+    (plain/255 and the product correctly rounded, the sum of an FP32
+    residual, round half to even)."""
+    f = np.float32
+    pred = rgba[..., :3].astype(f) / f(255.0) + np.asarray(res).astype(f)
+    q = np.clip(np.rint(f(255.0) * pred), 0, 255).astype(np.uint8)
     out = rgba.copy()
     hole = mask != 0
     out[..., :3][hole] = q[hole]

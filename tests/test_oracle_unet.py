@@ -172,10 +172,31 @@ def test_make_input_and_composite_closed_forms():
     assert np.allclose(x[0, 0, 0], [1.0, 0.0, 0.2, 0.0, 0.0], atol=1e-7)
     assert np.allclose(x[0, 0, 1], [10 / 255, 20 / 255, 30 / 255, 1.0, 1.0])
     res = np.zeros((1, 1, 2, 3))
-    res[0, 0, 1] = [0.5 / 255, -1.0, 2.0]
+    res[0, 0, 1] = [0.0, -1.0, 2.0]
     out = U.composite(res, rgba, mask)
     assert out[0, 0, 0].tolist() == [255, 0, 51, 7]          # not a hole: unchanged
-    assert out[0, 0, 1].tolist() == [10, 0, 255, 40]         # rint(10.5) = 10 (ties to even), clamps, alpha kept
+    assert out[0, 0, 1].tolist() == [10, 0, 255, 40]         # zero residual keeps, clamps, alpha kept
+
+
+def test_composite_quantisation_in_fp32():
+    """Zero residual gives back every level, k/255 shifts by k (clamped), and
+    an exact FP32 tie x.5 rounds to the even neighbour."""
+    f = np.float32
+    lv = np.arange(256, dtype=np.uint8)
+    rgba = np.stack([lv, lv, lv, lv], -1)[None, None]
+    mask = np.ones(rgba.shape[:3], np.uint8)
+    for k in range(-5, 6):
+        out = U.composite(np.full(rgba.shape[:3] + (3,), f(k) / f(255)), rgba, mask)
+        assert np.array_equal(out[..., 0], np.clip(lv.astype(int) + k, 0, 255)[None, None])
+        assert np.array_equal(out[..., 3], rgba[..., 3])
+    for c in (10, 11, 100, 101):
+        r0 = f(0.5 / 255)
+        cand = r0 + np.arange(-200, 200, dtype=np.float32) * np.spacing(r0)
+        tie = cand[f(255) * (f(c) / f(255) + cand) == f(c + 0.5)]
+        assert tie.size > 0
+        px = np.array([[[[c, c, c, 255]]]], np.uint8)
+        out = U.composite(np.full((1, 1, 1, 3), tie[0]), px, np.ones((1, 1, 1), np.uint8))
+        assert out[0, 0, 0, 0] == (c if c % 2 == 0 else c + 1)
 
 
 def test_adamw_matches_torch():
