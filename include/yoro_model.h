@@ -1,0 +1,73 @@
+/*
+ * yoro_model.h -- inference of the learned hole filler as single calls.
+ *
+ * The network is the encoder-decoder whose layers yoro_nn.h exposes (the
+ * paper's own disocclusion fill is the filter of Section 7; a learned filler
+ * stands in for the data-driven inpainting that section sets aside as too
+ * heavy for a phone, and refines the nearest-background fill of Section 5,
+ * Observation O2).  These calls run its whole forward pass and composite on
+ * the device, so a serving loop can use it without a host-side sequencer.
+ *
+ * Weights: "model weights" are the bf16 forward copies of all 18 layers,
+ * packed back to back; layer i occupies elements [offset[i], offset[i+1])
+ * as [9][cout_pad][cin_pad] (yoro_model_layout).  yoro_model_pack makes
+ * them from FP32 masters laid out the same way.
+ *
+ * Conventions as in yoro.h: caller-owned device pointers, no allocation or
+ * synchronisation, work queued on the given stream, YORO_ERR_INVALID_ARG
+ * before anything is queued, YORO_ERR_WORKSPACE_TOO_SMALL when the
+ * workspace is short, YORO_ERR_DEVICE on a failed launch.
+ */
+#ifndef YORO_MODEL_H
+#define YORO_MODEL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define YORO_MODEL_LAYERS 18
+
+/* Host arrays: cin_pad[18], cout_pad[18] (the kernels' channel counts, each
+ * a multiple of 32) and offset[19] (elements).  Any pointer may be NULL. */
+int32_t yoro_model_layout(int32_t* cin_pad, int32_t* cout_pad, int64_t* offset);
+size_t yoro_model_weights_bytes(void);
+
+/* FP32 masters (offset[18] floats, same layout) -> bf16 model weights
+ * (round to nearest, ties to even). */
+int32_t yoro_model_pack(const float* master, void* weights, void* hip_stream);
+
+/* Workspace for n images of h x w (h, w multiples of 8, n*h*w < 2^31). */
+size_t yoro_model_workspace_bytes(int32_t n, int32_t h, int32_t w);
+
+/* Residual (FP32 [n*h*w][3]) of the network on n plain-filled images
+ * (rgba u8 [n][h][w][4], depth f32 [n][h][w], mask u8 [n][h][w]). */
+int32_t yoro_model_residual(const void* weights, const uint8_t* rgba, const float* depth, const uint8_t* mask,
+                            int32_t n, int32_t h, int32_t w, float* res, void* workspace, size_t workspace_bytes,
+                            void* hip_stream);
+
+/* Learned fill of n whole frames: out = rgba except on hole pixels
+ * (mask != 0), which get clamp(rint(255 * (plain / 255 + residual))) with
+ * alpha kept.  out may equal rgba. */
+int32_t yoro_model_fill(const void* weights, const uint8_t* rgba, const float* depth, const uint8_t* mask, int32_t n,
+                        int32_t h, int32_t w, uint8_t* out, void* workspace, size_t workspace_bytes,
+                        void* hip_stream);
+
+/* Learned fill of the planned blocks of one w x h frame (plan: device int32
+ * [k][4] as in yoro_nn.h; crop = tile + 2 * halo; the plan is trusted to
+ * keep crops inside the frame).  All k crops are gathered first, then run
+ * `chunk` at a time, so out may equal rgba.  Pixels outside the planned
+ * blocks, and non-hole pixels, are not written. */
+size_t yoro_model_tiles_workspace_bytes(int32_t k, int32_t chunk, int32_t tile, int32_t halo);
+int32_t yoro_model_fill_tiles(const void* weights, const uint8_t* rgba, const float* depth, const uint8_t* mask,
+                              int32_t w, int32_t h, const int32_t* plan, int32_t k, int32_t tile, int32_t halo,
+                              int32_t chunk, uint8_t* out, void* workspace, size_t workspace_bytes,
+                              void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* YORO_MODEL_H */

@@ -72,7 +72,8 @@ int32_t yoro_nn_conv3x3_wgrad(const void* x, int32_t ldx, const void* dy, int32_
                               void* hip_stream);
 
 /* FP32 master [9][cout][cin] -> bf16 forward copy [9][cout][cin] and backward
- * copy [9][cin][cout] with taps flipped (t -> 8 - t). */
+ * copy [9][cin][cout] with taps flipped (t -> 8 - t); w_bwd may be NULL
+ * (inference needs only the forward copy). */
 int32_t yoro_nn_pack_weights(const float* w, int32_t cin, int32_t cout, void* w_fwd, void* w_bwd, void* hip_stream);
 
 /* 2x2 average pool: x is n x h x w (h, w even), y is n x h/2 x w/2. */
@@ -109,6 +110,36 @@ int32_t yoro_nn_l1_grad(const float* res, const uint8_t* rgba, const uint8_t* ma
  * R, G, B and keep their alpha; other pixels are copied. */
 int32_t yoro_nn_composite(const float* res, const uint8_t* rgba, const uint8_t* mask, int64_t npix, uint8_t* out,
                           void* hip_stream);
+
+/*
+ * Hole-tile inference.  A w x h frame is cut into tile x tile blocks; only
+ * blocks with a hole need the network, each run inside a crop of
+ * crop x crop pixels (the block plus a halo on every side at least as wide
+ * as the network's boundary reach, 54 px) placed inside the frame on the
+ * 8-pixel pooling grid.  Each crop edge is then a frame edge or a halo away
+ * from the block, so the block's result equals the whole frame's.
+ *
+ * A plan is a device int32 array [k][4]: (crop x, crop y, block x, block y)
+ * per crop, the crop inside the frame and the block inside the crop.
+ *
+ * yoro_nn_tile_holes: counts[ty * ntx + tx] = number of pixels with
+ *   mask != 0 in block (tx, ty), ntx = ceil(w / tile); device u32 array.
+ * yoro_nn_gather_crops: copy the k planned crops of a frame's RGBA, depth and
+ *   mask into contiguous crop batches (k x crop x crop).
+ * yoro_nn_composite_tiles: for each planned crop, write the learned composite
+ *   of the hole pixels of its block into out (a frame, normally a copy of
+ *   the plain fill); res is the network's residual over the crop batch.
+ * The plan is read on the device and trusted: the caller keeps every crop
+ * inside the frame.
+ */
+int32_t yoro_nn_tile_holes(const uint8_t* mask, int32_t w, int32_t h, int32_t tile, uint32_t* counts,
+                           void* hip_stream);
+int32_t yoro_nn_gather_crops(const uint8_t* rgba, const float* depth, const uint8_t* mask, int32_t w, int32_t h,
+                             const int32_t* plan, int32_t k, int32_t crop, uint8_t* crop_rgba, float* crop_depth,
+                             uint8_t* crop_mask, void* hip_stream);
+int32_t yoro_nn_composite_tiles(const float* res, const int32_t* plan, int32_t k, int32_t crop, int32_t tile,
+                                const uint8_t* rgba, const uint8_t* mask, int32_t w, int32_t h, uint8_t* out,
+                                void* hip_stream);
 
 /* One AdamW step on n FP32 parameters (decoupled weight decay, bias-corrected
  * moments; step counts from 1). */

@@ -87,7 +87,7 @@ int32_t yoro_nn_conv3x3_wgrad(const void* x, int32_t ldx, const void* dy, int32_
 
 int32_t yoro_nn_pack_weights(const float* w, int32_t cin, int32_t cout, void* w_fwd, void* w_bwd, void* hip_stream) {
   const char* who = "yoro_nn_pack_weights";
-  if (!w || !w_fwd || !w_bwd || cin <= 0 || cout <= 0) return nn_fail(YORO_ERR_INVALID_ARG, "%s: bad argument", who);
+  if (!w || !w_fwd || cin <= 0 || cout <= 0) return nn_fail(YORO_ERR_INVALID_ARG, "%s: bad argument", who);
   return launched(yoro::nn_pack_weights(w, cin, cout, static_cast<uint16_t*>(w_fwd), static_cast<uint16_t*>(w_bwd),
                                         (hipStream_t)hip_stream),
                   who);
@@ -173,6 +173,40 @@ int32_t yoro_nn_adamw(float* w, float* m, float* v, const float* g, int64_t n, f
   const char* who = "yoro_nn_adamw";
   if (!w || !m || !v || !g || n <= 0 || step < 1) return nn_fail(YORO_ERR_INVALID_ARG, "%s: bad argument", who);
   return launched(yoro::nn_adamw(w, m, v, g, n, lr, beta1, beta2, eps, weight_decay, step, (hipStream_t)hip_stream),
+                  who);
+}
+
+int32_t yoro_nn_tile_holes(const uint8_t* mask, int32_t w, int32_t h, int32_t tile, uint32_t* counts,
+                           void* hip_stream) {
+  const char* who = "yoro_nn_tile_holes";
+  if (!mask || !counts || w <= 0 || h <= 0 || tile <= 0 || !al4(counts))
+    return nn_fail(YORO_ERR_INVALID_ARG, "%s: bad argument", who);
+  return launched(yoro::nn_tile_holes(mask, w, h, tile, counts, (hipStream_t)hip_stream), who);
+}
+
+int32_t yoro_nn_gather_crops(const uint8_t* rgba, const float* depth, const uint8_t* mask, int32_t w, int32_t h,
+                             const int32_t* plan, int32_t k, int32_t crop, uint8_t* crop_rgba, float* crop_depth,
+                             uint8_t* crop_mask, void* hip_stream) {
+  const char* who = "yoro_nn_gather_crops";
+  if (!rgba || !depth || !mask || !plan || !crop_rgba || !crop_depth || !crop_mask || w <= 0 || h <= 0 || k <= 0 ||
+      k > 65535 || crop <= 0 || crop > w || crop > h || !al4(rgba) || !al4(depth) || !al4(crop_rgba) ||
+      !al4(crop_depth) || !al4(plan))
+    return nn_fail(YORO_ERR_INVALID_ARG, "%s: bad argument", who);
+  return launched(yoro::nn_gather_crops(reinterpret_cast<const uint32_t*>(rgba), depth, mask, w, plan, k, crop,
+                                        reinterpret_cast<uint32_t*>(crop_rgba), crop_depth, crop_mask,
+                                        (hipStream_t)hip_stream),
+                  who);
+}
+
+int32_t yoro_nn_composite_tiles(const float* res, const int32_t* plan, int32_t k, int32_t crop, int32_t tile,
+                                const uint8_t* rgba, const uint8_t* mask, int32_t w, int32_t h, uint8_t* out,
+                                void* hip_stream) {
+  const char* who = "yoro_nn_composite_tiles";
+  if (!res || !plan || !rgba || !mask || !out || k <= 0 || k > 65535 || crop <= 0 || tile <= 0 || tile > crop ||
+      w <= 0 || h <= 0 || !al4(rgba) || !al4(out) || !al4(plan))
+    return nn_fail(YORO_ERR_INVALID_ARG, "%s: bad argument", who);
+  return launched(yoro::nn_composite_tiles(res, plan, k, crop, tile, w, h, reinterpret_cast<const uint32_t*>(rgba),
+                                           mask, reinterpret_cast<uint32_t*>(out), (hipStream_t)hip_stream),
                   who);
 }
 

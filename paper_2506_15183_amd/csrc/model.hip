@@ -1,0 +1,250 @@
+// Inference of the learned hole filler as single calls (include/yoro_model.h):
+// the forward sequence of the encoder-decoder over the layer kernels of
+// nn.hip, its activation buffers carved from a caller workspace, and the
+// hole-tile driver (gather all crops, run them in chunks, composite blocks).
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstdint>
+
+#include "yoro.h"
+#include "yoro_internal.h"
+#include "yoro_model.h"
+#include "yoro_nn.h"
+
+namespace {
+
+struct Layer {
+  int cin, cout;  // kernel channel counts (multiples of 32)
+};
+// e0a e0b e1a e1b e2a e2b e3a e3b d2a d2b d2c d1a d1b d1c d0a d0b d0c head; the
+// 5-channel input and the 3-channel head are padded to 32.
+constexpr Layer kLayers[YORO_MODEL_LAYERS] = {
+    {32, 32},   {32, 32},   {32, 64},   {64, 64},   {64, 128},  {128, 128}, {128, 256}, {256, 256}, {256, 128},
+    {256, 128}, {128, 128}, {128, 64},  {128, 64},  {64, 64},   {64, 32},   {64, 32},   {32, 32},   {32, 32}};
+
+long long layer_offset(int i) {
+  long long o = 0;
+  for (int j = 0; j < i; ++j) o += 9LL * kLayers[j].cin * kLayers[j].cout;
+  return o;
+}
+
+int32_t model_fail(int32_t status, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  yoro::set_last_error(buf);
+  return status;
+}
+
+bool al16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+bool al4(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }
+
+// Activation buffers of one forward pass (bf16 NHWC; res FP32 [P0][3]).
+struct Acts {
+  uint16_t *x0, *e0a, *c0, *d0b, *d0c, *u0;
+  uint16_t *p1, *e1a, *c1, *d1b, *d1c, *u1;
+  uint16_t *p2, *e2a, *c2, *d2b, *d2c, *u2;
+  uint16_t *p3, *e3a, *e3b;
+  float* res;
+};
+
+// Lays the buffers out from base (NULL: only measures); returns the bytes used.
+size_t carve(char* base, long long n, int h, int w, Acts* a) {
+  size_t off = 0;
+  auto take = [&](long long elems, size_t esize) -> char* {
+    char* p = base ? base + off : nullptr;
+    off += ((size_t)elems * esize + 255) & ~(size_t)255;
+    return p;
+  };
+  long long P[4];
+  for (int l = 0; l < 4; ++l) P[l] = n * (long long)(h >> l) * (w >> l);
+  auto bf = [&](long long p, int c) { return reinterpret_cast<uint16_t*>(take(p * c, 2)); };
+  Acts t;
+  t.x0 = bf(P[0], 32), t.e0a = bf(P[0], 32), t.c0 = bf(P[0], 64), t.d0b = bf(P[0], 32), t.d0c = bf(P[0], 32);
+  t.u0 = bf(P[0], 64);
+  t.p1 = bf(P[1], 32), t.e1a = bf(P[1], 64), t.c1 = bf(P[1], 128), t.d1b = bf(P[1], 64), t.d1c = bf(P[1], 64);
+  t.u1 = bf(P[1], 128);
+  t.p2 = bf(P[2], 64), t.e2a = bf(P[2], 128), t.c2 = bf(P[2], 256), t.d2b = bf(P[2], 128), t.d2c = bf(P[2], 128);
+  t.u2 = bf(P[2], 256);
+  t.p3 = bf(P[3], 128), t.e3a = bf(P[3], 256), t.e3b = bf(P[3], 256);
+  t.res = reinterpret_cast<float*>(take(P[0] * 3, 4));
+  if (a) *a = t;
+  return off;
+}
+
+// The forward pass; every step is a layer kernel of nn.hip.
+hipError_t forward(const uint16_t* wts, const uint8_t* rgba, const float* depth, const uint8_t* mask, int n, int h,
+                   int w, const Acts& a, hipStream_t s) {
+  using namespace yoro;
+  hipError_t e = hipSuccess;
+  auto ok = [&](hipError_t r) {
+    if (e == hipSuccess) e = r;
+  };
+  auto conv = [&](int i, const uint16_t* x, int ldx, int lev, uint16_t* y, int ldy) {
+    const Layer L = kLayers[i];
+    ok(nn_conv3x3(x, ldx, n, h >> lev, w >> lev, L.cin, wts + layer_offset(i), L.cout, y, ldy, 0, L.cout, 1, nullptr,
+                  0, s));
+  };
+  ok(nn_input(reinterpret_cast<const uint32_t*>(rgba), depth, mask, (long long)n * h * w, a.x0, s));
+  conv(0, a.x0, 32, 0, a.e0a, 32);
+  conv(1, a.e0a, 32, 0, a.c0 + 32, 64);  // e0b -> the skip half of c0
+  ok(nn_avgpool2(a.c0 + 32, 64, n, h, w, 32, a.p1, 32, s));
+  conv(2, a.p1, 32, 1, a.e1a, 64);
+  conv(3, a.e1a, 64, 1, a.c1 + 64, 128);  // e1b
+  ok(nn_avgpool2(a.c1 + 64, 128, n, h >> 1, w >> 1, 64, a.p2, 64, s));
+  conv(4, a.p2, 64, 2, a.e2a, 128);
+  conv(5, a.e2a, 128, 2, a.c2 + 128, 256);  // e2b
+  ok(nn_avgpool2(a.c2 + 128, 256, n, h >> 2, w >> 2, 128, a.p3, 128, s));
+  conv(6, a.p3, 128, 3, a.e3a, 256);
+  conv(7, a.e3a, 256, 3, a.e3b, 256);
+  ok(nn_upsample2(a.e3b, 256, n, h >> 3, w >> 3, 256, a.u2, 256, s));
+  conv(8, a.u2, 256, 2, a.c2, 256);  // d2a -> the decoder half of c2
+  conv(9, a.c2, 256, 2, a.d2b, 128);
+  conv(10, a.d2b, 128, 2, a.d2c, 128);
+  ok(nn_upsample2(a.d2c, 128, n, h >> 2, w >> 2, 128, a.u1, 128, s));
+  conv(11, a.u1, 128, 1, a.c1, 128);  // d1a
+  conv(12, a.c1, 128, 1, a.d1b, 64);
+  conv(13, a.d1b, 64, 1, a.d1c, 64);
+  ok(nn_upsample2(a.d1c, 64, n, h >> 1, w >> 1, 64, a.u0, 64, s));
+  conv(14, a.u0, 64, 0, a.c0, 64);  // d0a
+  conv(15, a.c0, 64, 0, a.d0b, 32);
+  conv(16, a.d0b, 32, 0, a.d0c, 32);
+  // Head: FP32 residual, the first 3 of its 32 padded outputs, no activation.
+  ok(nn_conv3x3(a.d0c, 32, n, h, w, 32, wts + layer_offset(17), 32, a.res, 3, 1, 3, 0, nullptr, 0, s));
+  return e;
+}
+
+int32_t launched(hipError_t e, const char* who) {
+  if (e != hipSuccess) return model_fail(YORO_ERR_DEVICE, "%s: launch failed: %s", who, hipGetErrorString(e));
+  return YORO_OK;
+}
+
+bool shape_ok(long long n, int h, int w) {
+  return n > 0 && h > 0 && w > 0 && h % 8 == 0 && w % 8 == 0 && n * h * w < (1LL << 31);
+}
+
+size_t crop_input_bytes(long long k, int crop) {
+  const long long px = k * crop * crop;
+  return (((size_t)px * 4 + 255) & ~(size_t)255) * 2 + (((size_t)px + 255) & ~(size_t)255);
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t yoro_model_layout(int32_t* cin_pad, int32_t* cout_pad, int64_t* offset) {
+  for (int i = 0; i < YORO_MODEL_LAYERS; ++i) {
+    if (cin_pad) cin_pad[i] = kLayers[i].cin;
+    if (cout_pad) cout_pad[i] = kLayers[i].cout;
+  }
+  if (offset)
+    for (int i = 0; i <= YORO_MODEL_LAYERS; ++i) offset[i] = layer_offset(i);
+  return YORO_OK;
+}
+
+size_t yoro_model_weights_bytes(void) { return (size_t)layer_offset(YORO_MODEL_LAYERS) * 2; }
+
+int32_t yoro_model_pack(const float* master, void* weights, void* hip_stream) {
+  const char* who = "yoro_model_pack";
+  if (!master || !weights || !al4(master) || !al16(weights))
+    return model_fail(YORO_ERR_INVALID_ARG, "%s: null or misaligned pointer", who);
+  hipError_t e = hipSuccess;
+  for (int i = 0; i < YORO_MODEL_LAYERS && e == hipSuccess; ++i)
+    e = yoro::nn_pack_weights(master + layer_offset(i), kLayers[i].cin, kLayers[i].cout,
+                              static_cast<uint16_t*>(weights) + layer_offset(i), nullptr, (hipStream_t)hip_stream);
+  return launched(e, who);
+}
+
+size_t yoro_model_workspace_bytes(int32_t n, int32_t h, int32_t w) {
+  if (!shape_ok(n, h, w)) return 0;
+  return carve(nullptr, n, h, w, nullptr);
+}
+
+int32_t yoro_model_residual(const void* weights, const uint8_t* rgba, const float* depth, const uint8_t* mask,
+                            int32_t n, int32_t h, int32_t w, float* res, void* workspace, size_t workspace_bytes,
+                            void* hip_stream) {
+  const char* who = "yoro_model_residual";
+  if (!weights || !rgba || !depth || !mask || !res || !workspace)
+    return model_fail(YORO_ERR_INVALID_ARG, "%s: null pointer", who);
+  if (!shape_ok(n, h, w)) return model_fail(YORO_ERR_INVALID_ARG, "%s: bad shape %d x %d x %d", who, n, h, w);
+  if (!al16(weights) || !al4(rgba) || !al4(depth) || !al4(res) || !al16(workspace))
+    return model_fail(YORO_ERR_INVALID_ARG, "%s: misaligned pointer", who);
+  Acts a;
+  if (workspace_bytes < carve(static_cast<char*>(workspace), n, h, w, &a))
+    return model_fail(YORO_ERR_WORKSPACE_TOO_SMALL, "%s: workspace too small", who);
+  a.res = res;
+  return launched(forward(static_cast<const uint16_t*>(weights), rgba, depth, mask, n, h, w, a, (hipStream_t)hip_stream),
+                  who);
+}
+
+int32_t yoro_model_fill(const void* weights, const uint8_t* rgba, const float* depth, const uint8_t* mask, int32_t n,
+                        int32_t h, int32_t w, uint8_t* out, void* workspace, size_t workspace_bytes,
+                        void* hip_stream) {
+  const char* who = "yoro_model_fill";
+  if (!weights || !rgba || !depth || !mask || !out || !workspace)
+    return model_fail(YORO_ERR_INVALID_ARG, "%s: null pointer", who);
+  if (!shape_ok(n, h, w)) return model_fail(YORO_ERR_INVALID_ARG, "%s: bad shape %d x %d x %d", who, n, h, w);
+  if (!al16(weights) || !al4(rgba) || !al4(depth) || !al4(out) || !al16(workspace))
+    return model_fail(YORO_ERR_INVALID_ARG, "%s: misaligned pointer", who);
+  Acts a;
+  if (workspace_bytes < carve(static_cast<char*>(workspace), n, h, w, &a))
+    return model_fail(YORO_ERR_WORKSPACE_TOO_SMALL, "%s: workspace too small", who);
+  hipStream_t s = (hipStream_t)hip_stream;
+  hipError_t e = forward(static_cast<const uint16_t*>(weights), rgba, depth, mask, n, h, w, a, s);
+  if (e == hipSuccess)
+    e = yoro::nn_composite(a.res, reinterpret_cast<const uint32_t*>(rgba), mask, (long long)n * h * w,
+                           reinterpret_cast<uint32_t*>(out), s);
+  return launched(e, who);
+}
+
+size_t yoro_model_tiles_workspace_bytes(int32_t k, int32_t chunk, int32_t tile, int32_t halo) {
+  if (k <= 0 || chunk <= 0 || tile <= 0 || halo < 0 || k > 65535) return 0;
+  const int crop = tile + 2 * halo;
+  if (!shape_ok(chunk < k ? chunk : k, crop, crop)) return 0;
+  return crop_input_bytes(k, crop) + carve(nullptr, chunk < k ? chunk : k, crop, crop, nullptr);
+}
+
+int32_t yoro_model_fill_tiles(const void* weights, const uint8_t* rgba, const float* depth, const uint8_t* mask,
+                              int32_t w, int32_t h, const int32_t* plan, int32_t k, int32_t tile, int32_t halo,
+                              int32_t chunk, uint8_t* out, void* workspace, size_t workspace_bytes,
+                              void* hip_stream) {
+  const char* who = "yoro_model_fill_tiles";
+  if (!weights || !rgba || !depth || !mask || !plan || !out || !workspace)
+    return model_fail(YORO_ERR_INVALID_ARG, "%s: null pointer", who);
+  const int crop = tile + 2 * halo;
+  if (w <= 0 || h <= 0 || k <= 0 || k > 65535 || chunk <= 0 || tile <= 0 || tile % 8 || halo < 0 || halo % 8 ||
+      crop > w || crop > h || w % 8 || h % 8)
+    return model_fail(YORO_ERR_INVALID_ARG, "%s: bad frame %d x %d, k %d, chunk %d, tile %d or halo %d", who, w, h, k,
+                      chunk, tile, halo);
+  if (!al16(weights) || !al4(rgba) || !al4(depth) || !al4(out) || !al4(plan) || !al16(workspace))
+    return model_fail(YORO_ERR_INVALID_ARG, "%s: misaligned pointer", who);
+  const size_t need = yoro_model_tiles_workspace_bytes(k, chunk, tile, halo);
+  if (need == 0) return model_fail(YORO_ERR_INVALID_ARG, "%s: chunk of crops too large", who);
+  if (workspace_bytes < need) return model_fail(YORO_ERR_WORKSPACE_TOO_SMALL, "%s: workspace too small", who);
+  const long long cpx = (long long)crop * crop;
+  char* ws = static_cast<char*>(workspace);
+  uint32_t* crgba = reinterpret_cast<uint32_t*>(ws);
+  float* cdepth = reinterpret_cast<float*>(ws + (((size_t)k * cpx * 4 + 255) & ~(size_t)255));
+  uint8_t* cmask = reinterpret_cast<uint8_t*>(ws + 2 * (((size_t)k * cpx * 4 + 255) & ~(size_t)255));
+  const int cmax = chunk < k ? chunk : k;
+  Acts a;
+  carve(ws + crop_input_bytes(k, crop), cmax, crop, crop, &a);
+  hipStream_t s = (hipStream_t)hip_stream;
+  hipError_t e = yoro::nn_gather_crops(reinterpret_cast<const uint32_t*>(rgba), depth, mask, w, plan, k, crop, crgba,
+                                       cdepth, cmask, s);
+  for (int c0 = 0; c0 < k && e == hipSuccess; c0 += cmax) {
+    const int kc = k - c0 < cmax ? k - c0 : cmax;
+    e = forward(static_cast<const uint16_t*>(weights), reinterpret_cast<const uint8_t*>(crgba + c0 * cpx),
+                cdepth + c0 * cpx, cmask + c0 * cpx, kc, crop, crop, a, s);
+    if (e == hipSuccess)
+      e = yoro::nn_composite_tiles(a.res, plan + 4 * c0, kc, crop, tile, w, h, reinterpret_cast<const uint32_t*>(rgba),
+                                   mask, reinterpret_cast<uint32_t*>(out), s);
+  }
+  return launched(e, who);
+}
+
+}  // extern "C"

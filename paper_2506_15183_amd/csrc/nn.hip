@@ -219,7 +219,7 @@ __global__ void pack_weights_kernel(const float* __restrict__ w, int cin, int co
     const int co = rem / cin, ci = rem % cin;
     const uint16_t h = to_bf16(w[i]);
     wf[i] = h;
-    wb[((long long)(8 - t) * cin + ci) * cout + co] = h;
+    if (wb) wb[((long long)(8 - t) * cin + ci) * cout + co] = h;
   }
 }
 
@@ -429,6 +429,73 @@ __global__ void adamw_kernel(float* __restrict__ w, float* __restrict__ m, float
   }
 }
 
+// ------------------------------------------------------------ hole tiles --
+// counts[ty * ntx + tx] = number of pixels with mask != 0 in the tile x tile
+// block at (tx, ty) (clipped to the frame).
+__global__ __launch_bounds__(256) void tile_holes_kernel(const uint8_t* __restrict__ mask, int w, int h, int tile,
+                                                         int ntx, uint32_t* __restrict__ counts) {
+  __shared__ uint32_t part[4];
+  const int tx = blockIdx.x % ntx, ty = blockIdx.x / ntx;
+  const int x0 = tx * tile, y0 = ty * tile;
+  const int x1 = min(x0 + tile, w), y1 = min(y0 + tile, h);
+  uint32_t c = 0;
+  for (int y = y0 + (int)threadIdx.y; y < y1; y += blockDim.y)
+    for (int x = x0 + (int)threadIdx.x; x < x1; x += blockDim.x) c += mask[(long long)y * w + x] != 0;
+  // blockDim = (64, 4): one wave per threadIdx.y.
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o);
+  if (threadIdx.x == 0) part[threadIdx.y] = c;
+  __syncthreads();
+  if (threadIdx.x == 0 && threadIdx.y == 0) counts[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
+}
+
+// plan[4k .. 4k+3] = (crop x, crop y, tile x, tile y) of crop k.  Copies crop k
+// (crop x crop pixels) of a frame into the crop batch.
+__global__ void gather_crops_kernel(const uint32_t* __restrict__ rgba, const float* __restrict__ depth,
+                                    const uint8_t* __restrict__ mask, int w, const int* __restrict__ plan, int crop,
+                                    uint32_t* __restrict__ crgba, float* __restrict__ cdepth,
+                                    uint8_t* __restrict__ cmask) {
+  const int k = blockIdx.y;
+  const int ox = plan[4 * k], oy = plan[4 * k + 1];
+  const long long n = (long long)crop * crop;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const int cy = (int)(i / crop), cx = (int)(i % crop);
+    const long long src = (long long)(oy + cy) * w + (ox + cx);
+    const long long dst = (long long)k * n + i;
+    crgba[dst] = rgba[src];
+    cdepth[dst] = depth[src];
+    cmask[dst] = mask[src];
+  }
+}
+
+// Writes the tile part of each crop's learned composite into the frame: hole
+// pixels of tile k become clamp(rint(255 * (plain/255 + res))), alpha kept;
+// other pixels are left as they are.
+__global__ void composite_tiles_kernel(const float* __restrict__ res, const int* __restrict__ plan, int crop, int tile,
+                                       int w, int h, const uint32_t* __restrict__ rgba,
+                                       const uint8_t* __restrict__ mask, uint32_t* __restrict__ out) {
+  const int k = blockIdx.y;
+  const int ox = plan[4 * k], oy = plan[4 * k + 1];
+  const int tx = plan[4 * k + 2], ty = plan[4 * k + 3];
+  const long long n = (long long)tile * tile;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const int x = tx + (int)(i % tile), y = ty + (int)(i / tile);
+    if (x >= w || y >= h) continue;
+    const long long p = (long long)y * w + x;
+    if (mask[p] == 0) continue;
+    const long long q = ((long long)k * crop + (y - oy)) * crop + (x - ox);
+    const uint32_t c = rgba[p];
+    uint32_t o = c & 0xFF000000u;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+      const float pred = (float)((c >> (8 * ch)) & 255u) / 255.0f + res[q * 3 + ch];
+      float v = rintf(255.0f * pred);
+      v = v < 0.0f ? 0.0f : (v > 255.0f ? 255.0f : v);
+      o |= (uint32_t)v << (8 * ch);
+    }
+    out[p] = o;
+  }
+}
+
 int grid_1d(long long n, int threads) {
   const long long g = (n + threads - 1) / threads;
   return (int)(g < 1 ? 1 : (g > 65536 ? 65536 : g));
@@ -540,6 +607,29 @@ hipError_t nn_adamw(float* w, float* m, float* v, const float* g, long long n, f
                     float wd, int step, hipStream_t s) {
   const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
   hipLaunchKernelGGL(adamw_kernel, dim3(grid_1d(n, 256)), dim3(256), 0, s, w, m, v, g, n, lr, b1, b2, eps, wd, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t nn_tile_holes(const uint8_t* mask, int w, int h, int tile, uint32_t* counts, hipStream_t s) {
+  const int ntx = (w + tile - 1) / tile, nty = (h + tile - 1) / tile;
+  hipLaunchKernelGGL(tile_holes_kernel, dim3(ntx * nty), dim3(64, 4), 0, s, mask, w, h, tile, ntx, counts);
+  return hipGetLastError();
+}
+
+hipError_t nn_gather_crops(const uint32_t* rgba, const float* depth, const uint8_t* mask, int w, const int* plan, int k,
+                           int crop, uint32_t* crgba, float* cdepth, uint8_t* cmask, hipStream_t s) {
+  const long long n = (long long)crop * crop;
+  const long long blocks = (n + 255) / 256;
+  hipLaunchKernelGGL(gather_crops_kernel, dim3((unsigned)(blocks < 1024 ? blocks : 1024), k), dim3(256), 0, s, rgba,
+                     depth, mask, w, plan, crop, crgba, cdepth, cmask);
+  return hipGetLastError();
+}
+
+hipError_t nn_composite_tiles(const float* res, const int* plan, int k, int crop, int tile, int w, int h,
+                              const uint32_t* rgba, const uint8_t* mask, uint32_t* out, hipStream_t s) {
+  const long long n = (long long)tile * tile;
+  hipLaunchKernelGGL(composite_tiles_kernel, dim3((unsigned)((n + 255) / 256), k), dim3(256), 0, s, res, plan, crop,
+                     tile, w, h, rgba, mask, out);
   return hipGetLastError();
 }
 

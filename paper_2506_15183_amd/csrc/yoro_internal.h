@@ -105,6 +105,11 @@ hipError_t nn_composite(const float* res, const uint32_t* rgba, const uint8_t* m
                         hipStream_t s);
 hipError_t nn_adamw(float* w, float* m, float* v, const float* g, long long n, float lr, float b1, float b2, float eps,
                     float wd, int step, hipStream_t s);
+hipError_t nn_tile_holes(const uint8_t* mask, int w, int h, int tile, uint32_t* counts, hipStream_t s);
+hipError_t nn_gather_crops(const uint32_t* rgba, const float* depth, const uint8_t* mask, int w, const int* plan, int k,
+                           int crop, uint32_t* crgba, float* cdepth, uint8_t* cmask, hipStream_t s);
+hipError_t nn_composite_tiles(const float* res, const int* plan, int k, int crop, int tile, int w, int h,
+                              const uint32_t* rgba, const uint8_t* mask, uint32_t* out, hipStream_t s);
 
 // Occupancy-derived workgroups per CU for the row kernels.
 int warp_blocks_per_cu(int max_width, bool batch);

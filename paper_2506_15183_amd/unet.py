@@ -19,6 +19,7 @@ every convolution is a multiple of 32 wide for the matrix cores.
 """
 from __future__ import annotations
 
+import copy
 import ctypes
 
 import numpy as np
@@ -64,6 +65,14 @@ def nnlib():
             "yoro_nn_l1_grad": [vp, vp, vp, vp, i64, vp, vp, vp, vp],
             "yoro_nn_composite": [vp, vp, vp, i64, vp, vp],
             "yoro_nn_adamw": [vp, vp, vp, vp, i64, f32, f32, f32, f32, f32, i32, vp],
+            "yoro_nn_tile_holes": [vp, i32, i32, i32, vp, vp],
+            "yoro_nn_gather_crops": [vp, vp, vp, i32, i32, vp, i32, i32, vp, vp, vp, vp],
+            "yoro_nn_composite_tiles": [vp, vp, i32, i32, i32, vp, vp, i32, i32, vp, vp],
+            "yoro_model_layout": [vp, vp, vp],
+            "yoro_model_pack": [vp, vp, vp],
+            "yoro_model_residual": [vp, vp, vp, vp, i32, i32, i32, vp, vp, sz, vp],
+            "yoro_model_fill": [vp, vp, vp, vp, i32, i32, i32, vp, vp, sz, vp],
+            "yoro_model_fill_tiles": [vp, vp, vp, vp, i32, i32, vp, i32, i32, i32, i32, vp, vp, sz, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -71,8 +80,56 @@ def nnlib():
             fn.restype = i32
         L.yoro_nn_conv3x3_wgrad_workspace.argtypes = [i32, i32, i32, i32, i32]
         L.yoro_nn_conv3x3_wgrad_workspace.restype = sz
+        L.yoro_model_weights_bytes.argtypes = []
+        L.yoro_model_weights_bytes.restype = sz
+        L.yoro_model_workspace_bytes.argtypes = [i32, i32, i32]
+        L.yoro_model_workspace_bytes.restype = sz
+        L.yoro_model_tiles_workspace_bytes.argtypes = [i32, i32, i32, i32]
+        L.yoro_model_tiles_workspace_bytes.restype = sz
         _nn = L
     return _nn
+
+
+def boundary_reach() -> int:
+    """How far (level-0 pixels) the zero padding at a crop's edge reaches into
+    the network's output: outputs farther than this from every edge of a crop
+    that is not a frame edge equal those of the whole frame, provided the crop
+    sits on the 8-pixel grid of the three 2x2 pools.  Each 3x3 convolution
+    adds one pixel, a pool halves (rounding up), an upsample doubles, and a
+    concatenation takes the larger reach of its two inputs."""
+    r, skips = 0, []
+    for level in range(4):
+        r += 2                      # two convolutions
+        if level < 3:
+            skips.append(r)
+            r = -(-r // 2)          # 2x2 average pool
+    for level in (2, 1, 0):
+        r = 2 * r + 1               # upsample, then the first decoder convolution
+        r = max(r, skips[level])    # concatenation with the encoder's output
+        r += 2                      # two more convolutions
+    return r + 1                    # head
+
+
+TILE, HALO = 128, 64                # crop = 256 x 256, the training window size
+
+
+def tile_plan(counts, h: int, w: int, tile: int = TILE, halo: int = HALO):
+    """Crops for the tile x tile blocks of an h x w frame whose hole count is
+    nonzero: int32 [k, 4] rows (crop x, crop y, block x, block y).  Each crop
+    (tile + 2 halo square) is placed on the frame, shifted inward at the
+    frame's edges, so every crop edge is a frame edge or at least `halo`
+    pixels from its block."""
+    crop = tile + 2 * halo
+    if crop > h or crop > w:
+        raise ValueError(f"frame {w}x{h} smaller than a {crop}-pixel crop")
+    if tile % 8 or halo % 8 or h % 8 or w % 8:
+        raise ValueError("tile, halo and the frame size must be multiples of 8")
+    ntx = (w + tile - 1) // tile
+    idx = np.flatnonzero(np.asarray(counts).reshape(-1))
+    ty, tx = (idx // ntx) * tile, (idx % ntx) * tile
+    ox = np.clip(tx - halo, 0, w - crop)
+    oy = np.clip(ty - halo, 0, h - crop)
+    return np.stack([ox, oy, tx, ty], 1).astype(np.int32).reshape(-1, 4)
 
 
 def _p(t, offset: int = 0):
@@ -123,6 +180,17 @@ class Buffers:
                                      (3, (256, 256))]:
                 ws = max(ws, L.yoro_nn_conv3x3_wgrad_workspace(n, h >> lev, w >> lev, cin, cout))
             self.wgrad_ws = torch.empty(ws // 4 + 4, dtype=torch.float32, device=device)
+
+    def first(self, n):
+        """The same buffers, used for the first n images only."""
+        if n == self.n:
+            return self
+        if not 0 < n <= self.n:
+            raise ValueError(f"{n} images do not fit buffers for {self.n}")
+        c = copy.copy(self)
+        c.n = n
+        c.P = [n * (self.h >> lev) * (self.w >> lev) for lev in range(4)]
+        return c
 
 
 class UNet:
@@ -313,6 +381,51 @@ class UNet:
         if out is None:
             out = torch.empty_like(rgba)
         return self.composite(rgba, mask, b, out, stream)
+
+    def tile_holes(self, mask, tile: int = TILE, stream=None):
+        """Device u32 hole count per tile x tile block of one frame's mask."""
+        h, w = mask.shape
+        counts = torch.empty(((w + tile - 1) // tile) * ((h + tile - 1) // tile), dtype=torch.int32,
+                             device=mask.device)
+        _ok(nnlib().yoro_nn_tile_holes(_p(mask), w, h, tile, _p(counts), yoro._stream(stream)))
+        return counts
+
+    def fill_tiles(self, rgba, depth, mask, out=None, tile: int = TILE, halo: int = HALO, chunk: int = 32,
+                   stream=None):
+        """Learned fill of one plain-filled frame (rgba [h, w, 4], depth and
+        mask [h, w]) that runs the network only on tile x tile blocks with a
+        hole, each inside a crop reaching `halo` pixels around it
+        (yoro_model_fill_tiles).  With halo >= boundary_reach() the result
+        equals fill() on the whole frame.  Reads the block hole counts back to
+        the host to plan the crops.  Returns (out, crops run)."""
+        h, w = depth.shape
+        if out is None:
+            out = torch.empty_like(rgba)
+        if out.data_ptr() != rgba.data_ptr():
+            out.copy_(rgba)
+        plan = tile_plan(self.tile_holes(mask, tile, stream).cpu().numpy(), h, w, tile, halo)
+        k = plan.shape[0]
+        if k == 0:
+            return out, 0
+        L = nnlib()
+        plan_d = torch.from_numpy(plan).to(self.device)
+        nbytes = L.yoro_model_tiles_workspace_bytes(k, chunk, tile, halo)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        _ok(L.yoro_model_fill_tiles(_p(self.wf), _p(rgba), _p(depth), _p(mask), w, h, _p(plan_d), k, tile, halo, chunk,
+                                    _p(out), _p(ws), nbytes, yoro._stream(stream)))
+        return out, k
+
+    def fill_native(self, rgba, depth, mask, out=None, stream=None):
+        """fill() through the library's own forward sequence (yoro_model_fill)."""
+        n, h, w = depth.shape
+        L = nnlib()
+        if out is None:
+            out = torch.empty_like(rgba)
+        nbytes = L.yoro_model_workspace_bytes(n, h, w)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        _ok(L.yoro_model_fill(_p(self.wf), _p(rgba), _p(depth), _p(mask), n, h, w, _p(out), _p(ws), nbytes,
+                              yoro._stream(stream)))
+        return out
 
     # ----------------------------------------------------- checkpointing --
     def state_dict(self):
