@@ -1,0 +1,351 @@
+// The real-time serving loop of include/yoro_serve.h: continuous batching of
+// arriving frames onto the persistent batched warp, completion tracking with
+// events, and the optional hole-tile learned refinement with its fallback.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdint>
+#include <deque>
+#include <vector>
+
+#include "yoro.h"
+#include "yoro_internal.h"
+#include "yoro_model.h"
+#include "yoro_serve.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+int32_t serve_fail(int32_t status, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  yoro::set_last_error(buf);
+  return status;
+}
+
+size_t up256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+int tiles_of(int w, int h, int tile) { return tile > 0 ? ((w + tile - 1) / tile) * ((h + tile - 1) / tile) : 0; }
+
+bool learned(const yoro_serve_options* o) { return o->policy == YORO_SERVE_LEARNED; }
+
+struct Layout {
+  size_t table;   // per-slot job table bytes
+  size_t counts;  // per-slot tile counts bytes (device and host)
+  size_t slot;    // per-slot device bytes
+  size_t plan;    // plan bytes (device and host)
+  int tiles;      // tiles of the largest frame
+};
+
+Layout layout(const yoro_serve_options* o, int max_w, int max_h) {
+  Layout L{};
+  L.table = up256(yoro_stereo_batch_workspace_bytes(o->max_batch));
+  L.tiles = learned(o) ? tiles_of(max_w, max_h, o->tile) : 0;
+  L.counts = up256((size_t)o->max_batch * L.tiles * 4);
+  L.slot = L.table + L.counts;
+  L.plan = up256((size_t)L.tiles * 16);
+  return L;
+}
+
+bool options_ok(const yoro_serve_options* o) {
+  if (!o || o->max_batch < 1 || o->max_batch > YORO_MAX_BATCH_JOBS || o->max_in_flight < 1 || o->max_in_flight > 64)
+    return false;
+  if (o->policy != YORO_SERVE_PLAIN && o->policy != YORO_SERVE_LEARNED) return false;
+  if (learned(o) && (o->tile <= 0 || o->tile % 8 || o->halo < 0 || o->halo % 8 || o->chunk < 1 ||
+                     !o->model_weights || !o->learned_workspace || !o->learned_stream ||
+                     !(o->learned_max_hole_fraction >= 0.0f)))
+    return false;
+  return true;
+}
+
+// In-flight plain batch.
+struct Batch {
+  int slot;
+  std::vector<int64_t> frames;
+};
+
+}  // namespace
+
+extern "C" {
+
+size_t yoro_serve_workspace_bytes(const yoro_serve_options* options, int32_t max_w, int32_t max_h) {
+  if (!options_ok(options) || max_w <= 0 || max_h <= 0) return 0;
+  const Layout L = layout(options, max_w, max_h);
+  return L.slot * options->max_in_flight + L.plan;
+}
+
+size_t yoro_serve_host_bytes(const yoro_serve_options* options, int32_t max_w, int32_t max_h) {
+  if (!options_ok(options) || max_w <= 0 || max_h <= 0) return 0;
+  const Layout L = layout(options, max_w, max_h);
+  return L.counts * options->max_in_flight + L.plan;
+}
+
+int32_t yoro_serve_admit(const int64_t* bytes, int32_t n, int64_t budget, int64_t reserved, int32_t* admitted) {
+  if (!bytes || !admitted || n < 0 || budget < 0 || reserved < 0) return -1;
+  int64_t left = budget - reserved;
+  int32_t count = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    const bool fits = bytes[i] >= 0 && bytes[i] <= left;
+    admitted[i] = fits ? 1 : 0;
+    if (fits) {
+      left -= bytes[i];
+      ++count;
+    }
+  }
+  return count;
+}
+
+int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, const yoro_serve_source* sources,
+                       int32_t n_sources, const yoro_serve_arrival* arrivals, int64_t n_arrivals,
+                       const yoro_serve_options* options, void* workspace, size_t workspace_bytes,
+                       void* host_staging, size_t host_bytes, void* hip_stream, yoro_serve_result* results) {
+  const char* who = "yoro_serve_run";
+  if (!headsets || n_headsets <= 0 || !sources || n_sources <= 0 || (!arrivals && n_arrivals) || n_arrivals < 0 ||
+      !results || !workspace || !host_staging)
+    return serve_fail(YORO_ERR_INVALID_ARG, "%s: null pointer or empty input", who);
+  if (!options_ok(options)) return serve_fail(YORO_ERR_INVALID_ARG, "%s: bad options", who);
+  const yoro_serve_options& O = *options;
+  const bool L_on = learned(&O);
+  int max_w = 0, max_h = 0;
+  for (int i = 0; i < n_headsets; ++i) {
+    const yoro_serve_headset& H = headsets[i];
+    if (H.n_sources < 1) return serve_fail(YORO_ERR_INVALID_ARG, "%s: headset %d: empty pool", who, i);
+    if (!H.admitted) continue;  // its arrivals are only marked rejected
+    if (H.n_outputs < 1 || H.n_outputs > YORO_SERVE_MAX_OUTPUTS || H.first_source < 0 ||
+        H.first_source + H.n_sources > n_sources || H.width <= 0 || H.height <= 0)
+      return serve_fail(YORO_ERR_INVALID_ARG, "%s: headset %d: bad pool or outputs", who, i);
+    for (int o = 0; o < H.n_outputs; ++o)
+      if (!H.dst_rgba[o] || (L_on && (!H.dst_mask[o] || !H.dst_depth[o])))
+        return serve_fail(YORO_ERR_INVALID_ARG, "%s: headset %d: missing output %d", who, i, o);
+    if (L_on) {
+      const int crop = O.tile + 2 * O.halo;
+      if (H.width % 8 || H.height % 8 || H.width < crop || H.height < crop)
+        return serve_fail(YORO_ERR_INVALID_ARG, "%s: headset %d: %d x %d does not take %d-pixel crops", who, i,
+                          H.width, H.height, crop);
+    }
+    max_w = H.width > max_w ? H.width : max_w;
+    max_h = H.height > max_h ? H.height : max_h;
+  }
+  for (int64_t k = 0; k < n_arrivals; ++k) {
+    const yoro_serve_arrival& A = arrivals[k];
+    if (A.headset < 0 || A.headset >= n_headsets || A.source < 0 || A.source >= headsets[A.headset].n_sources ||
+        (k > 0 && A.t_ns < arrivals[k - 1].t_ns))
+      return serve_fail(YORO_ERR_INVALID_ARG, "%s: arrival %lld: bad headset, source or order", who, (long long)k);
+  }
+  const Layout Lay = layout(&O, max_w, max_h);
+  if (workspace_bytes < yoro_serve_workspace_bytes(&O, max_w, max_h) ||
+      host_bytes < yoro_serve_host_bytes(&O, max_w, max_h))
+    return serve_fail(YORO_ERR_WORKSPACE_TOO_SMALL, "%s: workspace or host staging too small", who);
+  if (L_on && O.learned_workspace_bytes < yoro_model_tiles_workspace_bytes(Lay.tiles, O.chunk, O.tile, O.halo))
+    return serve_fail(YORO_ERR_WORKSPACE_TOO_SMALL, "%s: learned workspace too small", who);
+
+  hipStream_t s = (hipStream_t)hip_stream;
+  hipStream_t ls = (hipStream_t)O.learned_stream;
+  char* ws = static_cast<char*>(workspace);
+  char* hs = static_cast<char*>(host_staging);
+  int32_t* plan_dev = reinterpret_cast<int32_t*>(ws + Lay.slot * O.max_in_flight);
+  int32_t* plan_host = reinterpret_cast<int32_t*>(hs + Lay.counts * O.max_in_flight);
+
+  std::vector<hipEvent_t> ev(O.max_in_flight, nullptr);
+  hipEvent_t lev = nullptr;
+  hipError_t he = hipSuccess;
+  for (int i = 0; i < O.max_in_flight && he == hipSuccess; ++i) he = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
+  if (he == hipSuccess) he = hipEventCreateWithFlags(&lev, hipEventDisableTiming);
+
+  std::vector<int> next_out(n_headsets, 0);
+  // Last arrival written into each headset's output set: a finished frame is
+  // refined only while its output still holds it.
+  std::vector<int64_t> last_in(n_headsets * YORO_SERVE_MAX_OUTPUTS, -1);
+  std::vector<int> out_of(n_arrivals, 0);
+  std::vector<int> free_slots;
+  for (int i = O.max_in_flight - 1; i >= 0; --i) free_slots.push_back(i);
+  std::deque<int64_t> pending;
+  std::deque<Batch> inflight;
+  std::vector<int64_t> in_batch(n_headsets, -1);
+  int64_t batch_no = 0;
+  std::vector<yoro_job> jobs;
+  jobs.reserve(O.max_batch);
+  bool l_active = false;
+  int64_t l_frame = -1;
+  int l_headset = -1, l_out = -1;
+  int32_t status = he == hipSuccess ? YORO_OK : serve_fail(YORO_ERR_DEVICE, "%s: event: %s", who, hipGetErrorString(he));
+
+  const Clock::time_point t0 = Clock::now();
+  auto now_ns = [&]() { return (int64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(Clock::now() - t0).count(); };
+  int64_t next = 0;
+
+  // Learned stage for frame k whose counts are in counts_host; returns its path.
+  auto refine = [&](int64_t k, const uint32_t* counts) -> int32_t {
+    const yoro_serve_headset& H = headsets[arrivals[k].headset];
+    const int nt = tiles_of(H.width, H.height, O.tile);
+    int64_t holes = 0;
+    for (int t = 0; t < nt; ++t) holes += counts[t];
+    results[k].holes = holes;
+    if ((double)holes > (double)O.learned_max_hole_fraction * (double)H.width * H.height) return YORO_PATH_FALLBACK;
+    if (holes == 0) return YORO_PATH_LEARNED;  // nothing to refine
+    if (l_active || last_in[arrivals[k].headset * YORO_SERVE_MAX_OUTPUTS + out_of[k]] != k) return YORO_PATH_BUSY;
+    const int crop = O.tile + 2 * O.halo, ntx = (H.width + O.tile - 1) / O.tile;
+    int kc = 0;
+    for (int t = 0; t < nt; ++t) {
+      if (!counts[t]) continue;
+      const int tx = (t % ntx) * O.tile, ty = (t / ntx) * O.tile;
+      int ox = tx - O.halo, oy = ty - O.halo;
+      ox = ox < 0 ? 0 : (ox > H.width - crop ? H.width - crop : ox);
+      oy = oy < 0 ? 0 : (oy > H.height - crop ? H.height - crop : oy);
+      plan_host[4 * kc] = ox, plan_host[4 * kc + 1] = oy, plan_host[4 * kc + 2] = tx, plan_host[4 * kc + 3] = ty;
+      ++kc;
+    }
+    const int o = out_of[k];
+    hipError_t e = hipMemcpyAsync(plan_dev, plan_host, (size_t)kc * 16, hipMemcpyHostToDevice, ls);
+    if (e != hipSuccess) {
+      status = serve_fail(YORO_ERR_DEVICE, "%s: plan upload: %s", who, hipGetErrorString(e));
+      return -1;
+    }
+    const int32_t st = yoro_model_fill_tiles(O.model_weights, H.dst_rgba[o], H.dst_depth[o], H.dst_mask[o], H.width,
+                                             H.height, plan_dev, kc, O.tile, O.halo, O.chunk, H.dst_rgba[o],
+                                             O.learned_workspace, O.learned_workspace_bytes, ls);
+    if (st != YORO_OK) {
+      status = st;
+      return -1;
+    }
+    e = hipEventRecord(lev, ls);
+    if (e != hipSuccess) {
+      status = serve_fail(YORO_ERR_DEVICE, "%s: event record: %s", who, hipGetErrorString(e));
+      return -1;
+    }
+    l_active = true, l_frame = k, l_headset = arrivals[k].headset, l_out = o;
+    return YORO_PATH_LEARNED;
+  };
+
+  while (status == YORO_OK) {
+    // Arrivals that are due.
+    const int64_t t = now_ns();
+    while (next < n_arrivals && arrivals[next].t_ns <= t) {
+      yoro_serve_result& R = results[next];
+      R.launch_ns = -1, R.done_ns = -1, R.batch_frames = 0, R.holes = -1;
+      if (!headsets[arrivals[next].headset].admitted) {
+        R.path = YORO_PATH_REJECTED;
+      } else {
+        R.path = YORO_PATH_PLAIN;
+        pending.push_back(next);
+      }
+      ++next;
+    }
+    // Completed batches (one stream: they finish in order).
+    while (!inflight.empty() && status == YORO_OK) {
+      Batch& B = inflight.front();
+      const hipError_t q = hipEventQuery(ev[B.slot]);
+      if (q == hipErrorNotReady) break;
+      if (q != hipSuccess) {
+        status = serve_fail(YORO_ERR_DEVICE, "%s: batch: %s", who, hipGetErrorString(q));
+        break;
+      }
+      const int64_t tn = now_ns();
+      const uint32_t* counts = reinterpret_cast<const uint32_t*>(hs + Lay.counts * B.slot);
+      for (size_t i = 0; i < B.frames.size(); ++i) {
+        const int64_t k = B.frames[i];
+        if (!L_on) {
+          results[k].path = YORO_PATH_PLAIN, results[k].done_ns = tn;
+          continue;
+        }
+        const int32_t p = refine(k, counts + i * Lay.tiles);
+        if (p < 0) break;
+        results[k].path = p;
+        if (!(p == YORO_PATH_LEARNED && l_active && l_frame == k)) results[k].done_ns = tn;
+      }
+      free_slots.push_back(B.slot);
+      inflight.pop_front();
+    }
+    // The refinement in flight.
+    if (l_active && status == YORO_OK) {
+      const hipError_t q = hipEventQuery(lev);
+      if (q == hipSuccess) {
+        results[l_frame].done_ns = now_ns();
+        l_active = false;
+      } else if (q != hipErrorNotReady) {
+        status = serve_fail(YORO_ERR_DEVICE, "%s: refinement: %s", who, hipGetErrorString(q));
+      }
+    }
+    // Launch what has arrived.
+    while (status == YORO_OK && !pending.empty() && !free_slots.empty()) {
+      Batch B;
+      B.slot = free_slots.back();
+      free_slots.pop_back();
+      jobs.clear();
+      bool wait_learned = false;
+      // At most one frame per headset per batch (its outputs rotate, so two
+      // would collide); the others keep their place in the queue.
+      std::deque<int64_t> later;
+      while (!pending.empty() && (int)jobs.size() < O.max_batch) {
+        const int64_t k = pending.front();
+        pending.pop_front();
+        const yoro_serve_arrival& A = arrivals[k];
+        if (in_batch[A.headset] == batch_no) {
+          later.push_back(k);
+          continue;
+        }
+        in_batch[A.headset] = batch_no;
+        const yoro_serve_headset& H = headsets[A.headset];
+        const yoro_serve_source& S = sources[H.first_source + A.source];
+        const int o = next_out[A.headset];
+        next_out[A.headset] = (o + 1) % H.n_outputs;
+        out_of[k] = o;
+        last_in[A.headset * YORO_SERVE_MAX_OUTPUTS + o] = k;
+        if (l_active && A.headset == l_headset && o == l_out) wait_learned = true;
+        yoro_job j;
+        j.src_rgba = S.rgba, j.src_depth = S.depth;
+        j.dst_rgba = H.dst_rgba[o], j.dst_depth = H.dst_depth[o], j.dst_mask = H.dst_mask[o];
+        j.width = H.width, j.height = H.height, j.baseline_m = H.baseline_m, j.focal_px = H.focal_px;
+        j.target_eye = H.target_eye, j.fill_mode = YORO_FILL_NEAREST_BG;
+        jobs.push_back(j);
+        B.frames.push_back(k);
+      }
+      while (!later.empty()) {
+        pending.push_front(later.back());
+        later.pop_back();
+      }
+      ++batch_no;
+      hipError_t e = wait_learned ? hipStreamWaitEvent(s, lev, 0) : hipSuccess;
+      if (e != hipSuccess) {
+        status = serve_fail(YORO_ERR_DEVICE, "%s: wait: %s", who, hipGetErrorString(e));
+        break;
+      }
+      const int32_t st = yoro_stereo_batch(jobs.data(), (int32_t)jobs.size(), ws + Lay.slot * B.slot, Lay.table, s);
+      if (st != YORO_OK) {
+        status = st;
+        break;
+      }
+      if (L_on) {
+        uint32_t* cd = reinterpret_cast<uint32_t*>(ws + Lay.slot * B.slot + Lay.table);
+        for (size_t i = 0; i < jobs.size() && e == hipSuccess; ++i)
+          e = yoro::nn_tile_holes(jobs[i].dst_mask, jobs[i].width, jobs[i].height, O.tile, cd + i * Lay.tiles, s);
+        if (e == hipSuccess)
+          e = hipMemcpyAsync(hs + Lay.counts * B.slot, cd, jobs.size() * Lay.tiles * 4, hipMemcpyDeviceToHost, s);
+      }
+      if (e == hipSuccess) e = hipEventRecord(ev[B.slot], s);
+      if (e != hipSuccess) {
+        status = serve_fail(YORO_ERR_DEVICE, "%s: batch launch: %s", who, hipGetErrorString(e));
+        break;
+      }
+      const int64_t tl = now_ns();
+      for (int64_t k : B.frames) results[k].launch_ns = tl, results[k].batch_frames = (int32_t)B.frames.size();
+      inflight.push_back(std::move(B));
+    }
+    if (next == n_arrivals && pending.empty() && inflight.empty() && !l_active) break;
+  }
+  // Drain whatever is queued (after an error too) before the events go away.
+  (void)hipStreamSynchronize(s);
+  if (L_on) (void)hipStreamSynchronize(ls);
+  for (hipEvent_t e : ev)
+    if (e) (void)hipEventDestroy(e);
+  if (lev) (void)hipEventDestroy(lev);
+  return status;
+}
+
+}  // extern "C"

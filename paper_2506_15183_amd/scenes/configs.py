@@ -149,3 +149,48 @@ def render_frames(specs, nthreads: int = 0):
 
 def as_float32(x) -> np.float32:
     return np.float32(x)
+
+
+# ------------------------------------------------------------- serving --
+SERVE_SIZES = ((1440, 1600), (1832, 1920), (2160, 2160))
+SERVE_RATES_HZ = (72.0, 90.0, 120.0)
+
+
+@dataclass
+class HeadsetSpec:
+    index: int
+    rate_hz: float
+    width: int
+    height: int
+    target_eye: int  # the eye to produce; the headset renders the other (its dominant eye)
+    baseline_m: float
+    focal_px: float
+    phase_s: float   # first frame time, U[0, 1 / rate)
+
+
+def config5_headsets(n: int = 32, seed: int = 0) -> list[HeadsetSpec]:
+    """n headsets with rates and resolutions balanced over their three values
+    (seeded assignment), a seeded dominant eye, B ~ U[0.055, 0.072] m and
+    f ~ U[600, 1100] px."""
+    rng = np.random.default_rng(raycast.hash64(0x5345_5256, seed) & 0xFFFF_FFFF)
+    rates = rng.permutation(np.arange(n) % len(SERVE_RATES_HZ))
+    sizes = rng.permutation(np.arange(n) % len(SERVE_SIZES))
+    out = []
+    for i in range(n):
+        u = raycast.uniforms(frame_seed(5, 3_000_000 + seed * 4096 + i), 4)
+        r = SERVE_RATES_HZ[int(rates[i])]
+        w, h = SERVE_SIZES[int(sizes[i])]
+        out.append(HeadsetSpec(i, r, w, h, TARGET_RIGHT if u[0] < 0.5 else TARGET_LEFT,
+                               0.055 + (0.072 - 0.055) * float(u[1]), 600.0 + (1100.0 - 600.0) * float(u[2]),
+                               float(u[3]) / r))
+    return out
+
+
+def config5_pool_frame(width: int, height: int, target_eye: int, slot: int) -> FrameSpec:
+    """Pool frame `slot` for headsets of one resolution and eye: a scene of
+    U{100..300} objects, depth log-uniform on [0.3, 50] m, checker as config 2,
+    rendered with B = 0.063 m and f = 900 px."""
+    key = (SERVE_SIZES.index((width, height)) * 2 + target_eye) * 1024 + slot
+    u = raycast.uniforms(frame_seed(5, 4_000_000 + key), 1)
+    n = 100 + int(u[0] * 201)
+    return FrameSpec(width, height, 0.063, 900.0, target_eye, n, 0.3, 50.0, True, (4, 32), frame_seed(5, key))

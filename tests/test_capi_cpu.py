@@ -31,8 +31,14 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
     assert set(header_functions()) == set(yoro.EXPORTS)
     assert yoro.version() == 1
-    for name in header_functions("yoro_nn.h"):
-        assert hasattr(lib, name), name
+    for header in ("yoro_nn.h", "yoro_model.h", "yoro_serve.h"):
+        names = header_functions(header)
+        assert names, header
+        for name in names:
+            assert hasattr(lib, name), name
+    from paper_2506_15183_amd import serve
+
+    assert set(header_functions("yoro_serve.h")) == set(serve.EXPORTS)
 
 
 def test_nn_host_validation_rejects_without_launching():
