@@ -6,7 +6,12 @@ VR resolutions (16 each of 1024x1024, 1440x1600, 1832x1920, 2160x2160;
 184,569,856 target pixels), all resident in HBM, synthesised to the other eye
 by ONE persistent kernel launch replayed from a captured HIP graph.
 
-Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
+Beside the timed step the same run reports the other parts of the metric:
+hole PSNR of the plain and learned fills against the ray-cast target eye on
+held-out 1832x1920 frames (with the learned fill's matrix-core throughput),
+and p50/p99 frame latency of the serving loop for 32 headsets.
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--serve-seconds S] [--eval-frames F]
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -43,6 +48,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-single-frame", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=20.0, help="0 skips the serving runs")
+    ap.add_argument("--eval-frames", type=int, default=16, help="0 skips the hole-PSNR evaluation")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the plain path shards "
@@ -151,7 +158,7 @@ def main():
         t_cpu = 0.0
         reps = 0
         outs = None
-        while t_cpu < 10.0 and reps < 20:
+        while t_cpu < 10.0 and reps < 100:
             t1 = time.perf_counter()
             outs = [orc.reproject(r, d, s.baseline_m, s.focal_px, s.target_eye, orc.FILL_NEAREST_BG,
                                   nthreads=threads)[0] for s, (r, d) in zip(specs, frames)]
@@ -169,6 +176,44 @@ def main():
     traffic, sha = profiling.read_summary(os.path.join(ROOT, "profiles", "warp_batch_kernel_64frames.md"))
     if traffic is None or sha != profiling.kernel_source_sha():
         traffic = None
+
+    # ------------------------------------ learned fill: hole PSNR and throughput
+    quality, learned_roof, net = None, None, None
+    if args.eval_frames > 0 or args.serve_seconds > 0:
+        from paper_2506_15183_amd import train, unet
+
+        net = unet.UNet(dev, params=train.load_weights(train.DEFAULT_WEIGHTS))
+    if args.eval_frames > 0:
+        from paper_2506_15183_amd import evaluate
+
+        t1 = time.time()
+        quality = evaluate.evaluate(net, args.eval_frames)
+        log(f"hole PSNR ({time.time() - t1:.1f}s): {quality}")
+        learned_roof = {"bound": "mfma", "achieved": quality["learned_tflops"], "peak": evaluate.BF16_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": quality["learned_frac_of_bf16_peak"],
+                        "kernel": "conv3x3_kernel (whole 1832x1920 frame forward + composite)"}
+
+    # ------------------------------------------------------------ serving
+    serving = None
+    if args.serve_seconds > 0:
+        from paper_2506_15183_amd import serve
+        from paper_2506_15183_amd.scenes.configs import config5_headsets
+
+        t1 = time.time()
+        hs = config5_headsets(32)
+        cfg = serve.Config()
+        srv = serve.Server(hs, cfg, serve.pool_renderer(), model=net, log=log)
+        trace = serve.make_trace(hs, args.serve_seconds, cfg.n_sources)
+        serving = {
+            "workload": f"32 headsets at 72/90/120 Hz, 1440x1600 / 1832x1920 / 2160x2160, exponential 1 ms "
+                        f"render jitter, {args.serve_seconds:g} s, {cfg.budget_bytes / 1e9:g} GB HBM budget",
+            "admitted": int(srv.admitted.sum()), "resident_gb": round(srv.resident_bytes / 1e9, 3),
+            "plain": serve.summarize(trace, srv.run(trace, serve.PLAIN), hs, args.serve_seconds),
+            "learned_policy": serve.summarize(trace, srv.run(trace, serve.LEARNED), hs, args.serve_seconds),
+            "learned_max_hole_fraction": cfg.learned_max_hole_fraction,
+        }
+        log(f"serving ({time.time() - t1:.1f}s): {serving}")
+        del srv
 
     value = pixels * args.steps / wall / 1e6
     result = {
@@ -205,6 +250,9 @@ def main():
         "cpu_baseline": cpu,
         "parity_vs_oracle": parity,
         "single_frame": single,
+        "hole_psnr": quality,
+        "learned_fill_roofline": learned_roof,
+        "serving": serving,
     }
     print(json.dumps(result), flush=True)
 

@@ -68,6 +68,7 @@ bool options_ok(const yoro_serve_options* o) {
 struct Batch {
   int slot;
   std::vector<int64_t> frames;
+  bool warped = false;  // its warp event has been seen
 };
 
 }  // namespace
@@ -152,13 +153,21 @@ int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, c
   int32_t* plan_dev = reinterpret_cast<int32_t*>(ws + Lay.slot * O.max_in_flight);
   int32_t* plan_host = reinterpret_cast<int32_t*>(hs + Lay.counts * O.max_in_flight);
 
-  std::vector<hipEvent_t> ev(O.max_in_flight, nullptr);
+  // ev: a batch's warp is done; cev: its hole counts are on the host.
+  std::vector<hipEvent_t> ev(O.max_in_flight, nullptr), cev(O.max_in_flight, nullptr);
   hipEvent_t lev = nullptr;
   hipError_t he = hipSuccess;
-  for (int i = 0; i < O.max_in_flight && he == hipSuccess; ++i) he = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
+  for (int i = 0; i < O.max_in_flight && he == hipSuccess; ++i) {
+    he = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
+    if (he == hipSuccess) he = hipEventCreateWithFlags(&cev[i], hipEventDisableTiming);
+  }
   if (he == hipSuccess) he = hipEventCreateWithFlags(&lev, hipEventDisableTiming);
 
   std::vector<int> next_out(n_headsets, 0);
+  // Hole fraction of each headset's latest counted frame (-1: none yet).  A
+  // frame whose headset was last above the threshold is released as soon as
+  // its warp is done (fallback predicted); the others wait for their counts.
+  std::vector<double> last_frac(n_headsets, -1.0);
   // Last arrival written into each headset's output set: a finished frame is
   // refined only while its output still holds it.
   std::vector<int64_t> last_in(n_headsets * YORO_SERVE_MAX_OUTPUTS, -1);
@@ -240,24 +249,47 @@ int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, c
     // Completed batches (one stream: they finish in order).
     while (!inflight.empty() && status == YORO_OK) {
       Batch& B = inflight.front();
-      const hipError_t q = hipEventQuery(ev[B.slot]);
-      if (q == hipErrorNotReady) break;
-      if (q != hipSuccess) {
-        status = serve_fail(YORO_ERR_DEVICE, "%s: batch: %s", who, hipGetErrorString(q));
-        break;
-      }
-      const int64_t tn = now_ns();
-      const uint32_t* counts = reinterpret_cast<const uint32_t*>(hs + Lay.counts * B.slot);
-      for (size_t i = 0; i < B.frames.size(); ++i) {
-        const int64_t k = B.frames[i];
-        if (!L_on) {
-          results[k].path = YORO_PATH_PLAIN, results[k].done_ns = tn;
-          continue;
+      if (!B.warped) {
+        const hipError_t q = hipEventQuery(ev[B.slot]);
+        if (q == hipErrorNotReady) break;
+        if (q != hipSuccess) {
+          status = serve_fail(YORO_ERR_DEVICE, "%s: batch: %s", who, hipGetErrorString(q));
+          break;
         }
-        const int32_t p = refine(k, counts + i * Lay.tiles);
-        if (p < 0) break;
-        results[k].path = p;
-        if (!(p == YORO_PATH_LEARNED && l_active && l_frame == k)) results[k].done_ns = tn;
+        const int64_t tn = now_ns();
+        for (int64_t k : B.frames) {
+          if (!L_on) {
+            results[k].path = YORO_PATH_PLAIN, results[k].done_ns = tn;
+          } else if (last_frac[arrivals[k].headset] > (double)O.learned_max_hole_fraction) {
+            results[k].path = YORO_PATH_FALLBACK, results[k].done_ns = tn;
+          }
+        }
+        B.warped = true;
+      }
+      if (L_on) {
+        const hipError_t q = hipEventQuery(cev[B.slot]);
+        if (q == hipErrorNotReady) break;
+        if (q != hipSuccess) {
+          status = serve_fail(YORO_ERR_DEVICE, "%s: hole counts: %s", who, hipGetErrorString(q));
+          break;
+        }
+        const int64_t tn = now_ns();
+        const uint32_t* counts = reinterpret_cast<const uint32_t*>(hs + Lay.counts * B.slot);
+        for (size_t i = 0; i < B.frames.size(); ++i) {
+          const int64_t k = B.frames[i];
+          const yoro_serve_headset& H = headsets[arrivals[k].headset];
+          if (results[k].done_ns >= 0) {  // released at the warp: keep the statistics only
+            int64_t holes = 0;
+            for (int t = 0, nt = tiles_of(H.width, H.height, O.tile); t < nt; ++t) holes += counts[i * Lay.tiles + t];
+            results[k].holes = holes;
+          } else {
+            const int32_t p = refine(k, counts + i * Lay.tiles);
+            if (p < 0) break;
+            results[k].path = p;
+            if (!(p == YORO_PATH_LEARNED && l_active && l_frame == k)) results[k].done_ns = tn;
+          }
+          last_frac[arrivals[k].headset] = (double)results[k].holes / ((double)H.width * H.height);
+        }
       }
       free_slots.push_back(B.slot);
       inflight.pop_front();
@@ -321,14 +353,15 @@ int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, c
         status = st;
         break;
       }
-      if (L_on) {
+      e = hipEventRecord(ev[B.slot], s);
+      if (L_on && e == hipSuccess) {
         uint32_t* cd = reinterpret_cast<uint32_t*>(ws + Lay.slot * B.slot + Lay.table);
         for (size_t i = 0; i < jobs.size() && e == hipSuccess; ++i)
           e = yoro::nn_tile_holes(jobs[i].dst_mask, jobs[i].width, jobs[i].height, O.tile, cd + i * Lay.tiles, s);
         if (e == hipSuccess)
           e = hipMemcpyAsync(hs + Lay.counts * B.slot, cd, jobs.size() * Lay.tiles * 4, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipEventRecord(cev[B.slot], s);
       }
-      if (e == hipSuccess) e = hipEventRecord(ev[B.slot], s);
       if (e != hipSuccess) {
         status = serve_fail(YORO_ERR_DEVICE, "%s: batch launch: %s", who, hipGetErrorString(e));
         break;
@@ -343,6 +376,8 @@ int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, c
   (void)hipStreamSynchronize(s);
   if (L_on) (void)hipStreamSynchronize(ls);
   for (hipEvent_t e : ev)
+    if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : cev)
     if (e) (void)hipEventDestroy(e);
   if (lev) (void)hipEventDestroy(lev);
   return status;

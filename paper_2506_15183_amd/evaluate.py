@@ -1,0 +1,113 @@
+"""Hole PSNR of the plain and learned fills against the ray-cast target eye
+on held-out full frames, and the learned fill's inference throughput.
+
+    python -m paper_2506_15183_amd.evaluate --frames 16
+
+PSNR is over the RGB channels of the hole pixels (mask != 0) with peak 255,
+reported per frame (mean over frames) and pooled (one MSE over all hole
+pixels of all frames).  The learned fill runs on whole frames here: it equals
+the hole-tile fill bit for bit, and with hole blocks covering most of a frame
+the whole frame is the cheaper of the two.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+
+import numpy as np
+import torch
+
+from . import train, unet, yoro
+from .scenes.configs import config4_test_frames
+
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense bf16 matrix peak, vendor figure
+
+
+def algorithmic_flops(h: int, w: int, n: int = 1) -> float:
+    """FLOPs of one forward pass over the real channel counts (5-channel
+    input, 3-channel head; the kernels' zero padding to 32 not counted)."""
+    level = {"e0": 0, "e1": 1, "e2": 2, "e3": 3, "d2": 2, "d1": 1, "d0": 0, "he": 0}
+    return sum(2.0 * 9 * cin * cout * n * (h >> level[nm[:2]]) * (w >> level[nm[:2]]) for nm, cin, cout in unet.ARCH)
+
+
+def _psnr(sse: int, count: int) -> float:
+    if count == 0:
+        return float("nan")
+    mse = sse / (3.0 * count)
+    return float("inf") if mse == 0 else 10.0 * math.log10(255.0 ** 2 / mse)
+
+
+def _sse(a, b, m):
+    s, c = [int(v) for v in yoro.hole_sse(a, b, m).cpu().numpy().view(np.uint64)]
+    return s, c
+
+
+def evaluate(net: unet.UNet, n_frames: int = 16, log=None, timing_reps: int = 5):
+    dev = net.device
+    per_plain, per_learned = [], []
+    pooled = np.zeros((2, 2), dtype=np.int64)  # [plain, learned] x [sse, count]
+    blocks, blocks_total, hole_frac = 0, 0, []
+    times = []
+    for i, spec in enumerate(config4_test_frames(n_frames)):
+        s_rgba, s_depth = spec.render_source()
+        t_rgba, _ = spec.render_target()
+        src = torch.from_numpy(s_rgba).to(dev)
+        srd = torch.from_numpy(s_depth).to(dev)
+        tgt = torch.from_numpy(t_rgba).to(dev)
+        rgba, depth, mask = yoro.reproject(src, srd, spec.baseline_m, spec.focal_px, spec.target_eye,
+                                           yoro.FILL_NEAREST_BG)
+        out = net.fill_native(rgba[None], depth[None], mask[None])[0]
+        counts = net.tile_holes(mask).cpu().numpy()
+        blocks += int((counts > 0).sum())
+        blocks_total += counts.size
+        torch.cuda.synchronize()
+        if i == 0:  # time the whole-frame learned fill (resident inputs)
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(timing_reps)]
+            for a, b in ev:
+                a.record()
+                net.fill_native(rgba[None], depth[None], mask[None], out=out[None])
+                b.record()
+            torch.cuda.synchronize()
+            times = [a.elapsed_time(b) for a, b in ev]
+        sp = _sse(rgba, tgt, mask)
+        sl = _sse(out, tgt, mask)
+        pooled[0] += sp
+        pooled[1] += sl
+        per_plain.append(_psnr(*sp))
+        per_learned.append(_psnr(*sl))
+        hole_frac.append(sp[1] / spec.pixels)
+        if log:
+            log(f"frame {i}: holes {hole_frac[-1]:.3f}, plain {per_plain[-1]:.2f} dB, learned {per_learned[-1]:.2f} dB")
+    h, w = 1920, 1832
+    ms = float(np.median(times))
+    fl = algorithmic_flops(h, w)
+    return {
+        "frames": n_frames, "size": f"{w}x{h}",
+        "hole_fraction_mean": round(float(np.mean(hole_frac)), 4),
+        "hole_psnr_plain_db": round(_psnr(*pooled[0]), 3),
+        "hole_psnr_learned_db": round(_psnr(*pooled[1]), 3),
+        "hole_psnr_plain_mean_db": round(float(np.mean(per_plain)), 3),
+        "hole_psnr_learned_mean_db": round(float(np.mean(per_learned)), 3),
+        "hole_blocks_fraction": round(blocks / max(blocks_total, 1), 4),
+        "learned_ms_per_frame": round(ms, 3),
+        "learned_tflops": round(fl / (ms * 1e-3) / 1e12, 2),
+        "learned_frac_of_bf16_peak": round(fl / (ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS, 4),
+        "learned_flops_per_frame": fl,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--frames", type=int, default=16)
+    ap.add_argument("--weights", default=train.DEFAULT_WEIGHTS)
+    a = ap.parse_args()
+    net = unet.UNet("cuda", params=train.load_weights(a.weights))
+    res = evaluate(net, a.frames, log=lambda m: print(m, file=sys.stderr, flush=True))
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

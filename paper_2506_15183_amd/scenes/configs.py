@@ -194,3 +194,14 @@ def config5_pool_frame(width: int, height: int, target_eye: int, slot: int) -> F
     u = raycast.uniforms(frame_seed(5, 4_000_000 + key), 1)
     n = 100 + int(u[0] * 201)
     return FrameSpec(width, height, 0.063, 900.0, target_eye, n, 0.3, 50.0, True, (4, 32), frame_seed(5, key))
+
+
+def config4_test_frames(n: int = 16) -> list[FrameSpec]:
+    """Held-out full 1832 x 1920 frames for the learned fill (seeds disjoint
+    from the training and validation windows); scenes and B, f as config 3."""
+    out = []
+    for i in range(n):
+        u = raycast.uniforms(frame_seed(42, 5_000_000 + i), 3)
+        out.append(FrameSpec(1832, 1920, 0.055 + (0.072 - 0.055) * float(u[0]), 600.0 + (1100.0 - 600.0) * float(u[1]),
+                             TARGET_RIGHT, 50 + int(u[2] * 251), 0.3, 50.0, True, (4, 32), frame_seed(42, i)))
+    return out
