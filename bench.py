@@ -191,7 +191,7 @@ def main():
         log(f"hole PSNR ({time.time() - t1:.1f}s): {quality}")
         learned_roof = {"bound": "mfma", "achieved": quality["learned_tflops"], "peak": evaluate.BF16_PEAK_TFLOPS,
                         "unit": "TFLOP/s", "frac": quality["learned_frac_of_bf16_peak"],
-                        "kernel": "conv3x3_kernel (whole 1832x1920 frame forward + composite)"}
+                        "kernel": "conv3x3_tiled_kernel and the layer kernels: one whole 1832x1920 frame, forward + composite"}
 
     # ------------------------------------------------------------ serving
     serving = None

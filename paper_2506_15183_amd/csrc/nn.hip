@@ -11,8 +11,9 @@
 // input channels, on v_mfma_f32_16x16x32_bf16 (A: 16 pixels x 32 channels,
 // B: 32 channels x 16 outputs, D: 16 x 16 FP32).  Lane l of a wave holds A
 // row (l % 16) with k = 8*(l/16) .. +7, B column (l % 16) with the same k,
-// and D column (l % 16) with rows 4*(l/16) .. +3.  The same kernel computes
-// the input gradient with the weights flipped and transposed.
+// and D column (l % 16) with rows 4*(l/16) .. +3.  Input patches are staged
+// in LDS and shared by the nine taps.  The same kernel computes the input
+// gradient with the weights flipped and transposed.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -35,68 +36,109 @@ __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float(
 
 __device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
 
-constexpr int kConvThreads = 256;  // 4 waves; a workgroup covers 64 pixels
+constexpr int kConvThreads = 256;  // 4 waves
 
-// ---------------------------------------------------------------- conv3x3 --
-// Output tile: 64 pixels x CT channels; wave w takes pixels 16w..16w+15.
-// epi: 0 none, 1 ReLU, 2 multiply by (msrc > 0) (the ReLU derivative of the
-// forward activation at the same position).
+// ----------------------------------------------------------- conv3x3, tiled --
+// Output tile: 8 rows x 32 pixels of one image x CT channels per 256-thread
+// workgroup.  Per 32-channel input chunk the (8+2) x (32+2) input patch is
+// staged once in LDS and read by all nine taps; wave w computes rows 2w and
+// 2w+1 (four 16-pixel M tiles) x CT channels, so each B fragment (weights,
+// 16-byte loads from the cache) feeds four MFMAs and each A fragment CT/16.
+// The LDS pixel stride is 40 bf16 (32 channels + 8 pad = 80 bytes) so the 16
+// lanes reading one k group of 16 consecutive pixels hit distinct banks.
+constexpr int kTileH = 8, kTileW = 32;
+constexpr int kPatchH = kTileH + 2, kPatchW = kTileW + 2;
+constexpr int kPatchStride = 40;
+
 template <int CT>
-__global__ __launch_bounds__(kConvThreads) void conv3x3_kernel(const uint16_t* __restrict__ x, int ldx, int N, int H,
-                                                               int W, int Cin, const uint16_t* __restrict__ wgt,
-                                                               int Cout, void* __restrict__ y, int ldy, int y_fp32,
-                                                               int cout_store, int epi,
-                                                               const uint16_t* __restrict__ msrc, int ldm) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const long long P = (long long)N * H * W;
-  const long long p0 = (long long)blockIdx.x * 64 + wave * 16;
+__global__ __launch_bounds__(kConvThreads) void conv3x3_tiled_kernel(const uint16_t* __restrict__ x, int ldx, int N,
+                                                                     int H, int W, int Cin,
+                                                                     const uint16_t* __restrict__ wgt, int Cout,
+                                                                     void* __restrict__ y, int ldy, int y_fp32,
+                                                                     int cout_store, int epi,
+                                                                     const uint16_t* __restrict__ msrc, int ldm) {
+  constexpr int NB = CT / 16;
+  __shared__ __align__(16) uint16_t patch[kPatchH * kPatchW * kPatchStride];
+  const int tiles_x = (W + kTileW - 1) / kTileW, tiles_y = (H + kTileH - 1) / kTileH;
+  int b = blockIdx.x;
+  const int tx = b % tiles_x;
+  b /= tiles_x;
+  const int ty = b % tiles_y;
+  const int n = b / tiles_y;
+  const int x0 = tx * kTileW, y0 = ty * kTileH;
   const int co0 = blockIdx.y * CT;
-  // This lane's A row: pixel p0 + lane%16; its k group: channels 8*(lane/16).
-  const long long pa = p0 + (lane & 15);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int kg = (lane >> 4) * 8;
-  int ay = 0, ax = 0, an = 0;
-  const bool arow = pa < P;
-  if (arow) {
-    an = (int)(pa / ((long long)H * W));
-    const int rem = (int)(pa - (long long)an * H * W);
-    ay = rem / W;
-    ax = rem - ay * W;
-  }
-  floatx4 acc[CT / 16];
+  const long long img = (long long)n * H * W;
+  floatx4 acc[4][NB];
 #pragma unroll
-  for (int b = 0; b < CT / 16; ++b) acc[b] = floatx4{0.f, 0.f, 0.f, 0.f};
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[m][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+  // This lane's B row: output channel co0 + nb*16 + lane%16, k group kg.
+  const uint16_t* wrow = wgt + (long long)(co0 + (lane & 15)) * Cin + kg;
 
-  for (int t = 0; t < 9; ++t) {
-    const int yy = ay + t / 3 - 1, xx = ax + t % 3 - 1;
-    const bool in = arow && yy >= 0 && yy < H && xx >= 0 && xx < W;
-    const uint16_t* xrow = x + ((long long)an * H * W + (long long)(in ? yy : 0) * W + (in ? xx : 0)) * ldx + kg;
-    const uint16_t* wt = wgt + ((long long)t * Cout + co0 + (lane & 15)) * Cin + kg;
-    for (int ci = 0; ci < Cin; ci += 32) {
-      u32x4 av = {0u, 0u, 0u, 0u};
-      if (in) av = *reinterpret_cast<const u32x4*>(xrow + ci);
+  for (int ci0 = 0; ci0 < Cin; ci0 += 32) {
+    __syncthreads();  // the previous chunk's readers are done with the patch
+    for (int e = threadIdx.x; e < kPatchH * kPatchW * 4; e += kConvThreads) {
+      const int pix = e >> 2, part = e & 3;
+      const int py = pix / kPatchW, px = pix - py * kPatchW;
+      const int gy = y0 + py - 1, gx = x0 + px - 1;
+      u32x4 v = {0u, 0u, 0u, 0u};
+      if (gy >= 0 && gy < H && gx >= 0 && gx < W)
+        v = *reinterpret_cast<const u32x4*>(x + (img + (long long)gy * W + gx) * ldx + ci0 + part * 8);
+      *reinterpret_cast<u32x4*>(patch + pix * kPatchStride + part * 8) = v;
+    }
+    __syncthreads();
+    u32x4 bcur[NB], bnext[NB];
 #pragma unroll
-      for (int b = 0; b < CT / 16; ++b) {
-        const u32x4 bv = *reinterpret_cast<const u32x4*>(wt + (long long)b * 16 * Cin + ci);
-        acc[b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(av), as_bf16x8(bv), acc[b], 0, 0, 0);
+    for (int nb = 0; nb < NB; ++nb)
+      bcur[nb] = *reinterpret_cast<const u32x4*>(wrow + (long long)nb * 16 * Cin + ci0);
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      if (t < 8) {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          bnext[nb] = *reinterpret_cast<const u32x4*>(wrow + ((long long)(t + 1) * Cout + nb * 16) * Cin + ci0);
+      }
+      const int ky = t / 3, kx = t % 3;
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int r = 2 * wave + (m >> 1), c = (m & 1) * 16 + (lane & 15);
+        const u32x4 av =
+            *reinterpret_cast<const u32x4*>(patch + ((r + ky) * kPatchW + (c + kx)) * kPatchStride + kg);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+          acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(av), as_bf16x8(bcur[nb]), acc[m][nb], 0, 0,
+                                                               0);
+      }
+      if (t < 8) {
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) bcur[nb] = bnext[nb];
       }
     }
   }
-  // Epilogue: lane holds column co0 + 16b + lane%16, rows 4*(lane/16) + r.
+  // Epilogue: lane holds channel co0 + 16nb + lane%16 of pixels 4*(lane/16)+r
+  // of M tile m, i.e. row 2*wave + m/2, column 16*(m%2) + 4*(lane/16) + r.
 #pragma unroll
-  for (int b = 0; b < CT / 16; ++b) {
-    const int co = co0 + b * 16 + (lane & 15);
+  for (int m = 0; m < 4; ++m) {
+    const int gy = y0 + 2 * wave + (m >> 1);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const long long p = p0 + (lane >> 4) * 4 + r;
-      if (p >= P || co >= cout_store) continue;
-      float v = acc[b][r];
-      if (epi == 1) v = fmaxf(v, 0.0f);
-      if (epi == 2) v = (from_bf16(msrc[p * ldm + co]) > 0.0f) ? v : 0.0f;
-      if (y_fp32)
-        reinterpret_cast<float*>(y)[p * ldy + co] = v;
-      else
-        reinterpret_cast<uint16_t*>(y)[p * ldy + co] = to_bf16(v);
+    for (int nb = 0; nb < NB; ++nb) {
+      const int co = co0 + nb * 16 + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gx = x0 + (m & 1) * 16 + (lane >> 4) * 4 + r;
+        if (gy >= H || gx >= W || co >= cout_store) continue;
+        const long long p = img + (long long)gy * W + gx;
+        float v = acc[m][nb][r];
+        if (epi == 1) v = fmaxf(v, 0.0f);
+        if (epi == 2) v = (from_bf16(msrc[p * ldm + co]) > 0.0f) ? v : 0.0f;
+        if (y_fp32)
+          reinterpret_cast<float*>(y)[p * ldy + co] = v;
+        else
+          reinterpret_cast<uint16_t*>(y)[p * ldy + co] = to_bf16(v);
+      }
     }
   }
 }
@@ -506,14 +548,15 @@ int grid_1d(long long n, int threads) {
 // ------------------------------------------------------------- launchers --
 hipError_t nn_conv3x3(const uint16_t* x, int ldx, int N, int H, int W, int Cin, const uint16_t* wgt, int Cout, void* y,
                       int ldy, int y_fp32, int cout_store, int epi, const uint16_t* msrc, int ldm, hipStream_t s) {
-  const long long P = (long long)N * H * W;
-  const unsigned gx = (unsigned)((P + 63) / 64);
+  const long long tiles = (long long)N * ((H + kTileH - 1) / kTileH) * ((W + kTileW - 1) / kTileW);
+  if (tiles > 0x7FFFFFFFLL) return hipErrorInvalidValue;
+  const unsigned gx = (unsigned)tiles;
   if (Cout % 64 == 0) {
-    hipLaunchKernelGGL(conv3x3_kernel<64>, dim3(gx, Cout / 64), dim3(kConvThreads), 0, s, x, ldx, N, H, W, Cin, wgt,
-                       Cout, y, ldy, y_fp32, cout_store, epi, msrc, ldm);
+    hipLaunchKernelGGL(conv3x3_tiled_kernel<64>, dim3(gx, Cout / 64), dim3(kConvThreads), 0, s, x, ldx, N, H, W, Cin,
+                       wgt, Cout, y, ldy, y_fp32, cout_store, epi, msrc, ldm);
   } else {
-    hipLaunchKernelGGL(conv3x3_kernel<32>, dim3(gx, Cout / 32), dim3(kConvThreads), 0, s, x, ldx, N, H, W, Cin, wgt,
-                       Cout, y, ldy, y_fp32, cout_store, epi, msrc, ldm);
+    hipLaunchKernelGGL(conv3x3_tiled_kernel<32>, dim3(gx, Cout / 32), dim3(kConvThreads), 0, s, x, ldx, N, H, W, Cin,
+                       wgt, Cout, y, ldy, y_fp32, cout_store, epi, msrc, ldm);
   }
   return hipGetLastError();
 }
