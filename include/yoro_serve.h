@@ -8,14 +8,16 @@
  * launch of yoro.h per batch, up to max_batch frames, at most max_in_flight
  * batches queued), and records when each frame's result is final.
  *
- * Optional learned refinement (policy YORO_SERVE_LEARNED): after a batch's
- * warp the loop counts each frame's holes per tile on the device and reads
+ * Optional learned refinement (policy YORO_SERVE_LEARNED): once a batch's
+ * warp is seen done, the loop counts each frame's holes per tile on the
+ * device (on the learned stream, so the plain stream never waits) and reads
  * the counts back; a frame whose hole fraction is at most
  * learned_max_hole_fraction is refined by yoro_model_fill_tiles on the
  * learned stream (in place, on the frame's output), the others keep the
  * plain fill.  A frame whose headset's previous counted frame was above the
  * threshold is released as soon as its warp is done (fallback predicted, no
- * wait for its own count).  One refinement runs at a time; a frame that
+ * wait for its own count), and while a headset falls back its holes are
+ * counted on every 8th frame only (holes = -1 in the results of the others).  One refinement runs at a time; a frame that
  * finds it busy, or whose output set has already been handed to a newer
  * frame of its headset, keeps the plain fill.  A batch that reuses the
  * output set under refinement waits for it on the device.

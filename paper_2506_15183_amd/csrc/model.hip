@@ -45,9 +45,9 @@ bool al4(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }
 
 // Activation buffers of one forward pass (bf16 NHWC; res FP32 [P0][3]).
 struct Acts {
-  uint16_t *x0, *e0a, *c0, *d0b, *d0c, *u0;
-  uint16_t *p1, *e1a, *c1, *d1b, *d1c, *u1;
-  uint16_t *p2, *e2a, *c2, *d2b, *d2c, *u2;
+  uint16_t *x0, *e0a, *c0, *d0b, *d0c;
+  uint16_t *p1, *e1a, *c1, *d1b, *d1c;
+  uint16_t *p2, *e2a, *c2, *d2b, *d2c;
   uint16_t *p3, *e3a, *e3b;
   float* res;
 };
@@ -65,11 +65,8 @@ size_t carve(char* base, long long n, int h, int w, Acts* a) {
   auto bf = [&](long long p, int c) { return reinterpret_cast<uint16_t*>(take(p * c, 2)); };
   Acts t;
   t.x0 = bf(P[0], 32), t.e0a = bf(P[0], 32), t.c0 = bf(P[0], 64), t.d0b = bf(P[0], 32), t.d0c = bf(P[0], 32);
-  t.u0 = bf(P[0], 64);
   t.p1 = bf(P[1], 32), t.e1a = bf(P[1], 64), t.c1 = bf(P[1], 128), t.d1b = bf(P[1], 64), t.d1c = bf(P[1], 64);
-  t.u1 = bf(P[1], 128);
   t.p2 = bf(P[2], 64), t.e2a = bf(P[2], 128), t.c2 = bf(P[2], 256), t.d2b = bf(P[2], 128), t.d2c = bf(P[2], 128);
-  t.u2 = bf(P[2], 256);
   t.p3 = bf(P[3], 128), t.e3a = bf(P[3], 256), t.e3b = bf(P[3], 256);
   t.res = reinterpret_cast<float*>(take(P[0] * 3, 4));
   if (a) *a = t;
@@ -101,16 +98,20 @@ hipError_t forward(const uint16_t* wts, const uint8_t* rgba, const float* depth,
   ok(nn_avgpool2(a.c2 + 128, 256, n, h >> 2, w >> 2, 128, a.p3, 128, s));
   conv(6, a.p3, 128, 3, a.e3a, 256);
   conv(7, a.e3a, 256, 3, a.e3b, 256);
-  ok(nn_upsample2(a.e3b, 256, n, h >> 3, w >> 3, 256, a.u2, 256, s));
-  conv(8, a.u2, 256, 2, a.c2, 256);  // d2a -> the decoder half of c2
+  // The decoders' first convolutions read the lower level's output through
+  // a nearest x2 upsampling done in their input loads (no upsampled copy).
+  auto conv_up = [&](int i, const uint16_t* xlo, int ldx, int lev, uint16_t* y, int ldy) {
+    const Layer L = kLayers[i];
+    ok(nn_conv3x3_up(xlo, ldx, n, h >> lev, w >> lev, L.cin, wts + layer_offset(i), L.cout, y, ldy, 0, L.cout, 1,
+                     nullptr, 0, s));
+  };
+  conv_up(8, a.e3b, 256, 2, a.c2, 256);  // d2a -> the decoder half of c2
   conv(9, a.c2, 256, 2, a.d2b, 128);
   conv(10, a.d2b, 128, 2, a.d2c, 128);
-  ok(nn_upsample2(a.d2c, 128, n, h >> 2, w >> 2, 128, a.u1, 128, s));
-  conv(11, a.u1, 128, 1, a.c1, 128);  // d1a
+  conv_up(11, a.d2c, 128, 1, a.c1, 128);  // d1a
   conv(12, a.c1, 128, 1, a.d1b, 64);
   conv(13, a.d1b, 64, 1, a.d1c, 64);
-  ok(nn_upsample2(a.d1c, 64, n, h >> 1, w >> 1, 64, a.u0, 64, s));
-  conv(14, a.u0, 64, 0, a.c0, 64);  // d0a
+  conv_up(14, a.d1c, 64, 0, a.c0, 64);  // d0a
   conv(15, a.c0, 64, 0, a.d0b, 32);
   conv(16, a.d0b, 32, 0, a.d0c, 32);
   // Head: FP32 residual, the first 3 of its 32 padded outputs, no activation.

@@ -56,7 +56,8 @@ __global__ __launch_bounds__(kConvThreads) void conv3x3_tiled_kernel(const uint1
                                                                      const uint16_t* __restrict__ wgt, int Cout,
                                                                      void* __restrict__ y, int ldy, int y_fp32,
                                                                      int cout_store, int epi,
-                                                                     const uint16_t* __restrict__ msrc, int ldm) {
+                                                                     const uint16_t* __restrict__ msrc, int ldm,
+                                                                     int ups) {
   constexpr int NB = CT / 16;
   __shared__ __align__(16) uint16_t patch[kPatchH * kPatchW * kPatchStride];
   const int tiles_x = (W + kTileW - 1) / kTileW, tiles_y = (H + kTileH - 1) / kTileH;
@@ -85,8 +86,13 @@ __global__ __launch_bounds__(kConvThreads) void conv3x3_tiled_kernel(const uint1
       const int py = pix / kPatchW, px = pix - py * kPatchW;
       const int gy = y0 + py - 1, gx = x0 + px - 1;
       u32x4 v = {0u, 0u, 0u, 0u};
-      if (gy >= 0 && gy < H && gx >= 0 && gx < W)
-        v = *reinterpret_cast<const u32x4*>(x + (img + (long long)gy * W + gx) * ldx + ci0 + part * 8);
+      if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+        // ups: x is the half-resolution image and the input is its nearest
+        // x2 upsampling, read in place.
+        const long long src = ups ? (img >> 2) + (long long)(gy >> 1) * (W >> 1) + (gx >> 1)
+                                  : img + (long long)gy * W + gx;
+        v = *reinterpret_cast<const u32x4*>(x + src * ldx + ci0 + part * 8);
+      }
       *reinterpret_cast<u32x4*>(patch + pix * kPatchStride + part * 8) = v;
     }
     __syncthreads();
@@ -339,6 +345,119 @@ __global__ void upsample2_grad_kernel(const uint16_t* __restrict__ g, int ldg, i
   }
 }
 
+// Eight channels (16 bytes) per thread: the same arithmetic per element as
+// the kernels above, used when channel counts and strides are multiples of 8.
+__device__ __forceinline__ float lo_bf(uint32_t v) { return __uint_as_float(v << 16); }
+__device__ __forceinline__ float hi_bf(uint32_t v) { return __uint_as_float(v & 0xFFFF0000u); }
+__device__ __forceinline__ uint32_t pack_bf(float a, float b) {
+  return (uint32_t)to_bf16(a) | ((uint32_t)to_bf16(b) << 16);
+}
+
+__global__ void avgpool2_v8_kernel(const uint16_t* __restrict__ x, int ldx, int N, int h, int w, int c,
+                                   uint16_t* __restrict__ y, int ldy) {
+  const int ho = h / 2, wo = w / 2, c8 = c / 8;
+  const long long n = (long long)N * ho * wo * c8;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const int ch = (int)(i % c8) * 8;
+    long long q = i / c8;
+    const int j = (int)(q % wo);
+    q /= wo;
+    const int ii = (int)(q % ho);
+    const int nn = (int)(q / ho);
+    const long long b = ((long long)nn * h + 2 * ii) * w + 2 * j;
+    const u32x4 a = *reinterpret_cast<const u32x4*>(x + b * ldx + ch);
+    const u32x4 bb = *reinterpret_cast<const u32x4*>(x + (b + 1) * ldx + ch);
+    const u32x4 cc = *reinterpret_cast<const u32x4*>(x + (b + w) * ldx + ch);
+    const u32x4 d = *reinterpret_cast<const u32x4*>(x + (b + w + 1) * ldx + ch);
+    u32x4 o;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float sl = (lo_bf(a[k]) + lo_bf(bb[k])) + (lo_bf(cc[k]) + lo_bf(d[k]));
+      const float sh = (hi_bf(a[k]) + hi_bf(bb[k])) + (hi_bf(cc[k]) + hi_bf(d[k]));
+      o[k] = pack_bf(sl * 0.25f, sh * 0.25f);
+    }
+    *reinterpret_cast<u32x4*>(y + (((long long)nn * ho + ii) * wo + j) * ldy + ch) = o;
+  }
+}
+
+__global__ void avgpool2_grad_v8_kernel(const uint16_t* __restrict__ g, int ldg, const uint16_t* __restrict__ add,
+                                        int lda, const uint16_t* __restrict__ msrc, int ldm, int N, int h, int w, int c,
+                                        uint16_t* __restrict__ dx, int lddx) {
+  const int c8 = c / 8;
+  const long long n = (long long)N * h * w * c8;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const int ch = (int)(i % c8) * 8;
+    const long long p = i / c8;
+    const int xx = (int)(p % w);
+    const long long q = p / w;
+    const int yy = (int)(q % h);
+    const int nn = (int)(q / h);
+    const long long pg = ((long long)nn * (h / 2) + yy / 2) * (w / 2) + xx / 2;
+    const u32x4 gv = *reinterpret_cast<const u32x4*>(g + pg * ldg + ch);
+    u32x4 av = {0u, 0u, 0u, 0u}, mv = {0u, 0u, 0u, 0u};
+    if (add) av = *reinterpret_cast<const u32x4*>(add + p * lda + ch);
+    if (msrc) mv = *reinterpret_cast<const u32x4*>(msrc + p * ldm + ch);
+    u32x4 o;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      float vl = lo_bf(gv[k]) * 0.25f, vh = hi_bf(gv[k]) * 0.25f;
+      if (add) {
+        vl += lo_bf(av[k]);
+        vh += hi_bf(av[k]);
+      }
+      if (msrc) {
+        if (!(lo_bf(mv[k]) > 0.0f)) vl = 0.0f;
+        if (!(hi_bf(mv[k]) > 0.0f)) vh = 0.0f;
+      }
+      o[k] = pack_bf(vl, vh);
+    }
+    *reinterpret_cast<u32x4*>(dx + p * lddx + ch) = o;
+  }
+}
+
+__global__ void upsample2_v8_kernel(const uint16_t* __restrict__ x, int ldx, int N, int h, int w, int c,
+                                    uint16_t* __restrict__ y, int ldy) {
+  const int c8 = c / 8, W2 = 2 * w;
+  const long long n = (long long)N * 4 * h * w * c8;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const int ch = (int)(i % c8) * 8;
+    const long long p = i / c8;
+    const int xx = (int)(p % W2);
+    const long long q = p / W2;
+    const int yy = (int)(q % (2 * h));
+    const int nn = (int)(q / (2 * h));
+    *reinterpret_cast<u32x4*>(y + p * ldy + ch) =
+        *reinterpret_cast<const u32x4*>(x + (((long long)nn * h + yy / 2) * w + xx / 2) * ldx + ch);
+  }
+}
+
+__global__ void upsample2_grad_v8_kernel(const uint16_t* __restrict__ g, int ldg, int N, int h, int w, int c,
+                                         uint16_t* __restrict__ dx, int lddx) {
+  const int c8 = c / 8, W2 = 2 * w;
+  const long long n = (long long)N * h * w * c8;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const int ch = (int)(i % c8) * 8;
+    const long long p = i / c8;
+    const int xx = (int)(p % w);
+    const long long q = p / w;
+    const int yy = (int)(q % h);
+    const int nn = (int)(q / h);
+    const long long b = ((long long)nn * 2 * h + 2 * yy) * W2 + 2 * xx;
+    const u32x4 a = *reinterpret_cast<const u32x4*>(g + b * ldg + ch);
+    const u32x4 bb = *reinterpret_cast<const u32x4*>(g + (b + 1) * ldg + ch);
+    const u32x4 cc = *reinterpret_cast<const u32x4*>(g + (b + W2) * ldg + ch);
+    const u32x4 d = *reinterpret_cast<const u32x4*>(g + (b + W2 + 1) * ldg + ch);
+    u32x4 o;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float sl = (lo_bf(a[k]) + lo_bf(bb[k])) + (lo_bf(cc[k]) + lo_bf(d[k]));
+      const float sh = (hi_bf(a[k]) + hi_bf(bb[k])) + (hi_bf(cc[k]) + hi_bf(d[k]));
+      o[k] = pack_bf(sl, sh);
+    }
+    *reinterpret_cast<u32x4*>(dx + p * lddx + ch) = o;
+  }
+}
+
 // --------------------------------------------------- input, loss, output --
 constexpr float kLogZmin = -1.2039728043259361f;  // log(0.3)
 constexpr float kLogZmax = 3.912023005428146f;    // log(50)
@@ -546,41 +665,71 @@ int grid_1d(long long n, int threads) {
 }  // namespace
 
 // ------------------------------------------------------------- launchers --
-hipError_t nn_conv3x3(const uint16_t* x, int ldx, int N, int H, int W, int Cin, const uint16_t* wgt, int Cout, void* y,
-                      int ldy, int y_fp32, int cout_store, int epi, const uint16_t* msrc, int ldm, hipStream_t s) {
+namespace {
+hipError_t conv3x3_launch(const uint16_t* x, int ldx, int N, int H, int W, int Cin, const uint16_t* wgt, int Cout,
+                          void* y, int ldy, int y_fp32, int cout_store, int epi, const uint16_t* msrc, int ldm, int ups,
+                          hipStream_t s) {
   const long long tiles = (long long)N * ((H + kTileH - 1) / kTileH) * ((W + kTileW - 1) / kTileW);
   if (tiles > 0x7FFFFFFFLL) return hipErrorInvalidValue;
   const unsigned gx = (unsigned)tiles;
-  if (Cout % 64 == 0) {
+  if (cout_store <= 16) {  // e.g. the 3-channel head: only the first 16 outputs are computed
+    hipLaunchKernelGGL(conv3x3_tiled_kernel<16>, dim3(gx, 1), dim3(kConvThreads), 0, s, x, ldx, N, H, W, Cin, wgt,
+                       Cout, y, ldy, y_fp32, cout_store, epi, msrc, ldm, ups);
+  } else if (Cout % 64 == 0) {
     hipLaunchKernelGGL(conv3x3_tiled_kernel<64>, dim3(gx, Cout / 64), dim3(kConvThreads), 0, s, x, ldx, N, H, W, Cin,
-                       wgt, Cout, y, ldy, y_fp32, cout_store, epi, msrc, ldm);
+                       wgt, Cout, y, ldy, y_fp32, cout_store, epi, msrc, ldm, ups);
   } else {
     hipLaunchKernelGGL(conv3x3_tiled_kernel<32>, dim3(gx, Cout / 32), dim3(kConvThreads), 0, s, x, ldx, N, H, W, Cin,
-                       wgt, Cout, y, ldy, y_fp32, cout_store, epi, msrc, ldm);
+                       wgt, Cout, y, ldy, y_fp32, cout_store, epi, msrc, ldm, ups);
   }
   return hipGetLastError();
 }
+}  // namespace
 
-size_t nn_wgrad_chunks(long long P) { return (size_t)((P + kWgradChunk - 1) / kWgradChunk); }
+hipError_t nn_conv3x3(const uint16_t* x, int ldx, int N, int H, int W, int Cin, const uint16_t* wgt, int Cout, void* y,
+                      int ldy, int y_fp32, int cout_store, int epi, const uint16_t* msrc, int ldm, hipStream_t s) {
+  return conv3x3_launch(x, ldx, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi, msrc, ldm, 0, s);
+}
+
+hipError_t nn_conv3x3_up(const uint16_t* x, int ldx, int N, int H, int W, int Cin, const uint16_t* wgt, int Cout,
+                         void* y, int ldy, int y_fp32, int cout_store, int epi, const uint16_t* msrc, int ldm,
+                         hipStream_t s) {
+  if (H % 2 || W % 2) return hipErrorInvalidValue;
+  return conv3x3_launch(x, ldx, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi, msrc, ldm, 1, s);
+}
+
+// Pixels per split-K chunk: at least kWgradChunk, and large enough that at
+// most kWgradMaxChunks partial sums are written and added up.
+long long wgrad_chunk_pix(long long P) {
+  long long c = (P + kWgradMaxChunks - 1) / kWgradMaxChunks;
+  c = (c + 31) / 32 * 32;
+  return c > kWgradChunk ? c : kWgradChunk;
+}
+
+size_t nn_wgrad_chunks(long long P) {
+  const long long c = wgrad_chunk_pix(P);
+  return (size_t)((P + c - 1) / c);
+}
 
 hipError_t nn_conv3x3_wgrad(const uint16_t* x, int ldx, const uint16_t* dy, int lddy, int N, int H, int W, int Cin,
                             int Cout, float* dw, float* ws, hipStream_t s) {
   const long long P = (long long)N * H * W;
   const int nchunks = (int)nn_wgrad_chunks(P);
+  const int chunk_pix = (int)wgrad_chunk_pix(P);
   const int tco = Cout % 64 == 0 ? 64 : 32, tci = Cin % 64 == 0 ? 64 : 32;
   const dim3 grid(9 * (Cout / tco) * (Cin / tci), nchunks);
   if (tco == 64 && tci == 64)
     hipLaunchKernelGGL((conv3x3_wgrad_kernel<64, 64>), grid, dim3(256), 0, s, x, ldx, dy, lddy, N, H, W, Cin, Cout,
-                       kWgradChunk, ws);
+                       chunk_pix, ws);
   else if (tco == 64)
     hipLaunchKernelGGL((conv3x3_wgrad_kernel<64, 32>), grid, dim3(256), 0, s, x, ldx, dy, lddy, N, H, W, Cin, Cout,
-                       kWgradChunk, ws);
+                       chunk_pix, ws);
   else if (tci == 64)
     hipLaunchKernelGGL((conv3x3_wgrad_kernel<32, 64>), grid, dim3(256), 0, s, x, ldx, dy, lddy, N, H, W, Cin, Cout,
-                       kWgradChunk, ws);
+                       chunk_pix, ws);
   else
     hipLaunchKernelGGL((conv3x3_wgrad_kernel<32, 32>), grid, dim3(256), 0, s, x, ldx, dy, lddy, N, H, W, Cin, Cout,
-                       kWgradChunk, ws);
+                       chunk_pix, ws);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const long long n = 9LL * Cout * Cin;
@@ -593,7 +742,16 @@ hipError_t nn_pack_weights(const float* w, int cin, int cout, uint16_t* wf, uint
   return hipGetLastError();
 }
 
+static bool v8(int c, const void* a, int lda, const void* b, int ldb) {
+  return c % 8 == 0 && lda % 8 == 0 && ldb % 8 == 0 && ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b)) & 15u) == 0;
+}
+
 hipError_t nn_avgpool2(const uint16_t* x, int ldx, int N, int h, int w, int c, uint16_t* y, int ldy, hipStream_t s) {
+  if (v8(c, x, ldx, y, ldy)) {
+    hipLaunchKernelGGL(avgpool2_v8_kernel, dim3(grid_1d((long long)N * (h / 2) * (w / 2) * (c / 8), 256)), dim3(256), 0,
+                       s, x, ldx, N, h, w, c, y, ldy);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(avgpool2_kernel, dim3(grid_1d((long long)N * (h / 2) * (w / 2) * c, 256)), dim3(256), 0, s, x, ldx,
                      N, h, w, c, y, ldy);
   return hipGetLastError();
@@ -601,12 +759,22 @@ hipError_t nn_avgpool2(const uint16_t* x, int ldx, int N, int h, int w, int c, u
 
 hipError_t nn_avgpool2_grad(const uint16_t* g, int ldg, const uint16_t* add, int lda, const uint16_t* msrc, int ldm,
                             int N, int h, int w, int c, uint16_t* dx, int lddx, hipStream_t s) {
+  if (v8(c, g, ldg, dx, lddx) && (!add || v8(c, add, lda, add, lda)) && (!msrc || v8(c, msrc, ldm, msrc, ldm))) {
+    hipLaunchKernelGGL(avgpool2_grad_v8_kernel, dim3(grid_1d((long long)N * h * w * (c / 8), 256)), dim3(256), 0, s, g,
+                       ldg, add, lda, msrc, ldm, N, h, w, c, dx, lddx);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(avgpool2_grad_kernel, dim3(grid_1d((long long)N * h * w * c, 256)), dim3(256), 0, s, g, ldg, add,
                      lda, msrc, ldm, N, h, w, c, dx, lddx);
   return hipGetLastError();
 }
 
 hipError_t nn_upsample2(const uint16_t* x, int ldx, int N, int h, int w, int c, uint16_t* y, int ldy, hipStream_t s) {
+  if (v8(c, x, ldx, y, ldy)) {
+    hipLaunchKernelGGL(upsample2_v8_kernel, dim3(grid_1d((long long)N * 4 * h * w * (c / 8), 256)), dim3(256), 0, s, x,
+                       ldx, N, h, w, c, y, ldy);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(upsample2_kernel, dim3(grid_1d((long long)N * 4 * h * w * c, 256)), dim3(256), 0, s, x, ldx, N, h,
                      w, c, y, ldy);
   return hipGetLastError();
@@ -614,6 +782,11 @@ hipError_t nn_upsample2(const uint16_t* x, int ldx, int N, int h, int w, int c, 
 
 hipError_t nn_upsample2_grad(const uint16_t* g, int ldg, int N, int h, int w, int c, uint16_t* dx, int lddx,
                              hipStream_t s) {
+  if (v8(c, g, ldg, dx, lddx)) {
+    hipLaunchKernelGGL(upsample2_grad_v8_kernel, dim3(grid_1d((long long)N * h * w * (c / 8), 256)), dim3(256), 0, s, g,
+                       ldg, N, h, w, c, dx, lddx);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(upsample2_grad_kernel, dim3(grid_1d((long long)N * h * w * c, 256)), dim3(256), 0, s, g, ldg, N, h,
                      w, c, dx, lddx);
   return hipGetLastError();

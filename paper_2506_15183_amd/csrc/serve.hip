@@ -35,10 +35,14 @@ int tiles_of(int w, int h, int tile) { return tile > 0 ? ((w + tile - 1) / tile)
 
 bool learned(const yoro_serve_options* o) { return o->policy == YORO_SERVE_LEARNED; }
 
+// Device workspace: max_in_flight job-table slots (held until a batch's warp
+// is done), then 2 * max_in_flight hole-count slots (held until its counts
+// are on the host), then the crop plan.  Host staging: the count slots'
+// copies, then the plan.
 struct Layout {
   size_t table;   // per-slot job table bytes
   size_t counts;  // per-slot tile counts bytes (device and host)
-  size_t slot;    // per-slot device bytes
+  int count_slots;
   size_t plan;    // plan bytes (device and host)
   int tiles;      // tiles of the largest frame
 };
@@ -48,7 +52,7 @@ Layout layout(const yoro_serve_options* o, int max_w, int max_h) {
   L.table = up256(yoro_stereo_batch_workspace_bytes(o->max_batch));
   L.tiles = learned(o) ? tiles_of(max_w, max_h, o->tile) : 0;
   L.counts = up256((size_t)o->max_batch * L.tiles * 4);
-  L.slot = L.table + L.counts;
+  L.count_slots = learned(o) ? 2 * o->max_in_flight : 0;
   L.plan = up256((size_t)L.tiles * 16);
   return L;
 }
@@ -66,10 +70,17 @@ bool options_ok(const yoro_serve_options* o) {
 
 // In-flight plain batch.
 struct Batch {
-  int slot;
+  int slot;             // job-table slot (and its warp event)
+  int cslot = -1;       // hole-count slot (and its event), learned policy
   std::vector<int64_t> frames;
+  std::vector<char> counted;  // frames whose holes are counted
   bool warped = false;  // its warp event has been seen
+  bool counting = false;  // hole counts were queued
 };
+
+// While a headset's frames fall back, its hole fraction is re-counted on
+// every kRecount-th frame only (a frame that may be refined is always counted).
+constexpr int kRecount = 8;
 
 }  // namespace
 
@@ -78,13 +89,13 @@ extern "C" {
 size_t yoro_serve_workspace_bytes(const yoro_serve_options* options, int32_t max_w, int32_t max_h) {
   if (!options_ok(options) || max_w <= 0 || max_h <= 0) return 0;
   const Layout L = layout(options, max_w, max_h);
-  return L.slot * options->max_in_flight + L.plan;
+  return L.table * options->max_in_flight + L.counts * L.count_slots + L.plan;
 }
 
 size_t yoro_serve_host_bytes(const yoro_serve_options* options, int32_t max_w, int32_t max_h) {
   if (!options_ok(options) || max_w <= 0 || max_h <= 0) return 0;
   const Layout L = layout(options, max_w, max_h);
-  return L.counts * options->max_in_flight + L.plan;
+  return L.counts * L.count_slots + L.plan;
 }
 
 int32_t yoro_serve_admit(const int64_t* bytes, int32_t n, int64_t budget, int64_t reserved, int32_t* admitted) {
@@ -150,17 +161,17 @@ int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, c
   hipStream_t ls = (hipStream_t)O.learned_stream;
   char* ws = static_cast<char*>(workspace);
   char* hs = static_cast<char*>(host_staging);
-  int32_t* plan_dev = reinterpret_cast<int32_t*>(ws + Lay.slot * O.max_in_flight);
-  int32_t* plan_host = reinterpret_cast<int32_t*>(hs + Lay.counts * O.max_in_flight);
+  char* counts_dev = ws + Lay.table * O.max_in_flight;
+  int32_t* plan_dev = reinterpret_cast<int32_t*>(counts_dev + Lay.counts * Lay.count_slots);
+  int32_t* plan_host = reinterpret_cast<int32_t*>(hs + Lay.counts * Lay.count_slots);
 
   // ev: a batch's warp is done; cev: its hole counts are on the host.
-  std::vector<hipEvent_t> ev(O.max_in_flight, nullptr), cev(O.max_in_flight, nullptr);
+  std::vector<hipEvent_t> ev(O.max_in_flight, nullptr), cev(Lay.count_slots, nullptr);
   hipEvent_t lev = nullptr;
   hipError_t he = hipSuccess;
-  for (int i = 0; i < O.max_in_flight && he == hipSuccess; ++i) {
-    he = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
-    if (he == hipSuccess) he = hipEventCreateWithFlags(&cev[i], hipEventDisableTiming);
-  }
+  for (int i = 0; i < O.max_in_flight && he == hipSuccess; ++i) he = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
+  for (int i = 0; i < Lay.count_slots && he == hipSuccess; ++i)
+    he = hipEventCreateWithFlags(&cev[i], hipEventDisableTiming);
   if (he == hipSuccess) he = hipEventCreateWithFlags(&lev, hipEventDisableTiming);
 
   std::vector<int> next_out(n_headsets, 0);
@@ -168,12 +179,14 @@ int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, c
   // frame whose headset was last above the threshold is released as soon as
   // its warp is done (fallback predicted); the others wait for their counts.
   std::vector<double> last_frac(n_headsets, -1.0);
+  std::vector<int> since_count(n_headsets, 0);
   // Last arrival written into each headset's output set: a finished frame is
   // refined only while its output still holds it.
   std::vector<int64_t> last_in(n_headsets * YORO_SERVE_MAX_OUTPUTS, -1);
   std::vector<int> out_of(n_arrivals, 0);
-  std::vector<int> free_slots;
+  std::vector<int> free_slots, free_cslots;
   for (int i = O.max_in_flight - 1; i >= 0; --i) free_slots.push_back(i);
+  for (int i = Lay.count_slots - 1; i >= 0; --i) free_cslots.push_back(i);
   std::deque<int64_t> pending;
   std::deque<Batch> inflight;
   std::vector<int64_t> in_batch(n_headsets, -1);
@@ -246,38 +259,73 @@ int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, c
       }
       ++next;
     }
-    // Completed batches (one stream: they finish in order).
-    while (!inflight.empty() && status == YORO_OK) {
-      Batch& B = inflight.front();
-      if (!B.warped) {
-        const hipError_t q = hipEventQuery(ev[B.slot]);
-        if (q == hipErrorNotReady) break;
-        if (q != hipSuccess) {
-          status = serve_fail(YORO_ERR_DEVICE, "%s: batch: %s", who, hipGetErrorString(q));
+    // Warps done (one stream: they finish in order).  A batch's job-table
+    // slot is free as soon as its warp is; under the plain policy, and for
+    // frames whose headset predicts a fallback, the result is final then.
+    for (Batch& B : inflight) {
+      if (B.warped) continue;
+      const hipError_t q = hipEventQuery(ev[B.slot]);
+      if (q == hipErrorNotReady) break;
+      if (q != hipSuccess) {
+        status = serve_fail(YORO_ERR_DEVICE, "%s: batch: %s", who, hipGetErrorString(q));
+        break;
+      }
+      const int64_t tn = now_ns();
+      B.counted.assign(B.frames.size(), 0);
+      for (size_t i = 0; i < B.frames.size(); ++i) {
+        const int64_t k = B.frames[i];
+        const int h = arrivals[k].headset;
+        if (!L_on) {
+          results[k].path = YORO_PATH_PLAIN, results[k].done_ns = tn;
+        } else if (last_frac[h] > (double)O.learned_max_hole_fraction) {
+          results[k].path = YORO_PATH_FALLBACK, results[k].done_ns = tn;
+          if (++since_count[h] >= kRecount) B.counted[i] = 1, since_count[h] = 0;
+        } else {
+          B.counted[i] = 1, since_count[h] = 0;
+        }
+      }
+      B.warped = true;
+      free_slots.push_back(B.slot);
+      bool any = false;
+      for (char c : B.counted) any |= c != 0;
+      if (L_on && any) {
+        // Count the holes (on the learned stream) only now that the frames'
+        // completion has been taken, so issuing the work delays no one.
+        uint32_t* cd = reinterpret_cast<uint32_t*>(counts_dev + Lay.counts * B.cslot);
+        hipError_t e = hipSuccess;
+        for (size_t i = 0; i < B.frames.size() && e == hipSuccess; ++i) {
+          if (!B.counted[i]) continue;
+          const int64_t k = B.frames[i];
+          const yoro_serve_headset& H = headsets[arrivals[k].headset];
+          e = yoro::nn_tile_holes(H.dst_mask[out_of[k]], H.width, H.height, O.tile, cd + i * Lay.tiles, ls);
+        }
+        if (e == hipSuccess)
+          e = hipMemcpyAsync(hs + Lay.counts * B.cslot, cd, B.frames.size() * Lay.tiles * 4, hipMemcpyDeviceToHost,
+                             ls);
+        if (e == hipSuccess) e = hipEventRecord(cev[B.cslot], ls);
+        if (e != hipSuccess) {
+          status = serve_fail(YORO_ERR_DEVICE, "%s: hole counts: %s", who, hipGetErrorString(e));
           break;
         }
-        const int64_t tn = now_ns();
-        for (int64_t k : B.frames) {
-          if (!L_on) {
-            results[k].path = YORO_PATH_PLAIN, results[k].done_ns = tn;
-          } else if (last_frac[arrivals[k].headset] > (double)O.learned_max_hole_fraction) {
-            results[k].path = YORO_PATH_FALLBACK, results[k].done_ns = tn;
-          }
-        }
-        B.warped = true;
+        B.counting = true;
       }
-      if (L_on) {
-        const hipError_t q = hipEventQuery(cev[B.slot]);
+    }
+    // Hole counts on the host (learned stream: in order too).
+    while (!inflight.empty() && status == YORO_OK && inflight.front().warped) {
+      Batch& B = inflight.front();
+      if (L_on && B.counting) {
+        const hipError_t q = hipEventQuery(cev[B.cslot]);
         if (q == hipErrorNotReady) break;
         if (q != hipSuccess) {
           status = serve_fail(YORO_ERR_DEVICE, "%s: hole counts: %s", who, hipGetErrorString(q));
           break;
         }
         const int64_t tn = now_ns();
-        const uint32_t* counts = reinterpret_cast<const uint32_t*>(hs + Lay.counts * B.slot);
+        const uint32_t* counts = reinterpret_cast<const uint32_t*>(hs + Lay.counts * B.cslot);
         for (size_t i = 0; i < B.frames.size(); ++i) {
           const int64_t k = B.frames[i];
           const yoro_serve_headset& H = headsets[arrivals[k].headset];
+          if (!B.counted[i]) continue;
           if (results[k].done_ns >= 0) {  // released at the warp: keep the statistics only
             int64_t holes = 0;
             for (int t = 0, nt = tiles_of(H.width, H.height, O.tile); t < nt; ++t) holes += counts[i * Lay.tiles + t];
@@ -291,7 +339,7 @@ int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, c
           last_frac[arrivals[k].headset] = (double)results[k].holes / ((double)H.width * H.height);
         }
       }
-      free_slots.push_back(B.slot);
+      if (L_on) free_cslots.push_back(B.cslot);
       inflight.pop_front();
     }
     // The refinement in flight.
@@ -305,10 +353,14 @@ int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, c
       }
     }
     // Launch what has arrived.
-    while (status == YORO_OK && !pending.empty() && !free_slots.empty()) {
+    while (status == YORO_OK && !pending.empty() && !free_slots.empty() && (!L_on || !free_cslots.empty())) {
       Batch B;
       B.slot = free_slots.back();
       free_slots.pop_back();
+      if (L_on) {
+        B.cslot = free_cslots.back();
+        free_cslots.pop_back();
+      }
       jobs.clear();
       bool wait_learned = false;
       // At most one frame per headset per batch (its outputs rotate, so two
@@ -348,20 +400,12 @@ int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, c
         status = serve_fail(YORO_ERR_DEVICE, "%s: wait: %s", who, hipGetErrorString(e));
         break;
       }
-      const int32_t st = yoro_stereo_batch(jobs.data(), (int32_t)jobs.size(), ws + Lay.slot * B.slot, Lay.table, s);
+      const int32_t st = yoro_stereo_batch(jobs.data(), (int32_t)jobs.size(), ws + Lay.table * B.slot, Lay.table, s);
       if (st != YORO_OK) {
         status = st;
         break;
       }
       e = hipEventRecord(ev[B.slot], s);
-      if (L_on && e == hipSuccess) {
-        uint32_t* cd = reinterpret_cast<uint32_t*>(ws + Lay.slot * B.slot + Lay.table);
-        for (size_t i = 0; i < jobs.size() && e == hipSuccess; ++i)
-          e = yoro::nn_tile_holes(jobs[i].dst_mask, jobs[i].width, jobs[i].height, O.tile, cd + i * Lay.tiles, s);
-        if (e == hipSuccess)
-          e = hipMemcpyAsync(hs + Lay.counts * B.slot, cd, jobs.size() * Lay.tiles * 4, hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipEventRecord(cev[B.slot], s);
-      }
       if (e != hipSuccess) {
         status = serve_fail(YORO_ERR_DEVICE, "%s: batch launch: %s", who, hipGetErrorString(e));
         break;

@@ -83,11 +83,17 @@ hipError_t launch_hole_sse(const uint32_t* rgba, const uint32_t* ref, const uint
 void set_last_error(const char* msg);
 
 // Learned-fill kernels (defined in nn.hip).  bf16 tensors are raw uint16_t.
-constexpr int kWgradChunk = 2048;  // pixels per split-K chunk of the weight gradient
+constexpr int kWgradChunk = 2048;      // minimum pixels per split-K chunk of the weight gradient
+constexpr int kWgradMaxChunks = 128;  // at most this many chunk partial sums
 constexpr int kLossBlocks = 512;   // blocks (and partial sums) of the L1 loss
 size_t nn_wgrad_chunks(long long P);
 hipError_t nn_conv3x3(const uint16_t* x, int ldx, int N, int H, int W, int Cin, const uint16_t* wgt, int Cout, void* y,
                       int ldy, int y_fp32, int cout_store, int epi, const uint16_t* msrc, int ldm, hipStream_t s);
+// The same convolution applied to the nearest x2 upsampling of x (x is
+// N x H/2 x W/2; H, W even), read in place.
+hipError_t nn_conv3x3_up(const uint16_t* x, int ldx, int N, int H, int W, int Cin, const uint16_t* wgt, int Cout,
+                         void* y, int ldy, int y_fp32, int cout_store, int epi, const uint16_t* msrc, int ldm,
+                         hipStream_t s);
 hipError_t nn_conv3x3_wgrad(const uint16_t* x, int ldx, const uint16_t* dy, int lddy, int N, int H, int W, int Cin,
                             int Cout, float* dw, float* ws, hipStream_t s);
 hipError_t nn_pack_weights(const float* w, int cin, int cout, uint16_t* wf, uint16_t* wb, hipStream_t s);

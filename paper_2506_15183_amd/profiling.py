@@ -2,7 +2,7 @@
 
 Workflow (each step its own process; the GPU steps under rocprofv3):
 
-  1. rocprofv3 --kernel-trace --stats -d OUT/trace -o t -- python bench.py --steps 20 --warmup 5 --no-cpu-baseline
+  1. rocprofv3 --kernel-trace --stats -d OUT/trace -o t -- python bench.py --no-cpu-baseline --no-single-frame --serve-seconds 0 --eval-frames 0
   2. rocprofv3 --pmc FETCH_SIZE -d OUT/fetch -o f -- python -m paper_2506_15183_amd.profiling counters
   3. rocprofv3 --pmc WRITE_SIZE -d OUT/write -o w -- python -m paper_2506_15183_amd.profiling counters
   4. python -m paper_2506_15183_amd.profiling summarize OUT > profiles/<kernel>_<workload>.md
@@ -60,6 +60,97 @@ def counters_workload(launches: int = 5) -> None:
     print(f"counters workload done: {launches} warp launches, {launches} copies of {COPY_BYTES} B", flush=True)
 
 
+def learned_workload(frames: int = 4, steps: int = 4) -> None:
+    """Whole-frame learned fill of a 1832 x 1920 frame, then training steps on
+    16 windows of 256 x 256 (seeded synthetic inputs, committed weights)."""
+    import numpy as np
+    import torch
+
+    from . import train, unet
+
+    net = unet.UNet("cuda", params=train.load_weights(train.DEFAULT_WEIGHTS))
+    rng = np.random.default_rng(0)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    h, w = 1920, 1832
+    rgba = T(rng.integers(0, 256, (1, h, w, 4), dtype=np.uint8))
+    depth = T(np.exp(rng.uniform(np.log(0.3), np.log(50), (1, h, w))).astype(np.float32))
+    mask = T((rng.random((1, h, w)) < 0.2).astype(np.uint8))
+    out = torch.empty_like(rgba)
+    for _ in range(frames):
+        net.fill_native(rgba, depth, mask, out=out)
+    n = 16
+    batch = [T(rng.integers(0, 256, (n, 256, 256, 4), dtype=np.uint8)),
+             T(np.exp(rng.uniform(np.log(0.3), np.log(50), (n, 256, 256))).astype(np.float32)),
+             T((rng.random((n, 256, 256)) < 0.2).astype(np.uint8)),
+             T(rng.integers(0, 256, (n, 256, 256, 4), dtype=np.uint8))]
+    for _ in range(steps):
+        net.train_step(*batch)
+    torch.cuda.synchronize()
+    print(f"learned workload done: {frames} frames, {steps} training steps", flush=True)
+
+
+def summarize_learned(trace_dir: str) -> str:
+    """Per-layer kernel durations of the last whole-frame forward pass and the
+    kernel totals of the last training step, from a kernel trace of
+    ``learned_workload``."""
+    c = _db(trace_dir)
+    rows = list(c.execute("select name, duration from kernels order by start"))
+
+    def short(n):
+        n = n.replace("void ", "").replace("yoro::(anonymous namespace)::", "")
+        return n.split("(")[0]
+
+    starts = [i for i, (n, _) in enumerate(rows) if short(n).startswith("unet_input")]
+    fwd_at = [i for i in starts if i + 1 < len(rows)]
+    # The whole-frame forwards come first, the training steps after them.
+    lines = ["# Learned fill kernels: one 1832x1920 forward pass and one training step", "",
+             "Commands (from the repository root, on one MI355X; OUT=gpurun_out/prof_learned):", "", "```",
+             "rocprofv3 --kernel-trace --stats -d $OUT -o l -- python -m paper_2506_15183_amd.profiling learned",
+             "python -m paper_2506_15183_amd.profiling summarize-learned $OUT", "```", "",
+             "## Forward pass (last whole-frame fill), in order", "",
+             "FLOPs per convolution over the channels the kernels compute (padded to 32, the head's 16-wide tile).",
+             "", "| # | step | kernel | us | TFLOP/s |", "|---|---|---|---|---|"]
+    steps = ["input", "e0a", "e0b", "pool", "e1a", "e1b", "pool", "e2a", "e2b", "pool", "e3a", "e3b",
+             "d2a (upsampling load)", "d2b", "d2c", "d1a (upsampling load)", "d1b", "d1c", "d0a (upsampling load)",
+             "d0b", "d0c", "head", "composite"]
+    lev = {"e0": 0, "e1": 1, "e2": 2, "e3": 3, "d2": 2, "d1": 1, "d0": 0, "he": 0}
+    cin = {"e0a": 32, "e0b": 32, "e1a": 32, "e1b": 64, "e2a": 64, "e2b": 128, "e3a": 128, "e3b": 256, "d2a": 256,
+           "d2b": 256, "d2c": 128, "d1a": 128, "d1b": 128, "d1c": 64, "d0a": 64, "d0b": 64, "d0c": 32, "head": 32}
+    cout = {"e0a": 32, "e0b": 32, "e1a": 64, "e1b": 64, "e2a": 128, "e2b": 128, "e3a": 256, "e3b": 256, "d2a": 128,
+            "d2b": 128, "d2c": 128, "d1a": 64, "d1b": 64, "d1c": 64, "d0a": 32, "d0b": 32, "d0c": 32, "head": 16}
+    i0 = fwd_at[3] if len(fwd_at) > 4 else fwd_at[0]
+    total = 0.0
+    k = 0
+    for name, dur in rows[i0:]:
+        nm = short(name)
+        total += dur
+        st = steps[k] if k < len(steps) else "?"
+        key = st.split(" ")[0]
+        tf = ""
+        if key in cin:
+            px = (1920 >> lev[key[:2]]) * (1832 >> lev[key[:2]])
+            tf = f"{2.0 * 9 * cin[key] * cout[key] * px / dur / 1e3:.0f}"
+        lines.append(f"| {k} | {st} | `{nm}` | {dur / 1000:.1f} | {tf} |")
+        k += 1
+        if nm.startswith("composite"):
+            break
+    lines += ["", f"forward total: {total / 1000:.1f} us", "", "## Training step (last), kernel totals", "",
+              "| kernel | calls | us |", "|---|---|---|"]
+    last = fwd_at[-1]
+    agg = {}
+    for name, dur in rows[last:]:
+        nm = short(name)
+        if nm.startswith("at::") or "rocclr" in nm:
+            continue
+        a = agg.setdefault(nm, [0, 0.0])
+        a[0] += 1
+        a[1] += dur
+    for nm, (cnt, d) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+        lines.append(f"| `{nm}` | {cnt} | {d / 1000:.1f} |")
+    lines += ["", f"training step total: {sum(v[1] for v in agg.values()) / 1000:.1f} us", ""]
+    return "\n".join(lines)
+
+
 def _db(path_dir: str) -> sqlite3.Connection:
     files = glob.glob(os.path.join(path_dir, "**", "*_results.db"), recursive=True)
     if not files:
@@ -114,7 +205,7 @@ def summarize(out_dir: str, pixels: int, algo_bytes_per_px: int = 12) -> str:
         "Commands (from the repository root, on one MI355X; OUT=gpurun_out/prof):",
         "",
         "```",
-        "rocprofv3 --kernel-trace --stats -d $OUT/trace -o t -- python bench.py --steps 20 --warmup 5 --no-cpu-baseline",
+        "rocprofv3 --kernel-trace --stats -d $OUT/trace -o t -- python bench.py --no-cpu-baseline --no-single-frame --serve-seconds 0 --eval-frames 0",
         "rocprofv3 --pmc FETCH_SIZE -d $OUT/fetch -o f -- python -m paper_2506_15183_amd.profiling counters",
         "rocprofv3 --pmc WRITE_SIZE -d $OUT/write -o w -- python -m paper_2506_15183_amd.profiling counters",
         "python -m paper_2506_15183_amd.profiling summarize $OUT",
@@ -163,6 +254,10 @@ def read_summary(path: str):
 if __name__ == "__main__":
     if len(sys.argv) >= 2 and sys.argv[1] == "counters":
         counters_workload()
+    elif len(sys.argv) >= 2 and sys.argv[1] == "learned":
+        learned_workload()
+    elif len(sys.argv) >= 3 and sys.argv[1] == "summarize-learned":
+        print(summarize_learned(sys.argv[2]))
     elif len(sys.argv) >= 3 and sys.argv[1] == "summarize":
         sys.path.insert(0, os.path.dirname(HERE))
         from paper_2506_15183_amd.scenes import config3_frames
