@@ -37,6 +37,30 @@
  *   mask 2).  Mask values: 0 hit, 1 hole (filled, or left empty when no
  *   fill is asked for), 2 hole with no hit in its row.
  *
+ *   Patcher fill (Section 7, Algorithm 3 with its weight function,
+ *   Equation 7), mode OR_FILL_PATCHER.  The listing mixes coordinate spaces
+ *   (intermediate-buffer records and colour samples at the same index, a uv
+ *   coordinate against pixel widths) and is one-dimensional although the
+ *   kernel is said to be h = 3 rows high, so it is taken as follows.  For a
+ *   hole at (x, y) with nearest row hits L and R (as above, L = -1 or R = W
+ *   when absent) the kernel starts at the nearest-background hit e chosen as
+ *   above, with depth ze, and runs outward from the hole, away from it, over
+ *   n = min(R - L - 1, 16) columns (the disocclusion width, capped; past 16
+ *   accepted samples the remaining weight is below 2^-16) and, per column,
+ *   rows y, y - 1, y + 1.  A sample is used only if it lies in the frame, is
+ *   a hit (mask 0, never a filled hole) and is not nearer than the edge
+ *   (depth >= ze: the foreground skip).  With t = |x - e| / (R - L - 1),
+ *   the position in the disocclusion (u - r_x) / r_z measured from the
+ *   background edge (in the paper's own orientation, the left eye made
+ *   from the right with the background on the left, r_x is that edge; the
+ *   distance from e keeps the two eyes mirror images), each used sample takes
+ *   w = w_rem / 2 + (0.3 w_rem) t of the remaining weight w_rem (which
+ *   starts at 1): c_acc += C w, w_rem -= w.  The hole gets
+ *   clamp(rint(c_acc / (1 - w_rem))) per RGB channel, the edge's alpha and
+ *   depth, mask 1; a hole with no hit in its row stays empty (mask 2).  All
+ *   of it in FP32 in exactly this order (it decides 8-bit values).  The
+ *   edge itself is always the first sample, so the division is never by 0.
+ *
  * Rounding reading: d = roundf(q), halfway cases away from zero, with
  * q = (B*f)/z, one FP32 multiply then one correctly rounded FP32 division.
  * Depths that are NaN, zero or negative carry no geometry and are skipped; a
@@ -55,7 +79,8 @@
 #endif
 
 enum { OR_TARGET_RIGHT = 0, OR_TARGET_LEFT = 1 };
-enum { OR_FILL_NONE = 0, OR_FILL_NEAREST_BG = 1, OR_FILL_SIDE_ONLY = 101 };
+enum { OR_FILL_NONE = 0, OR_FILL_NEAREST_BG = 1, OR_FILL_PATCHER = 3, OR_FILL_SIDE_ONLY = 101 };
+#define OR_PATCH_MAX_COLS 16
 
 #define OR_EMPTY 0xFFFFFFFFFFFFFFFFull
 
@@ -120,6 +145,78 @@ static void fill_row(uint8_t* rgba, float* depth, uint8_t* mask, const uint8_t* 
   }
 }
 
+/* Patcher value of the hole at (x, y) of a frame whose hits have mask 0. */
+static void patcher_pixel(const uint8_t* rgba, const float* depth, const uint8_t* mask, int32_t width,
+                          int32_t height, int32_t x, int32_t y, int32_t s, uint8_t* out_rgba, float* out_z,
+                          uint8_t* out_m) {
+  const size_t row = (size_t)y * (size_t)width;
+  int32_t L = x - 1, R = x + 1;
+  while (L >= 0 && mask[row + L] != 0) --L;
+  while (R < width && mask[row + R] != 0) ++R;
+  if (L < 0 && R >= width) {
+    memset(out_rgba, 0, 4);
+    *out_z = INFINITY;
+    *out_m = 2;
+    return;
+  }
+  int32_t e;
+  if (L < 0) e = R;
+  else if (R >= width) e = L;
+  else if (depth[row + L] > depth[row + R]) e = L;
+  else if (depth[row + R] > depth[row + L]) e = R;
+  else e = (s < 0) ? R : L;
+  const float ze = depth[row + e];
+  const int32_t rz = R - L - 1;
+  const float t = (float)abs(x - e) / (float)rz;
+  const int32_t dir = (e == R) ? 1 : -1;
+  const int32_t n = rz < OR_PATCH_MAX_COLS ? rz : OR_PATCH_MAX_COLS;
+  static const int32_t dys[3] = {0, -1, 1};
+  float w_rem = 1.0f, acc[3] = {0.0f, 0.0f, 0.0f};
+  for (int32_t k = 0; k < n; ++k) {
+    const int32_t cx = e + dir * k;
+    if (cx < 0 || cx >= width) break;
+    for (int32_t j = 0; j < 3; ++j) {
+      const int32_t cy = y + dys[j];
+      if (cy < 0 || cy >= height) continue;
+      const size_t p = (size_t)cy * (size_t)width + (size_t)cx;
+      if (mask[p] != 0) continue;    /* only resolved hits */
+      if (depth[p] < ze) continue;   /* skip foreground */
+      const float a = w_rem * 0.5f;
+      const float b = 0.3f * w_rem;
+      const float w = a + b * t;
+      for (int c = 0; c < 3; ++c) acc[c] = acc[c] + (float)rgba[4 * p + c] * w;
+      w_rem = w_rem - w;
+    }
+  }
+  const float norm = 1.0f - w_rem;
+  for (int c = 0; c < 3; ++c) {
+    float v = rintf(acc[c] / norm);
+    v = v < 0.0f ? 0.0f : (v > 255.0f ? 255.0f : v);
+    out_rgba[c] = (uint8_t)v;
+  }
+  out_rgba[3] = rgba[4 * (row + (size_t)e) + 3];
+  *out_z = ze;
+  *out_m = 1;
+}
+
+/* Patcher over a whole frame, in place: holes (mask != 0) are refilled from
+ * hits only, so the order does not matter. */
+static void patcher_frame(uint8_t* rgba, float* depth, uint8_t* mask, int32_t width, int32_t height, int32_t s) {
+  for (int32_t y = 0; y < height; ++y)
+    for (int32_t x = 0; x < width; ++x) {
+      const size_t i = (size_t)y * (size_t)width + (size_t)x;
+      if (mask[i] == 0) continue;
+      uint8_t c[4];
+      float z;
+      uint8_t m;
+      patcher_pixel(rgba, depth, mask, width, height, x, y, s, c, &z, &m);
+      /* Written after all reads of this pixel; other holes read hits only. */
+      memcpy(&rgba[4 * i], c, 4);
+      depth[i] = z;
+      mask[i] = m;
+    }
+}
+
 /*
  * Reproject one frame.  src_rgba: H*W*4 bytes; src_depth: H*W floats;
  * dst_rgba: H*W*4; dst_depth and dst_mask may be NULL.  Returns 0, or -1 on
@@ -130,6 +227,18 @@ int oracle_reproject(const uint8_t* src_rgba, const float* src_depth, int32_t wi
                      uint8_t* dst_rgba, float* dst_depth, uint8_t* dst_mask, int32_t nthreads) {
   if (width <= 0 || height <= 0 || !src_rgba || !src_depth || !dst_rgba) return -1;
   if (target_eye != OR_TARGET_RIGHT && target_eye != OR_TARGET_LEFT) return -1;
+  if (fill_mode == OR_FILL_PATCHER) {
+    /* The Patcher reads neighbouring rows: warp every row first, then fill. */
+    const size_t n = (size_t)width * (size_t)height;
+    float* z = dst_depth ? dst_depth : (float*)malloc(sizeof(float) * n);
+    uint8_t* m = dst_mask ? dst_mask : (uint8_t*)malloc(n);
+    int rc = oracle_reproject(src_rgba, src_depth, width, height, baseline_m, focal_px, target_eye, OR_FILL_NONE,
+                              dst_rgba, z, m, nthreads);
+    if (rc == 0) patcher_frame(dst_rgba, z, m, width, height, target_eye == OR_TARGET_RIGHT ? -1 : +1);
+    if (!dst_depth) free(z);
+    if (!dst_mask) free(m);
+    return rc;
+  }
   const float bf = baseline_m * focal_px;
   const int32_t s = (target_eye == OR_TARGET_RIGHT) ? -1 : +1;
 #ifdef _OPENMP
@@ -205,6 +314,10 @@ int oracle_fill_holes(uint8_t* rgba, float* depth, uint8_t* mask, int32_t width,
   if (target_eye != OR_TARGET_RIGHT && target_eye != OR_TARGET_LEFT) return -1;
   if (fill_mode == OR_FILL_NONE) return 0;
   const int32_t s = (target_eye == OR_TARGET_RIGHT) ? -1 : +1;
+  if (fill_mode == OR_FILL_PATCHER) {
+    patcher_frame(rgba, depth, mask, width, height, s);
+    return 0;
+  }
   uint8_t* hit = (uint8_t*)malloc((size_t)width);
   float* zr = (float*)malloc(sizeof(float) * (size_t)width);
   uint8_t* col = (uint8_t*)malloc(4 * (size_t)width);

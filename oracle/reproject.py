@@ -17,7 +17,7 @@ SRC = os.path.join(_HERE, "reproject.c")
 LIB = os.path.join(_HERE, "liboracle_reproject.so")
 
 TARGET_RIGHT, TARGET_LEFT = 0, 1
-FILL_NONE, FILL_NEAREST_BG, FILL_SIDE_ONLY = 0, 1, 101
+FILL_NONE, FILL_NEAREST_BG, FILL_PATCHER, FILL_SIDE_ONLY = 0, 1, 3, 101
 
 CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared"]
 
