@@ -68,7 +68,17 @@ typedef enum yoro_fill_mode {
    * opposite the shift (right for YORO_TARGET_RIGHT, left for
    * YORO_TARGET_LEFT); with one neighbour take it (Section 5 O2; Section 7,
    * Patcher figure). */
-  YORO_FILL_NEAREST_BG = 1
+  YORO_FILL_NEAREST_BG = 1,
+  /* The weighted Patcher (Section 7, Algorithm 3 with Equation 7): from the
+   * nearest-background hit e of a hole at x (chosen as above, nearest hits L
+   * and R), samples outward from e over min(R - L - 1, 16) columns and rows
+   * y, y-1, y+1 that are hits not nearer than e; each takes
+   * w_rem/2 + 0.3 w_rem |x - e| / (R - L - 1) of the remaining weight w_rem
+   * (starting at 1); the hole gets rint(sum(C w) / (1 - w_rem)) per RGB
+   * channel in FP32, e's alpha and depth, mask 1.  Reads neighbouring rows,
+   * so yoro_reproject needs dst_depth and dst_mask for it and the batched
+   * call does not take it (YORO_ERR_UNSUPPORTED). */
+  YORO_FILL_PATCHER = 3
 } yoro_fill_mode;
 
 typedef enum yoro_status {

@@ -79,7 +79,7 @@ int32_t check_frame(const void* src_rgba, const void* src_depth, int32_t width, 
                 (double)baseline_m, (double)focal_px);
   if (target_eye != YORO_TARGET_RIGHT && target_eye != YORO_TARGET_LEFT)
     return fail(YORO_ERR_INVALID_ARG, "%s: unknown target eye %d", who, target_eye);
-  if (fill_mode != YORO_FILL_NONE && fill_mode != YORO_FILL_NEAREST_BG)
+  if (fill_mode != YORO_FILL_NONE && fill_mode != YORO_FILL_NEAREST_BG && fill_mode != YORO_FILL_PATCHER)
     return fail(YORO_ERR_INVALID_ARG, "%s: unknown fill mode %d", who, fill_mode);
   if (!aligned4(src_rgba) || !aligned4(src_depth) || !aligned4(dst_rgba) || (dst_depth && !aligned4(dst_depth)))
     return fail(YORO_ERR_INVALID_ARG, "%s: RGBA and depth pointers must be 4-byte aligned", who);
@@ -140,12 +140,20 @@ int32_t yoro_reproject(const uint8_t* src_rgba, const float* src_depth, int32_t 
     int32_t st = check_frame(src_rgba, src_depth, width, height, baseline_m, focal_px, target_eye, fill_mode,
                              dst_rgba, dst_depth, dst_mask, "yoro_reproject");
     if (st != YORO_OK) return st;
+    const bool patcher = fill_mode == YORO_FILL_PATCHER;
+    if (patcher && (!dst_depth || !dst_mask))
+      return fail(YORO_ERR_INVALID_ARG, "yoro_reproject: the Patcher fill needs dst_depth and dst_mask");
+    // The Patcher reads neighbouring rows: warp every row first, then fill.
     yoro_job j{src_rgba, src_depth, dst_rgba, dst_depth, dst_mask, width, height, baseline_m, focal_px,
-               target_eye, fill_mode};
+               target_eye, patcher ? (int32_t)YORO_FILL_NONE : fill_mode};
     const int ppt = pick_ppt(width);
     if (ppt < 0) return fail(YORO_ERR_UNSUPPORTED, "yoro_reproject: width %d too wide", width);
     const int grid = grid_for(height, yoro::warp_blocks_per_cu(width, false));
     hipError_t e = yoro::launch_warp_single(make_job(j, 0), ppt, grid, (hipStream_t)hip_stream);
+    if (e == hipSuccess && patcher)
+      e = yoro::launch_fill(reinterpret_cast<uint32_t*>(dst_rgba), dst_depth, dst_mask, width, height, target_eye,
+                            fill_mode, ppt, grid_for(height, yoro::fill_blocks_per_cu(width, fill_mode)),
+                            (hipStream_t)hip_stream);
     if (e != hipSuccess) return fail(YORO_ERR_DEVICE, "yoro_reproject: launch failed: %s", hipGetErrorString(e));
     return ok();
   } catch (...) {
@@ -163,7 +171,7 @@ int32_t yoro_fill_holes(uint8_t* rgba, float* depth, uint8_t* mask, int32_t widt
       return fail(YORO_ERR_UNSUPPORTED, "yoro_fill_holes: %dx%d exceeds the supported size", width, height);
     if (target_eye != YORO_TARGET_RIGHT && target_eye != YORO_TARGET_LEFT)
       return fail(YORO_ERR_INVALID_ARG, "yoro_fill_holes: unknown target eye %d", target_eye);
-    if (fill_mode != YORO_FILL_NONE && fill_mode != YORO_FILL_NEAREST_BG)
+    if (fill_mode != YORO_FILL_NONE && fill_mode != YORO_FILL_NEAREST_BG && fill_mode != YORO_FILL_PATCHER)
       return fail(YORO_ERR_INVALID_ARG, "yoro_fill_holes: unknown fill mode %d", fill_mode);
     if (!aligned4(rgba) || !aligned4(depth))
       return fail(YORO_ERR_INVALID_ARG, "yoro_fill_holes: rgba and depth must be 4-byte aligned");
@@ -174,7 +182,7 @@ int32_t yoro_fill_holes(uint8_t* rgba, float* depth, uint8_t* mask, int32_t widt
       return fail(YORO_ERR_INVALID_ARG, "yoro_fill_holes: buffers overlap");
     if (fill_mode == YORO_FILL_NONE) return ok();
     const int ppt = pick_ppt(width);
-    const int grid = grid_for(height, yoro::fill_blocks_per_cu(width));
+    const int grid = grid_for(height, yoro::fill_blocks_per_cu(width, fill_mode));
     hipError_t e = yoro::launch_fill(reinterpret_cast<uint32_t*>(rgba), depth, mask, width, height, target_eye,
                                      fill_mode, ppt, grid, (hipStream_t)hip_stream);
     if (e != hipSuccess) return fail(YORO_ERR_DEVICE, "yoro_fill_holes: launch failed: %s", hipGetErrorString(e));
@@ -210,6 +218,8 @@ int32_t yoro_stereo_batch_prepare(const yoro_job* jobs, int32_t n_jobs, void* de
       int32_t st = check_frame(j.src_rgba, j.src_depth, j.width, j.height, j.baseline_m, j.focal_px, j.target_eye,
                                j.fill_mode, j.dst_rgba, j.dst_depth, j.dst_mask, who);
       if (st != YORO_OK) return st;
+      if (j.fill_mode == YORO_FILL_PATCHER)
+        return fail(YORO_ERR_UNSUPPORTED, "%s: the Patcher fill reads neighbouring rows; use yoro_reproject", who);
       const uintptr_t n = (uintptr_t)j.width * (uintptr_t)j.height;
       ranges.push_back({(uintptr_t)j.src_rgba, (uintptr_t)j.src_rgba + 4 * n, false});
       ranges.push_back({(uintptr_t)j.src_depth, (uintptr_t)j.src_depth + 4 * n, false});

@@ -416,6 +416,111 @@ __global__ __launch_bounds__(kThreads) void fill_kernel(uint32_t* rgba, float* d
 }
 
 // ---------------------------------------------------------------------------
+// Patcher fill of a warped frame, in place (Section 7, Algorithm 3 with the
+// weight function of Equation 7).  For a hole at (x, y): the nearest hits L
+// and R of its row and the nearest-background edge e among them (as in the
+// plain fill), then samples outward from e, away from the hole, over
+// n = min(R - L - 1, kPatchCols) columns and rows y, y - 1, y + 1; a sample
+// counts if it is a hit not nearer than the edge.  Each counted sample takes
+// w = w_rem/2 + 0.3 w_rem t of the remaining weight, t = |x - e| / (R - L - 1)
+// the hole's position measured from the edge, and the hole becomes
+// rint(sum(C w) / (1 - w_rem)) per channel, with the edge's alpha and depth.
+// FP32 in exactly that order (the arithmetic decides 8-bit values).  Row y
+// is staged in LDS; rows y +- 1 are read from memory, hits only (a hole's
+// mask stays nonzero when it is filled, so in place is safe).
+constexpr int kPatchCols = 16;
+
+template <int PPT>
+__global__ __launch_bounds__(kThreads) void patcher_kernel(uint32_t* rgba, float* depth, uint8_t* mask, int W, int H,
+                                                           int target_eye, int wl) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint32_t* col = reinterpret_cast<uint32_t*>(smem);
+  uint32_t* zs = col + wl;  // depth bits
+  uint64_t* hm = reinterpret_cast<uint64_t*>(zs + wl);
+  const int tid = threadIdx.x;
+  const bool target_right = target_eye == 0;
+  const int nw = (W + 63) >> 6;
+  for (int y = blockIdx.x; y < H; y += gridDim.x) {
+    const size_t row = (size_t)y * (size_t)W;
+    uint8_t m8[PPT];
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      const int x = tid + i * kThreads;
+      m8[i] = 1;
+      if (x < W) {
+        m8[i] = mask[row + x];
+        col[x] = rgba[row + x];
+        zs[x] = __float_as_uint(depth[row + x]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      const int x = tid + i * kThreads;
+      const uint64_t m = __ballot(x < W && m8[i] == 0);
+      if ((tid & 63) == 0 && x < W) hm[x >> 6] = m;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      const int x = tid + i * kThreads;
+      if (x < W && m8[i] != 0) {
+        int L, R;
+        nearest_hits_walk(hm, nw, W, x, L, R);
+        const int e = pick_side(L, R, W, L >= 0 ? zs[L] : 0u, R < W ? zs[R] : 0u, target_right);
+        if (e < 0) {
+          rgba[row + x] = 0u;
+          depth[row + x] = __builtin_inff();
+          mask[row + x] = 2;
+          continue;
+        }
+        const float ze = __uint_as_float(zs[e]);
+        const int rz = R - L - 1;
+        const float t = (float)abs(x - e) / (float)rz;
+        const int dir = e == R ? 1 : -1;
+        const int n = rz < kPatchCols ? rz : kPatchCols;
+        float w_rem = 1.0f, a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
+        for (int k = 0; k < n; ++k) {
+          const int cx = e + dir * k;
+          if (cx < 0 || cx >= W) break;
+          for (int j = 0; j < 3; ++j) {
+            const int cy = y + (j == 0 ? 0 : (j == 1 ? -1 : 1));
+            if (cy < 0 || cy >= H) continue;
+            uint32_t c;
+            float z;
+            if (j == 0) {
+              if (!((hm[cx >> 6] >> (cx & 63)) & 1ull)) continue;
+              c = col[cx];
+              z = __uint_as_float(zs[cx]);
+            } else {
+              const size_t q = (size_t)cy * (size_t)W + (size_t)cx;
+              if (mask[q] != 0) continue;
+              c = rgba[q];
+              z = depth[q];
+            }
+            if (z < ze) continue;  // foreground
+            const float wa = w_rem * 0.5f;
+            const float wb = 0.3f * w_rem;
+            const float w = wa + wb * t;
+            a0 = a0 + (float)(c & 255u) * w;
+            a1 = a1 + (float)((c >> 8) & 255u) * w;
+            a2 = a2 + (float)((c >> 16) & 255u) * w;
+            w_rem = w_rem - w;
+          }
+        }
+        const float norm = 1.0f - w_rem;
+        const float v0 = fminf(fmaxf(rintf(a0 / norm), 0.0f), 255.0f);
+        const float v1 = fminf(fmaxf(rintf(a1 / norm), 0.0f), 255.0f);
+        const float v2 = fminf(fmaxf(rintf(a2 / norm), 0.0f), 255.0f);
+        rgba[row + x] = (uint32_t)v0 | ((uint32_t)v1 << 8) | ((uint32_t)v2 << 16) | (col[e] & 0xFF000000u);
+        depth[row + x] = ze;
+        mask[row + x] = 1;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Hole error: integer sum of squared RGB differences over mask != 0.
 __global__ __launch_bounds__(kThreads) void zero2_kernel(unsigned long long* out) {
   if (threadIdx.x < 2) out[threadIdx.x] = 0ull;
@@ -509,17 +614,22 @@ hipError_t launch_warp_batch(const BatchHeader* hdr, const DevJob* jobs, int max
 
 hipError_t launch_fill(uint32_t* rgba, float* depth, uint8_t* mask, int32_t width, int32_t height, int32_t target_eye,
                        int32_t fill_mode, int ppt, int grid, hipStream_t stream) {
-  (void)fill_mode;
   const int wl = lds_width(width);
   const size_t lds = fill_lds_bytes(wl);
+  const bool patcher = fill_mode == kFillPatcher;
   switch (ppt) {
-#define X(P)                                                                                              \
-  case P: {                                                                                               \
-    hipError_t e = set_lds_limit((const void*)fill_kernel<P>, lds);                                       \
-    if (e != hipSuccess) return e;                                                                        \
-    hipLaunchKernelGGL(fill_kernel<P>, dim3(grid), dim3(kThreads), lds, stream, rgba, depth, mask, width, \
-                       height, target_eye, wl);                                                           \
-    return hipGetLastError();                                                                             \
+#define X(P)                                                                                                  \
+  case P: {                                                                                                   \
+    const void* k = patcher ? (const void*)patcher_kernel<P> : (const void*)fill_kernel<P>;                   \
+    hipError_t e = set_lds_limit(k, lds);                                                                     \
+    if (e != hipSuccess) return e;                                                                            \
+    if (patcher)                                                                                              \
+      hipLaunchKernelGGL(patcher_kernel<P>, dim3(grid), dim3(kThreads), lds, stream, rgba, depth, mask, width, \
+                         height, target_eye, wl);                                                             \
+    else                                                                                                      \
+      hipLaunchKernelGGL(fill_kernel<P>, dim3(grid), dim3(kThreads), lds, stream, rgba, depth, mask, width,    \
+                         height, target_eye, wl);                                                             \
+    return hipGetLastError();                                                                                 \
   }
     YORO_PPT_CASES(X)
 #undef X
@@ -567,16 +677,18 @@ int warp_blocks_per_cu(int max_width, bool batch) {
   return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
-int fill_blocks_per_cu(int width) {
+int fill_blocks_per_cu(int width, int fill_mode) {
   int nb = 0;
   const int ppt = ppt_for(width);
   const size_t lds = fill_lds_bytes(lds_width(width));
+  const bool patcher = fill_mode == kFillPatcher;
   hipError_t e = hipErrorInvalidValue;
   switch (ppt) {
-#define X(P)                                                                              \
-  case P:                                                                                 \
-    (void)set_lds_limit((const void*)fill_kernel<P>, lds);                                \
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fill_kernel<P>, kThreads, lds); \
+#define X(P)                                                                                       \
+  case P:                                                                                          \
+    (void)set_lds_limit(patcher ? (const void*)patcher_kernel<P> : (const void*)fill_kernel<P>, lds); \
+    e = patcher ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, patcher_kernel<P>, kThreads, lds)  \
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fill_kernel<P>, kThreads, lds);    \
     break;
     YORO_PPT_CASES(X)
 #undef X

@@ -44,6 +44,7 @@ struct UploadChunk {
 };
 
 constexpr int kThreads = 256;      // threads per workgroup (4 waves of 64)
+constexpr int kFillPatcher = 3;    // YORO_FILL_PATCHER
 constexpr int kMaxPPT = 32;        // pixels per thread: width <= kThreads * kMaxPPT = 8192
 
 // Pixels per thread for rows up to max_width columns: the smallest
@@ -119,6 +120,6 @@ hipError_t nn_composite_tiles(const float* res, const int* plan, int k, int crop
 
 // Occupancy-derived workgroups per CU for the row kernels.
 int warp_blocks_per_cu(int max_width, bool batch);
-int fill_blocks_per_cu(int width);
+int fill_blocks_per_cu(int width, int fill_mode);
 
 }  // namespace yoro

@@ -1,5 +1,6 @@
-"""Hole PSNR of the plain and learned fills against the ray-cast target eye
-on held-out full frames, and the learned fill's inference throughput.
+"""Hole PSNR of the plain nearest-background fill, the paper's Patcher and
+the learned fill against the ray-cast target eye on held-out full frames,
+and the learned fill's inference throughput.
 
     python -m paper_2506_15183_amd.evaluate --frames 16
 
@@ -46,8 +47,9 @@ def _sse(a, b, m):
 
 def evaluate(net: unet.UNet, n_frames: int = 16, log=None, timing_reps: int = 5):
     dev = net.device
-    per_plain, per_learned = [], []
-    pooled = np.zeros((2, 2), dtype=np.int64)  # [plain, learned] x [sse, count]
+    per_plain, per_learned, per_patch = [], [], []
+    pooled = np.zeros((3, 2), dtype=np.int64)  # [plain, learned, patcher] x [sse, count]
+    patch_times = []
     blocks, blocks_total, hole_frac = 0, 0, []
     times = []
     for i, spec in enumerate(config4_test_frames(n_frames)):
@@ -72,15 +74,26 @@ def evaluate(net: unet.UNet, n_frames: int = 16, log=None, timing_reps: int = 5)
                 b.record()
             torch.cuda.synchronize()
             times = [a.elapsed_time(b) for a, b in ev]
+        # The paper's Patcher on the same frame (warp, then the weighted fill).
+        ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        ev[0].record()
+        prgba, _, _ = yoro.reproject(src, srd, spec.baseline_m, spec.focal_px, spec.target_eye, yoro.FILL_PATCHER)
+        ev[1].record()
+        torch.cuda.synchronize()
+        patch_times.append(ev[0].elapsed_time(ev[1]))
         sp = _sse(rgba, tgt, mask)
         sl = _sse(out, tgt, mask)
+        sq = _sse(prgba, tgt, mask)
         pooled[0] += sp
         pooled[1] += sl
+        pooled[2] += sq
         per_plain.append(_psnr(*sp))
         per_learned.append(_psnr(*sl))
+        per_patch.append(_psnr(*sq))
         hole_frac.append(sp[1] / spec.pixels)
         if log:
-            log(f"frame {i}: holes {hole_frac[-1]:.3f}, plain {per_plain[-1]:.2f} dB, learned {per_learned[-1]:.2f} dB")
+            log(f"frame {i}: holes {hole_frac[-1]:.3f}, plain {per_plain[-1]:.2f} dB, patcher {per_patch[-1]:.2f} dB, "
+                f"learned {per_learned[-1]:.2f} dB")
     h, w = 1920, 1832
     ms = float(np.median(times))
     fl = algorithmic_flops(h, w)
@@ -88,9 +101,12 @@ def evaluate(net: unet.UNet, n_frames: int = 16, log=None, timing_reps: int = 5)
         "frames": n_frames, "size": f"{w}x{h}",
         "hole_fraction_mean": round(float(np.mean(hole_frac)), 4),
         "hole_psnr_plain_db": round(_psnr(*pooled[0]), 3),
+        "hole_psnr_patcher_db": round(_psnr(*pooled[2]), 3),
         "hole_psnr_learned_db": round(_psnr(*pooled[1]), 3),
         "hole_psnr_plain_mean_db": round(float(np.mean(per_plain)), 3),
+        "hole_psnr_patcher_mean_db": round(float(np.mean(per_patch)), 3),
         "hole_psnr_learned_mean_db": round(float(np.mean(per_learned)), 3),
+        "patcher_warp_and_fill_ms_per_frame": round(float(np.median(patch_times[1:] or patch_times)), 4),
         "hole_blocks_fraction": round(blocks / max(blocks_total, 1), 4),
         "learned_ms_per_frame": round(ms, 3),
         "learned_tflops": round(fl / (ms * 1e-3) / 1e12, 2),

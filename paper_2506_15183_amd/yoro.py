@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libyoro.so")
 
 TARGET_RIGHT, TARGET_LEFT = 0, 1
-FILL_NONE, FILL_NEAREST_BG = 0, 1
+FILL_NONE, FILL_NEAREST_BG, FILL_PATCHER = 0, 1, 3
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE_TOO_SMALL, ERR_DEVICE = 0, 1, 2, 3, 4
 MAX_WIDTH, MAX_HEIGHT = 8192, 16384
 

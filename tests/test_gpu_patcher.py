@@ -1,0 +1,107 @@
+"""GPU parity of the Patcher fill (YORO_FILL_PATCHER) against the oracle,
+bit-exact: through yoro_reproject (warp, then the Patcher) and through
+yoro_fill_holes in place, on ray-cast scenes, random frames with forced
+collisions and ragged widths, both eyes, and the hand-worked rows of the
+oracle's pins."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle import reproject as orc
+from paper_2506_15183_amd.scenes import synth
+from paper_2506_15183_amd.scenes.configs import config1_frame, config2_frame
+
+pytestmark = pytest.mark.gpu
+
+R, L = 0, 1
+
+
+def _gpu():
+    import torch
+
+    from paper_2506_15183_amd import yoro
+
+    return torch, yoro
+
+
+def run_reproject(rgba, depth, B, f, eye):
+    torch, yoro = _gpu()
+    a = torch.from_numpy(np.ascontiguousarray(rgba)).cuda()
+    d = torch.from_numpy(np.ascontiguousarray(depth)).cuda()
+    out = yoro.reproject(a, d, B, f, eye, yoro.FILL_PATCHER)
+    torch.cuda.synchronize()
+    return tuple(t.cpu().numpy() for t in out)
+
+
+def run_fill(rgba, depth, mask, eye):
+    torch, yoro = _gpu()
+    a, d, m = [torch.from_numpy(np.ascontiguousarray(x).copy()).cuda() for x in (rgba, depth, mask)]
+    yoro.fill_holes(a, d, m, eye, yoro.FILL_PATCHER)
+    torch.cuda.synchronize()
+    return a.cpu().numpy(), d.cpu().numpy(), m.cpu().numpy()
+
+
+def assert_same(g, o, what=""):
+    assert np.array_equal(g[0], o[0]), f"rgba differs {what}: {np.argwhere(np.any(g[0] != o[0], axis=-1))[:5]}"
+    assert np.array_equal(g[1].view(np.uint32), o[1].view(np.uint32)), f"depth differs {what}"
+    assert np.array_equal(g[2], o[2]), f"mask differs {what}"
+
+
+@pytest.mark.parametrize("eye", [R, L])
+@pytest.mark.parametrize("spec_fn", [config1_frame, config2_frame])
+def test_scenes(cuda, spec_fn, eye):
+    spec = spec_fn(0)
+    rgba, depth = spec.render_source()
+    g = run_reproject(rgba, depth, spec.baseline_m, spec.focal_px, eye)
+    o = orc.reproject(rgba, depth, spec.baseline_m, spec.focal_px, eye, orc.FILL_PATCHER)
+    assert_same(g, o, spec_fn.__name__)
+
+
+@pytest.mark.parametrize("W", [1, 2, 17, 64, 65, 257, 1000, 2160, 4097])
+def test_random_frames(cuda, W):
+    H = 4 if W > 2000 else 9
+    for k, (levels, special) in enumerate([(3, 0.0), (None, 0.08), (6, 0.03)]):
+        rgba, depth = synth.random_frame(500 + W + k, W, H, depth_levels=levels, special_frac=special,
+                                         zmin=0.05, zmax=30.0)
+        for eye in (R, L):
+            g = run_reproject(rgba, depth, 0.063, 900.0, eye)
+            o = orc.reproject(rgba, depth, 0.063, 900.0, eye, orc.FILL_PATCHER)
+            assert_same(g, o, f"W={W} case={k} eye={eye}")
+
+
+def test_fill_in_place_matches_oracle(cuda):
+    spec = config2_frame(1)
+    rgba, depth = spec.render_source()
+    warped = orc.reproject(rgba, depth, spec.baseline_m, spec.focal_px, R, orc.FILL_NONE)
+    for eye in (R, L):
+        g = run_fill(*warped, eye)
+        o = orc.fill_holes(*warped, eye, orc.FILL_PATCHER)
+        assert_same(g, o, f"eye={eye}")
+    # Rows with holes only, and hand-built rows (two-sample closed form).
+    rows = synth.random_rows(7, 300, 11, hole_frac=0.6)
+    rows[2][3] = 1
+    rows[0][3] = 0
+    rows[1][3] = np.inf
+    assert_same(run_fill(*rows, R), orc.fill_holes(*rows, R, orc.FILL_PATCHER), "random rows")
+    cols = np.array([[50, 0, 0, 200, 100, 7]], np.uint8)
+    rgba = np.repeat(cols[..., None], 4, axis=-1)
+    rgba[..., 3] = 255
+    depth = np.array([[1.0, np.inf, np.inf, 10.0, 10.0, 10.0]], np.float32)
+    mask = np.array([[0, 1, 1, 0, 0, 0]], np.uint8)
+    out = run_fill(rgba, depth, mask, R)[0]
+    assert out[0, 1, 0] == 183 and out[0, 2, 0] == 174
+
+
+def test_argument_checks(cuda):
+    torch, yoro = _gpu()
+    a = torch.zeros((4, 8, 4), dtype=torch.uint8, device="cuda")
+    d = torch.ones((4, 8), dtype=torch.float32, device="cuda")
+    with pytest.raises(yoro.YoroError) as ei:
+        yoro.reproject(a, d, 0.06, 900.0, R, yoro.FILL_PATCHER, with_depth=False)
+    assert ei.value.status == yoro.ERR_INVALID_ARG
+    out = torch.empty_like(a)
+    job = yoro.make_job(a, d, out, None, None, 0.06, 900.0, R, yoro.FILL_PATCHER)
+    with pytest.raises(yoro.YoroError) as ei:
+        yoro.StereoBatch([job]).prepare()
+    assert ei.value.status == yoro.ERR_UNSUPPORTED
