@@ -40,10 +40,10 @@ constexpr int kConvThreads = 256;  // 4 waves
 
 // ----------------------------------------------------------- conv3x3, tiled --
 // Output tile: 8 rows x 32 pixels of one image x CT channels per 256-thread
-// workgroup.  Per 32-channel input chunk the (8+2) x (32+2) input patch is
-// staged once in LDS and read by all nine taps; wave w computes rows 2w and
-// 2w+1 (four 16-pixel M tiles) x CT channels, so each B fragment (weights,
-// 16-byte loads from the cache) feeds four MFMAs and each A fragment CT/16.
+// workgroup.  Per 32-channel input chunk the (8+2) x (32+2) input patch and
+// the chunk's weights for all nine taps are staged once in LDS; wave w
+// computes rows 2w and 2w+1 (four 16-pixel M tiles) x CT channels, so each
+// B fragment feeds four MFMAs and each A fragment CT/16.
 // The LDS pixel stride is 40 bf16 (32 channels + 8 pad = 80 bytes) so the 16
 // lanes reading one k group of 16 consecutive pixels hit distinct banks.
 constexpr int kTileH = 8, kTileW = 32;
@@ -60,6 +60,8 @@ __global__ __launch_bounds__(kConvThreads) void conv3x3_tiled_kernel(const uint1
                                                                      int ups) {
   constexpr int NB = CT / 16;
   __shared__ __align__(16) uint16_t patch[kPatchH * kPatchW * kPatchStride];
+  // The chunk's weights for all nine taps: [tap][output channel][32 + 8 pad].
+  __shared__ __align__(16) uint16_t wlds[9 * CT * kPatchStride];
   const int tiles_x = (W + kTileW - 1) / kTileW, tiles_y = (H + kTileH - 1) / kTileH;
   int b = blockIdx.x;
   const int tx = b % tiles_x;
@@ -76,8 +78,6 @@ __global__ __launch_bounds__(kConvThreads) void conv3x3_tiled_kernel(const uint1
   for (int m = 0; m < 4; ++m)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[m][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
-  // This lane's B row: output channel co0 + nb*16 + lane%16, k group kg.
-  const uint16_t* wrow = wgt + (long long)(co0 + (lane & 15)) * Cin + kg;
 
   for (int ci0 = 0; ci0 < Cin; ci0 += 32) {
     __syncthreads();  // the previous chunk's readers are done with the patch
@@ -95,18 +95,19 @@ __global__ __launch_bounds__(kConvThreads) void conv3x3_tiled_kernel(const uint1
       }
       *reinterpret_cast<u32x4*>(patch + pix * kPatchStride + part * 8) = v;
     }
+    for (int e = threadIdx.x; e < 9 * CT * 4; e += kConvThreads) {
+      const int tc = e >> 2, part = e & 3;  // tc = tap * CT + output channel
+      const int t = tc / CT, co = tc - t * CT;
+      *reinterpret_cast<u32x4*>(wlds + tc * kPatchStride + part * 8) =
+          *reinterpret_cast<const u32x4*>(wgt + ((long long)t * Cout + co0 + co) * Cin + ci0 + part * 8);
+    }
     __syncthreads();
-    u32x4 bcur[NB], bnext[NB];
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb)
-      bcur[nb] = *reinterpret_cast<const u32x4*>(wrow + (long long)nb * 16 * Cin + ci0);
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
-      if (t < 8) {
+      u32x4 bcur[NB];
 #pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-          bnext[nb] = *reinterpret_cast<const u32x4*>(wrow + ((long long)(t + 1) * Cout + nb * 16) * Cin + ci0);
-      }
+      for (int nb = 0; nb < NB; ++nb)
+        bcur[nb] = *reinterpret_cast<const u32x4*>(wlds + (t * CT + nb * 16 + (lane & 15)) * kPatchStride + kg);
       const int ky = t / 3, kx = t % 3;
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
@@ -117,10 +118,6 @@ __global__ __launch_bounds__(kConvThreads) void conv3x3_tiled_kernel(const uint1
         for (int nb = 0; nb < NB; ++nb)
           acc[m][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(av), as_bf16x8(bcur[nb]), acc[m][nb], 0, 0,
                                                                0);
-      }
-      if (t < 8) {
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) bcur[nb] = bnext[nb];
       }
     }
   }
