@@ -20,10 +20,10 @@
 //      per wave64 a ballot of "target reached" gives one 64-bit hit mask per
 //      64 columns, and the holes are appended to a compact per-row list (one
 //      LDS atomic per wave);
-//   E  each wave scans the hit masks word by word in registers; each listed
-//      hole then finds its nearest hit on either side in O(1) and takes the
-//      farther one (Section 5 O2; Section 7 Patcher figure: on equal depth,
-//      the side opposite the shift), overwriting its provisional value.
+//   E  each listed hole walks the hit masks from its own word to its
+//      nearest hit on either side and takes the farther one (Section 5 O2;
+//      Section 7 Patcher figure: on equal depth, the side opposite the
+//      shift), overwriting its provisional value.
 //
 // The code avoids divergent branches where it can: on CDNA the scalar unit
 // issues at the same per-SIMD rate as the vector ALU, so exec-mask juggling
@@ -79,68 +79,9 @@ __device__ __forceinline__ void for_cols(int W, F&& body) {
   }
 }
 
-// Word-level scan of the hit masks, held in registers by every wave: lane l
-// covers words l and l + 64.  last[k] = the largest hit column in words
-// <= k (or -1); first[k] = the smallest hit column in words >= k (or W).
-struct WordScan {
-  int last0, last1, first0, first1;
-};
-
-__device__ __forceinline__ WordScan scan_words(const uint64_t* mask, int nw, int W) {
-  const int l = threadIdx.x & 63;
-  const uint64_t m0 = l < nw ? mask[l] : 0ull;
-  const uint64_t m1 = l + 64 < nw ? mask[l + 64] : 0ull;
-  WordScan r;
-  r.last0 = m0 ? l * 64 + 63 - __clzll((long long)m0) : -1;
-  r.last1 = m1 ? (l + 64) * 64 + 63 - __clzll((long long)m1) : -1;
-  r.first0 = m0 ? l * 64 + __ffsll((long long)m0) - 1 : W;
-  r.first1 = m1 ? (l + 64) * 64 + __ffsll((long long)m1) - 1 : W;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const int a0 = __shfl_up(r.last0, off), a1 = __shfl_up(r.last1, off);
-    const int b0 = __shfl_down(r.first0, off), b1 = __shfl_down(r.first1, off);
-    if (l >= off) {
-      r.last0 = max(r.last0, a0);
-      r.last1 = max(r.last1, a1);
-    }
-    if (l + off < 64) {
-      r.first0 = min(r.first0, b0);
-      r.first1 = min(r.first1, b1);
-    }
-  }
-  // Carry the first 64 words into the second 64 (and back for first).
-  const int carry_last = __shfl(r.last0, 63), carry_first = __shfl(r.first1, 0);
-  r.last1 = max(r.last1, carry_last);
-  r.first0 = min(r.first0, carry_first);
-  return r;
-}
-
-// last[k] / first[k] of the scan for a word index k (uniform or not); every
-// lane of the wave must call it (cross-lane reads).
-__device__ __forceinline__ int scan_last(const WordScan& s, int k) {
-  const int a = __shfl(s.last0, k & 63), b = __shfl(s.last1, k & 63);
-  return k < 0 ? -1 : (k < 64 ? a : b);
-}
-__device__ __forceinline__ int scan_first(const WordScan& s, int k, int nw, int W) {
-  const int a = __shfl(s.first0, k & 63), b = __shfl(s.first1, k & 63);
-  return k >= nw ? W : (k < 64 ? a : b);
-}
-
-// Nearest hit strictly left (L, or -1) and strictly right (R, or W) of
-// column x: inside x's own word from its mask, beyond it from the scan.
-__device__ __forceinline__ void nearest_hits(const uint64_t* mask, const WordScan& sc, int nw, int W, int x, int& L,
-                                             int& R) {
-  const int w = x >> 6, b = x & 63;
-  const uint64_t m = mask[w];
-  const uint64_t lo = m & ((1ull << b) - 1ull);
-  const uint64_t hi = (b == 63) ? 0ull : (m >> (b + 1)) << (b + 1);
-  const int Lw = scan_last(sc, w - 1);
-  const int Rw = scan_first(sc, w + 1, nw, W);
-  L = lo ? (w * 64 + 63 - __clzll((long long)lo)) : Lw;
-  R = hi ? (w * 64 + __ffsll((long long)hi) - 1) : Rw;
-}
-
-// Nearest hits by walking the masks word by word (stand-alone fill).
+// Nearest hits strictly left (L, or -1) and strictly right (R, or W) of
+// column x, walking the hit masks word by word from x's own word (hole runs
+// are short: most walks end in the first or second word).
 __device__ __forceinline__ void nearest_hits_walk(const uint64_t* mask, int nw, int W, int x, int& L, int& R) {
   const int w0 = x >> 6, b = x & 63;
   int w = w0;
@@ -197,8 +138,9 @@ __device__ __forceinline__ int round_half_away(float q) {
   return (__float_as_int(y) - 0x4B000000) + ((q - r) == 0.5f ? 1 : 0);
 }
 
-// Phases A-E for row y of job J, whose inputs are in registers.
-template <int PPT>
+// Phases A-E for row y of job J, whose inputs are in registers.  EXTRA:
+// the job also asks for the depth and/or mask outputs.
+template <int PPT, bool EXTRA>
 __device__ __forceinline__ void warp_fill_row(const DevJob& J, int y, const RowIn<PPT>& in, unsigned char* smem,
                                               int wl) {
   RowLds s(smem, wl);
@@ -215,8 +157,8 @@ __device__ __forceinline__ void warp_fill_row(const DevJob& J, int y, const RowI
   const int nfull = W / kThreads;
   const size_t row = (size_t)y * (size_t)W;
   YORO_GLOBAL uint32_t* orow = gmem(J.dst_rgba) + row;
-  YORO_GLOBAL float* zrow = J.dst_depth ? gmem(J.dst_depth) + row : nullptr;
-  YORO_GLOBAL uint8_t* mrow = J.dst_mask ? gmem(J.dst_mask) + row : nullptr;
+  YORO_GLOBAL float* zrow = (EXTRA && J.dst_depth) ? gmem(J.dst_depth) + row : nullptr;
+  YORO_GLOBAL uint8_t* mrow = (EXTRA && J.dst_mask) ? gmem(J.dst_mask) + row : nullptr;
 
   // A: clear keys.
   for_cols<PPT>(W, [&](int, int x) { s.key[x] = kEmpty; });
@@ -301,7 +243,6 @@ __device__ __forceinline__ void warp_fill_row(const DevJob& J, int y, const RowI
     }
     __syncthreads();
     // E: fill the listed holes.  Only hits are read, only holes written.
-    const WordScan sc = scan_words(s.mask, nw, W);
     const int nh = (int)*s.nholes;
     for (int h0 = tid - lane; h0 < nh; h0 += kThreads) {  // whole waves: the scan reads need every lane
       const int h = h0 + lane;
@@ -309,7 +250,7 @@ __device__ __forceinline__ void warp_fill_row(const DevJob& J, int y, const RowI
       const bool act = (h < nh) & (x < W);  // every listed column is < W; guard the store anyway
       x = act ? x : 0;
       int L, R;
-      nearest_hits(s.mask, sc, nw, W, x, L, R);
+      nearest_hits_walk(s.mask, nw, W, x, L, R);
       const uint32_t zl = (uint32_t)(s.key[max(L, 0)] >> 32);
       const uint32_t zr = (uint32_t)(s.key[min(R, W - 1)] >> 32);
       const int p = pick_side(L, R, W, zl, zr, target_right);
@@ -334,7 +275,7 @@ __global__ __launch_bounds__(kThreads) void warp_single_kernel(DevJob J, int wl)
     const RowIn<PPT> cur = in;
     const int yn = y + gridDim.x;
     if (yn < J.height) load_row<PPT>(J, yn, in);
-    warp_fill_row<PPT>(J, y, cur, smem, wl);
+    warp_fill_row<PPT, true>(J, y, cur, smem, wl);
   }
 }
 
@@ -359,7 +300,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
     RowIn<PPT> cur;
     if (J.width <= wl) load_row<PPT>(J, (int)(r - J.row_start), cur);
     if (J.width <= wl) {
-      warp_fill_row<PPT>(J, (int)(r - J.row_start), cur, smem, wl);
+      if (J.dst_depth || J.dst_mask)
+        warp_fill_row<PPT, true>(J, (int)(r - J.row_start), cur, smem, wl);
+      else
+        warp_fill_row<PPT, false>(J, (int)(r - J.row_start), cur, smem, wl);
     } else if (threadIdx.x == 0) {
       atomicAdd(&hdr->errors, 1u);  // rows wider than the LDS layout are skipped
     }
