@@ -214,6 +214,21 @@ def main():
         }
         log(f"serving ({time.time() - t1:.1f}s): {serving}")
         del srv
+        # Scenes with few holes (2-3 %, under the threshold): the learned
+        # policy refines frames, at most one every 50 ms (a GPU-time budget).
+        t1 = time.time()
+        sparse_s = max(args.serve_seconds / 2, 1.0)
+        cfg_s = serve.Config(learned_min_interval_ms=50.0)
+        srv = serve.Server(hs, cfg_s, serve.pool_renderer(sparse=True), model=net, log=log)
+        trace = serve.make_trace(hs, sparse_s, cfg_s.n_sources)
+        serving["sparse_scenes"] = {
+            "workload": f"as above with scenes of U{{20..60}} objects at depth >= 2 m, {sparse_s:g} s, "
+                        f"refinement at most every {cfg_s.learned_min_interval_ms:g} ms",
+            "plain": serve.summarize(trace, srv.run(trace, serve.PLAIN), hs, sparse_s),
+            "learned_policy": serve.summarize(trace, srv.run(trace, serve.LEARNED), hs, sparse_s),
+        }
+        log(f"serving, sparse scenes ({time.time() - t1:.1f}s): {serving['sparse_scenes']}")
+        del srv
 
     value = pixels * args.steps / wall / 1e6
     result = {

@@ -10,14 +10,18 @@
  *
  * Optional learned refinement (policy YORO_SERVE_LEARNED): once a batch's
  * warp is seen done, the loop counts each frame's holes per tile on the
- * device (on the learned stream, so the plain stream never waits) and reads
- * the counts back; a frame whose hole fraction is at most
+ * device (on a stream of its own that the call creates and destroys, so
+ * neither the plain stream nor a refinement delays it) and reads the counts
+ * back; a frame whose hole fraction is at most
  * learned_max_hole_fraction is refined by yoro_model_fill_tiles on the
  * learned stream (in place, on the frame's output), the others keep the
  * plain fill.  A frame whose headset's previous counted frame was above the
  * threshold is released as soon as its warp is done (fallback predicted, no
  * wait for its own count), and while a headset falls back its holes are
- * counted on every 8th frame only (holes = -1 in the results of the others).  One refinement runs at a time; a frame that
+ * counted on every 8th frame only (holes = -1 in the results of the others).
+ * Refinements start at least learned_min_interval_ns apart (a GPU-time
+ * budget); a frame that comes sooner, or while a refinement runs, keeps the
+ * plain fill (path BUSY) and is released as soon as its warp is done.  One refinement runs at a time; a frame that
  * finds it busy, or whose output set has already been handed to a newer
  * frame of its headset, keeps the plain fill.  A batch that reuses the
  * output set under refinement waits for it on the device.
@@ -85,6 +89,7 @@ typedef struct yoro_serve_options {
   size_t learned_workspace_bytes;
   int32_t tile, halo, chunk;         /* hole-tile inference (yoro_model.h) */
   void* learned_stream;              /* hipStream_t for the refinement */
+  int64_t learned_min_interval_ns;   /* refinements start at least this far apart */
 } yoro_serve_options;
 
 typedef struct yoro_serve_result {   /* one per arrival */

@@ -63,7 +63,7 @@ bool options_ok(const yoro_serve_options* o) {
   if (o->policy != YORO_SERVE_PLAIN && o->policy != YORO_SERVE_LEARNED) return false;
   if (learned(o) && (o->tile <= 0 || o->tile % 8 || o->halo < 0 || o->halo % 8 || o->chunk < 1 ||
                      !o->model_weights || !o->learned_workspace || !o->learned_stream ||
-                     !(o->learned_max_hole_fraction >= 0.0f)))
+                     !(o->learned_max_hole_fraction >= 0.0f) || o->learned_min_interval_ns < 0))
     return false;
   return true;
 }
@@ -173,6 +173,10 @@ int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, c
   for (int i = 0; i < Lay.count_slots && he == hipSuccess; ++i)
     he = hipEventCreateWithFlags(&cev[i], hipEventDisableTiming);
   if (he == hipSuccess) he = hipEventCreateWithFlags(&lev, hipEventDisableTiming);
+  // Hole counts get a stream of their own (default priority), so a frame's
+  // decision never queues behind a refinement.
+  hipStream_t cs = nullptr;
+  if (he == hipSuccess && L_on) he = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
 
   std::vector<int> next_out(n_headsets, 0);
   // Hole fraction of each headset's latest counted frame (-1: none yet).  A
@@ -195,6 +199,7 @@ int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, c
   jobs.reserve(O.max_batch);
   bool l_active = false;
   int64_t l_frame = -1;
+  int64_t l_started = -1;  // start of the last refinement (ns), -1: none yet
   int l_headset = -1, l_out = -1;
   int32_t status = he == hipSuccess ? YORO_OK : serve_fail(YORO_ERR_DEVICE, "%s: event: %s", who, hipGetErrorString(he));
 
@@ -212,6 +217,8 @@ int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, c
     if ((double)holes > (double)O.learned_max_hole_fraction * (double)H.width * H.height) return YORO_PATH_FALLBACK;
     if (holes == 0) return YORO_PATH_LEARNED;  // nothing to refine
     if (l_active || last_in[arrivals[k].headset * YORO_SERVE_MAX_OUTPUTS + out_of[k]] != k) return YORO_PATH_BUSY;
+    const int64_t t_start = now_ns();
+    if (l_started >= 0 && t_start - l_started < O.learned_min_interval_ns) return YORO_PATH_BUSY;
     const int crop = O.tile + 2 * O.halo, ntx = (H.width + O.tile - 1) / O.tile;
     int kc = 0;
     for (int t = 0; t < nt; ++t) {
@@ -242,6 +249,7 @@ int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, c
       return -1;
     }
     l_active = true, l_frame = k, l_headset = arrivals[k].headset, l_out = o;
+    l_started = t_start;
     return YORO_PATH_LEARNED;
   };
 
@@ -280,6 +288,10 @@ int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, c
         } else if (last_frac[h] > (double)O.learned_max_hole_fraction) {
           results[k].path = YORO_PATH_FALLBACK, results[k].done_ns = tn;
           if (++since_count[h] >= kRecount) B.counted[i] = 1, since_count[h] = 0;
+        } else if (l_active || (l_started >= 0 && tn - l_started < O.learned_min_interval_ns)) {
+          // No refinement could start now: the plain fill is final.
+          results[k].path = YORO_PATH_BUSY, results[k].done_ns = tn;
+          if (++since_count[h] >= kRecount) B.counted[i] = 1, since_count[h] = 0;
         } else {
           B.counted[i] = 1, since_count[h] = 0;
         }
@@ -289,7 +301,7 @@ int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, c
       bool any = false;
       for (char c : B.counted) any |= c != 0;
       if (L_on && any) {
-        // Count the holes (on the learned stream) only now that the frames'
+        // Count the holes (on the count stream) only now that the frames'
         // completion has been taken, so issuing the work delays no one.
         uint32_t* cd = reinterpret_cast<uint32_t*>(counts_dev + Lay.counts * B.cslot);
         hipError_t e = hipSuccess;
@@ -297,12 +309,12 @@ int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, c
           if (!B.counted[i]) continue;
           const int64_t k = B.frames[i];
           const yoro_serve_headset& H = headsets[arrivals[k].headset];
-          e = yoro::nn_tile_holes(H.dst_mask[out_of[k]], H.width, H.height, O.tile, cd + i * Lay.tiles, ls);
+          e = yoro::nn_tile_holes(H.dst_mask[out_of[k]], H.width, H.height, O.tile, cd + i * Lay.tiles, cs);
         }
         if (e == hipSuccess)
           e = hipMemcpyAsync(hs + Lay.counts * B.cslot, cd, B.frames.size() * Lay.tiles * 4, hipMemcpyDeviceToHost,
-                             ls);
-        if (e == hipSuccess) e = hipEventRecord(cev[B.cslot], ls);
+                             cs);
+        if (e == hipSuccess) e = hipEventRecord(cev[B.cslot], cs);
         if (e != hipSuccess) {
           status = serve_fail(YORO_ERR_DEVICE, "%s: hole counts: %s", who, hipGetErrorString(e));
           break;
@@ -419,6 +431,10 @@ int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, c
   // Drain whatever is queued (after an error too) before the events go away.
   (void)hipStreamSynchronize(s);
   if (L_on) (void)hipStreamSynchronize(ls);
+  if (cs) {
+    (void)hipStreamSynchronize(cs);
+    (void)hipStreamDestroy(cs);
+  }
   for (hipEvent_t e : ev)
     if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : cev)

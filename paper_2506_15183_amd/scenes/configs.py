@@ -186,12 +186,17 @@ def config5_headsets(n: int = 32, seed: int = 0) -> list[HeadsetSpec]:
     return out
 
 
-def config5_pool_frame(width: int, height: int, target_eye: int, slot: int) -> FrameSpec:
+def config5_pool_frame(width: int, height: int, target_eye: int, slot: int, sparse: bool = False) -> FrameSpec:
     """Pool frame `slot` for headsets of one resolution and eye: a scene of
     U{100..300} objects, depth log-uniform on [0.3, 50] m, checker as config 2,
-    rendered with B = 0.063 m and f = 900 px."""
-    key = (SERVE_SIZES.index((width, height)) * 2 + target_eye) * 1024 + slot
+    rendered with B = 0.063 m and f = 900 px.  sparse: U{20..60} objects at
+    depth log-uniform on [2, 50] m (about 2-3 % of pixels are holes, under the
+    learned policy's threshold)."""
+    key = (SERVE_SIZES.index((width, height)) * 2 + target_eye) * 1024 + slot + (1 << 20 if sparse else 0)
     u = raycast.uniforms(frame_seed(5, 4_000_000 + key), 1)
+    if sparse:
+        return FrameSpec(width, height, 0.063, 900.0, target_eye, 20 + int(u[0] * 41), 2.0, 50.0, True, (4, 32),
+                         frame_seed(5, key))
     n = 100 + int(u[0] * 201)
     return FrameSpec(width, height, 0.063, 900.0, target_eye, n, 0.3, 50.0, True, (4, 32), frame_seed(5, key))
 

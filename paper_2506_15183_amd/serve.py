@@ -63,6 +63,7 @@ class Options(ctypes.Structure):
         ("learned_workspace_bytes", ctypes.c_size_t),
         ("tile", ctypes.c_int32), ("halo", ctypes.c_int32), ("chunk", ctypes.c_int32),
         ("learned_stream", ctypes.c_void_p),
+        ("learned_min_interval_ns", ctypes.c_int64),
     ]
 
 
@@ -145,6 +146,7 @@ class Config:
     halo: int = 64
     chunk: int = 8
     learned_max_hole_fraction: float = 0.05
+    learned_min_interval_ms: float = 0.0
 
 
 class Server:
@@ -219,6 +221,7 @@ class Server:
         o = Options()
         o.max_batch, o.max_in_flight, o.policy = c.max_batch, c.max_in_flight, policy
         o.learned_max_hole_fraction = c.learned_max_hole_fraction
+        o.learned_min_interval_ns = int(c.learned_min_interval_ms * 1e6)
         o.tile, o.halo, o.chunk = c.tile, c.halo, c.chunk
         if policy == LEARNED:
             o.model_weights = self.model.wf.data_ptr()
@@ -260,6 +263,11 @@ def summarize(trace, res, headsets, seconds: float):
         "frames_per_s": round(float(done.sum()) / span, 1),
         "mean_batch_frames": round(float(res["batch_frames"][done].mean()), 3) if done.any() else None,
     }
+    refined = res["path"][done] == PATH_LEARNED
+    if refined.any():
+        out["learned_frames_p50_ms"] = round(float(np.percentile(lat[refined], 50)), 4)
+        out["learned_frames_max_ms"] = round(float(lat[refined].max()), 4)
+        out["p99_plain_path_frames_ms"] = round(float(np.percentile(lat[~refined], 99)), 4)
     holes = res["holes"][done]
     if (holes >= 0).any():
         frac = holes[holes >= 0] / px[holes >= 0]
@@ -268,7 +276,7 @@ def summarize(trace, res, headsets, seconds: float):
     return out
 
 
-def pool_renderer(n_threads: int = 0):
+def pool_renderer(n_threads: int = 0, sparse: bool = False):
     """Pool frames shared by headsets of the same resolution and eye (each
     headset still holds its own resident copy)."""
     cache = {}
@@ -276,7 +284,8 @@ def pool_renderer(n_threads: int = 0):
     def frames(h: HeadsetSpec, slot: int):
         key = (h.width, h.height, h.target_eye, slot)
         if key not in cache:
-            cache[key] = config5_pool_frame(h.width, h.height, h.target_eye, slot).render_source(nthreads=n_threads)
+            spec = config5_pool_frame(h.width, h.height, h.target_eye, slot, sparse=sparse)
+            cache[key] = spec.render_source(nthreads=n_threads)
         return cache[key]
 
     return frames
@@ -290,6 +299,8 @@ def main():
     ap.add_argument("--learned", action="store_true", help="also run the learned policy with its fallback")
     ap.add_argument("--weights", default=None)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--sparse", action="store_true", help="scenes with few holes (U{20..60} objects, depth >= 2 m)")
+    ap.add_argument("--learned-interval-ms", type=float, default=0.0)
     a = ap.parse_args()
     log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
     hs = config5_headsets(a.headsets, a.seed)
@@ -298,8 +309,8 @@ def main():
         from . import train, unet
 
         model = unet.UNet("cuda", params=train.load_weights(a.weights or train.DEFAULT_WEIGHTS))
-    cfg = Config(budget_bytes=int(a.budget_gb * 1e9))
-    srv = Server(hs, cfg, pool_renderer(), model=model, log=log)
+    cfg = Config(budget_bytes=int(a.budget_gb * 1e9), learned_min_interval_ms=a.learned_interval_ms)
+    srv = Server(hs, cfg, pool_renderer(sparse=a.sparse), model=model, log=log)
     trace = make_trace(hs, a.seconds, cfg.n_sources, seed=a.seed)
     log(f"{len(trace)} arrivals over {a.seconds} s")
     out = {"headsets": len(hs), "admitted": int(srv.admitted.sum()), "resident_gb": round(srv.resident_bytes / 1e9, 3)}
