@@ -339,6 +339,135 @@ int oracle_fill_holes(uint8_t* rgba, float* depth, uint8_t* mask, int32_t width,
 }
 
 /*
+ * Resolution-independent intermediate buffer (Section 6 (c) and (d)):
+ * the reprojection runs on a buffer of ceil(W/k) x ceil(H/k) texels
+ * (k = 1, 2, 4, 8, 16), one per k x k block of pixels (the last row and
+ * column of blocks may be cut by the frame's edge), that holds, per texel,
+ * how far its pixel moves; the full-resolution image is then sampled
+ * through it.  Readings:
+ *   texel (i, j) takes the depth z of the full-resolution source pixel at
+ *   its block's centre, (k i + c, k j + c) with c = k / 2 (c = 0 for
+ *   k = 1), each coordinate clamped to the frame;
+ *   q = (B f) / z with the direct path's skip rule (z > 0, q < W); the
+ *   texel moves by the rounded texel disparity dk = roundf(q / k) to
+ *   it = i - dk (right eye; i + dk for the left), skipped unless
+ *   0 <= it < ceil(W/k); the nearest depth wins (key: depth bits, then texel
+ *   index); the winner's record is its shift q, in full-resolution pixels,
+ *   and its depth z;
+ *   full-resolution pixel (x, y) reads buffer row y / k at
+ *   u = (x - c) / k, i0 = floor(u), f = u - i0, the nearest texel
+ *   n = f < 0.5 ? i0 : i0 + 1 (clamped to the row; it is always the texel
+ *   whose k x k block holds the pixel): a hole there is a hole here;
+ *   otherwise the shift is n's, or, with linear interpolation along the
+ *   row (Section 6 (d)), when i0 and i0 + 1 are both in the row, both hits
+ *   and their shifts within one pixel of each other (one surface),
+ *   s = s0 + f (s1 - s0);
+ *   the source column is x + roundf(s) (right eye; x - roundf(s) for the
+ *   left), a hole if off the row; a hit takes that source pixel's RGBA and
+ *   the depth of texel n; the nearest-background fill then runs on the
+ *   full-resolution row as in the direct path.
+ * FP32 throughout, in exactly this order.  With k = 1 every pixel is a
+ * texel, s = q, roundf(s) is the direct path's disparity and the result is
+ * the direct path's (pinned).
+ */
+int oracle_reproject_lowres(const uint8_t* src_rgba, const float* src_depth, int32_t width, int32_t height,
+                            float baseline_m, float focal_px, int32_t target_eye, int32_t fill_mode, int32_t k,
+                            int32_t linear, uint8_t* dst_rgba, float* dst_depth, uint8_t* dst_mask) {
+  if (width <= 0 || height <= 0 || !src_rgba || !src_depth || !dst_rgba) return -1;
+  if (target_eye != OR_TARGET_RIGHT && target_eye != OR_TARGET_LEFT) return -1;
+  if (!(k == 1 || k == 2 || k == 4 || k == 8 || k == 16)) return -1;
+  if (fill_mode != OR_FILL_NONE && fill_mode != OR_FILL_NEAREST_BG) return -1;
+  const float bf = baseline_m * focal_px;
+  const int32_t s = (target_eye == OR_TARGET_RIGHT) ? -1 : +1;
+  const int32_t wk = (width + k - 1) / k, hk = (height + k - 1) / k, c = k / 2;
+  uint64_t* K = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)wk);
+  float* sh = (float*)malloc(sizeof(float) * (size_t)wk);
+  float* zt = (float*)malloc(sizeof(float) * (size_t)wk);
+  uint8_t* hit = (uint8_t*)malloc((size_t)width);
+  float* zr = (float*)malloc(sizeof(float) * (size_t)width);
+  uint8_t* col = (uint8_t*)malloc(4 * (size_t)width);
+  float* dz = (float*)malloc(sizeof(float) * (size_t)width);
+  uint8_t* mk = (uint8_t*)malloc((size_t)width);
+  for (int32_t j = 0; j < hk; ++j) {
+    /* Stage 1: scatter the buffer row. */
+    const int32_t yc = k * j + c < height ? k * j + c : height - 1;
+    const size_t srow = (size_t)yc * (size_t)width;
+    for (int32_t i = 0; i < wk; ++i) K[i] = OR_EMPTY;
+    for (int32_t i = 0; i < wk; ++i) {
+      const int32_t xc = k * i + c < width ? k * i + c : width - 1;
+      const float z = src_depth[srow + (size_t)xc];
+      if (!(z > 0.0f)) continue;
+      const float q = bf / z;
+      if (!(q < (float)width)) continue;
+      const int32_t dk = (int32_t)roundf(q / (float)k);
+      const int32_t it = i + s * dk;
+      if (it < 0 || it >= wk) continue;
+      const uint64_t key = ((uint64_t)float_bits(z) << 32) | (uint64_t)(uint32_t)i;
+      if (key < K[it]) K[it] = key;
+    }
+    for (int32_t i = 0; i < wk; ++i) {
+      if (K[i] == OR_EMPTY) continue;
+      const float z = bits_float((uint32_t)(K[i] >> 32));
+      sh[i] = bf / z;
+      zt[i] = z;
+    }
+    /* Stage 2: the k full-resolution rows that read this buffer row. */
+    for (int32_t y = k * j; y < k * j + k && y < height; ++y) {
+      const size_t row = (size_t)y * (size_t)width;
+      for (int32_t x = 0; x < width; ++x) {
+        const float u = ((float)x - (float)c) / (float)k;
+        const float i0f = floorf(u);
+        const float f = u - i0f;
+        int32_t i0 = (int32_t)i0f, i1 = i0 + 1;
+        int32_t n = f < 0.5f ? i0 : i1;
+        n = n < 0 ? 0 : (n >= wk ? wk - 1 : n);
+        int ok = K[n] != OR_EMPTY;
+        int32_t xs = -1;
+        if (ok) {
+          float sv = sh[n];
+          if (linear && i0 >= 0 && i1 < wk && K[i0] != OR_EMPTY && K[i1] != OR_EMPTY &&
+              fabsf(sh[i1] - sh[i0]) <= 1.0f) {
+            const float dsh = sh[i1] - sh[i0];
+            const float m = f * dsh;
+            sv = sh[i0] + m;
+          }
+          const int32_t r = (int32_t)roundf(sv);
+          xs = (s < 0) ? x + r : x - r;
+          ok = xs >= 0 && xs < width;
+        }
+        if (ok) {
+          hit[x] = 1;
+          zr[x] = zt[n];
+          memcpy(&col[4 * x], &src_rgba[4 * (row + (size_t)xs)], 4);
+          dz[x] = zt[n];
+          mk[x] = 0;
+        } else {
+          hit[x] = 0;
+          zr[x] = INFINITY;
+          memset(&col[4 * x], 0, 4);
+          dz[x] = INFINITY;
+          mk[x] = 1;
+        }
+      }
+      uint8_t* orow = &dst_rgba[4 * row];
+      memcpy(orow, col, 4 * (size_t)width);
+      if (fill_mode != OR_FILL_NONE) fill_row(orow, dz, mk, hit, zr, col, width, s, fill_mode);
+      if (dst_depth) memcpy(&dst_depth[row], dz, sizeof(float) * (size_t)width);
+      if (dst_mask) memcpy(&dst_mask[row], mk, (size_t)width);
+    }
+  }
+  free(K);
+  free(sh);
+  free(zt);
+  free(hit);
+  free(zr);
+  free(col);
+  free(dz);
+  free(mk);
+  return 0;
+}
+
+/*
  * Hole error against a reference image (Section 9, PSNR): the sum of squared
  * RGB differences over pixels with mask != 0, and the number of such pixels.
  * Integer arithmetic, so the sum is exact.

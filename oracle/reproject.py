@@ -42,6 +42,11 @@ def lib():
         L.oracle_reproject.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_float, ctypes.c_float, ctypes.c_int32, ctypes.c_int32,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
+        L.oracle_reproject_lowres.restype = ctypes.c_int
+        L.oracle_reproject_lowres.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                              ctypes.c_float, ctypes.c_float, ctypes.c_int32, ctypes.c_int32,
+                                              ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.c_void_p]
         L.oracle_fill_holes.restype = ctypes.c_int
         L.oracle_fill_holes.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                         ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
@@ -79,6 +84,27 @@ def reproject(src_rgba: np.ndarray, src_depth: np.ndarray, baseline_m: float, fo
                                 nthreads)
     if rc != 0:
         raise ValueError("oracle_reproject: bad arguments")
+    return dst, dz, mk
+
+
+def reproject_lowres(src_rgba: np.ndarray, src_depth: np.ndarray, baseline_m: float, focal_px: float,
+                     target_eye: int = TARGET_RIGHT, fill_mode: int = FILL_NEAREST_BG, scale: int = 4,
+                     linear: bool = True):
+    """Reprojection through a 1/scale intermediate buffer (Section 6 (c), (d)):
+    (dst_rgba [H,W,4] u8, dst_depth [H,W] f32, dst_mask [H,W] u8)."""
+    src_rgba = np.ascontiguousarray(src_rgba, dtype=np.uint8)
+    src_depth = np.ascontiguousarray(src_depth, dtype=np.float32)
+    H, W = src_depth.shape
+    assert src_rgba.shape == (H, W, 4)
+    dst = np.empty_like(src_rgba)
+    dz = np.empty_like(src_depth)
+    mk = np.empty((H, W), dtype=np.uint8)
+    rc = lib().oracle_reproject_lowres(src_rgba.ctypes.data, src_depth.ctypes.data, W, H,
+                                       float(np.float32(baseline_m)), float(np.float32(focal_px)), target_eye,
+                                       fill_mode, int(scale), int(bool(linear)), dst.ctypes.data, dz.ctypes.data,
+                                       mk.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle_reproject_lowres: bad arguments")
     return dst, dz, mk
 
 
