@@ -9,7 +9,9 @@ by ONE persistent kernel launch replayed from a captured HIP graph.
 Beside the timed step the same run reports the other parts of the metric:
 hole PSNR of the plain and learned fills against the ray-cast target eye on
 held-out 1832x1920 frames (with the learned fill's matrix-core throughput),
-and p50/p99 frame latency of the serving loop for 32 headsets.
+and p50/p99 frame latency of the serving loop for 32 headsets; and the same
+batch through a downsampled intermediate buffer (scales 1-16), whose image
+error the evaluation reports.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--serve-seconds S] [--eval-frames F]
 Prints one JSON line.
@@ -28,6 +30,10 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 BYTES_PER_PIXEL = 12   # read 4 B depth + 4 B RGBA, write 4 B RGBA
+# Downsampled intermediate buffer scales timed on the same batch; its
+# algorithmic bytes per pixel are 4 B RGBA gathered + 4 B written + 4/k^2 B
+# of block-centre depth.
+LOWRES_SCALES = (1, 2, 4, 8, 16)
 
 
 def log(msg):
@@ -50,6 +56,7 @@ def main():
     ap.add_argument("--no-single-frame", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=20.0, help="0 skips the serving runs")
     ap.add_argument("--eval-frames", type=int, default=16, help="0 skips the hole-PSNR evaluation")
+    ap.add_argument("--no-lowres", action="store_true", help="skip the downsampled-buffer batch timings")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the plain path shards "
@@ -147,6 +154,38 @@ def main():
             "algorithmic_gb_s": round(BYTES_PER_PIXEL * spec2.pixels / (float(np.median(ms)) * 1e-3) / 1e9, 1),
         }
         log(f"single frame: {single}")
+
+    # ------------------- the same batch through a downsampled intermediate buffer
+    lowres = None
+    if not args.no_lowres:
+        lowres = []
+        for k in LOWRES_SCALES:
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.stream(stream):
+                batch.launch_lowres(k, True, stream=stream)
+                torch.cuda.synchronize()
+                with torch.cuda.graph(g, stream=stream):
+                    batch.launch_lowres(k, True, stream=stream)
+            torch.cuda.synchronize()
+            for _ in range(5):
+                g.replay()
+            n_rep = 50
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_rep)]
+            with torch.cuda.stream(stream):
+                for a, b in evs:
+                    a.record(stream)
+                    g.replay()
+                    b.record(stream)
+            torch.cuda.synchronize()
+            ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+            bpp = 8.0 + 4.0 / (k * k)
+            lowres.append({"scale": k, "linear": True, "launch_ms_avg": round(ms, 4),
+                           "mpix_s": round(pixels / (ms * 1e-3) / 1e6, 1),
+                           "algorithmic_bytes_per_pixel": round(bpp, 4),
+                           "algorithmic_gb_s": round(bpp * pixels / (ms * 1e-3) / 1e9, 1)})
+            del g
+        assert batch.errors() == 0
+        log(f"downsampled buffer: {lowres}")
 
     # ------------------------------------------------------ CPU oracle baseline
     cpu = None
@@ -265,6 +304,7 @@ def main():
         "cpu_baseline": cpu,
         "parity_vs_oracle": parity,
         "single_frame": single,
+        "lowres_batch": lowres,
         "hole_psnr": quality,
         "learned_fill_roofline": learned_roof,
         "serving": serving,

@@ -174,6 +174,48 @@ int32_t yoro_stereo_batch(const yoro_job* jobs_host, int32_t n_jobs, void* dev_w
 const uint32_t* yoro_stereo_batch_errors(const void* dev_workspace);
 
 /*
+ * yoro_reproject_lowres -- yoro_reproject through a downsampled intermediate
+ * buffer (Section 6 (c), resolution-independent intermediate buffers, and
+ * (d), linear interpolation along the row).  The warp runs on one texel per
+ * scale x scale block of the frame and the full-resolution image is then
+ * sampled through it:
+ *   k = scale (1, 2, 4, 8 or 16), c = k / 2 (0 for k = 1);
+ *   texel (i, j) takes the depth z of pixel (k i + c, k j + c), each
+ *   coordinate clamped to the frame (the last block row and column may be
+ *   cut by the frame's edge); q = bf / z with yoro_reproject's skip rule;
+ *   it moves to texel column i -+ roundf(q / k) (skipped unless inside the
+ *   buffer row, ceil(width / k) texels); the nearest depth wins and the
+ *   texel keeps q (full-resolution pixels) and z;
+ *   pixel (x, y) reads texel n = its own block's: none reached it -> hole;
+ *   else s = q of n, or with linear != 0, when the texels i0 = floor(u) and
+ *   i0 + 1 around u = (x - c) / k are both in the row, both reached and
+ *   their q differ by at most 1, s = q0 + f (q1 - q0) with f = u - i0;
+ *   the source column is x + roundf(s) (TARGET_RIGHT) or x - roundf(s)
+ *   (TARGET_LEFT); off the row -> hole; else the pixel takes that source
+ *   pixel's RGBA (its own row) and the depth z of texel n, mask 0.
+ * All FP32, each operation rounded once.  Holes are then filled per
+ * fill_mode exactly as yoro_reproject fills them.  With scale 1 the result
+ * is yoro_reproject's, bit for bit.  Arguments, ownership, outputs and
+ * errors as yoro_reproject; scale outside {1, 2, 4, 8, 16} or linear
+ * outside {0, 1} is YORO_ERR_INVALID_ARG.
+ */
+int32_t yoro_reproject_lowres(const uint8_t* src_rgba, const float* src_depth, int32_t width, int32_t height,
+                              float baseline_m, float focal_px, int32_t target_eye, int32_t fill_mode,
+                              int32_t scale, int32_t linear, uint8_t* dst_rgba, float* dst_depth,
+                              uint8_t* dst_mask, void* hip_stream);
+
+/*
+ * yoro_stereo_batch_launch_lowres -- run the jobs that the last prepare on
+ * this workspace uploaded, each as yoro_reproject_lowres with the given
+ * scale and linear flag, as one persistent kernel.  A workgroup takes
+ * scale rows of one block row at a time.  max_width and the error counter
+ * as in yoro_stereo_batch_launch.  Capture-safe: no allocation, copy or
+ * sync.
+ */
+int32_t yoro_stereo_batch_launch_lowres(const void* dev_workspace, int32_t max_width, int32_t scale,
+                                        int32_t linear, void* hip_stream);
+
+/*
  * yoro_hole_sse -- hole error of a synthesised eye against a reference image
  * (Section 9, PSNR = 10 log10(255^2 / MSE)).  Writes to dev_out[0] the sum
  * of squared R, G, B differences over pixels with mask != 0 (over all

@@ -55,6 +55,13 @@ bool device_facts(DeviceFacts* out) {
 
 int pick_ppt(int width) { return yoro::ppt_for(width); }
 
+// log2 of an intermediate-buffer scale of 1, 2, 4, 8 or 16; -1 otherwise.
+int scale_log2(int32_t scale) {
+  for (int lg = 0; lg <= 4; ++lg)
+    if (scale == (1 << lg)) return lg;
+  return -1;
+}
+
 bool aligned4(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }
 
 struct Range {
@@ -158,6 +165,49 @@ int32_t yoro_reproject(const uint8_t* src_rgba, const float* src_depth, int32_t 
     return ok();
   } catch (...) {
     return fail(YORO_ERR_DEVICE, "yoro_reproject: internal error");
+  }
+}
+
+int32_t yoro_reproject_lowres(const uint8_t* src_rgba, const float* src_depth, int32_t width, int32_t height,
+                              float baseline_m, float focal_px, int32_t target_eye, int32_t fill_mode,
+                              int32_t scale, int32_t linear, uint8_t* dst_rgba, float* dst_depth,
+                              uint8_t* dst_mask, void* hip_stream) {
+  try {
+    int32_t st = check_frame(src_rgba, src_depth, width, height, baseline_m, focal_px, target_eye, fill_mode,
+                             dst_rgba, dst_depth, dst_mask, "yoro_reproject_lowres");
+    if (st != YORO_OK) return st;
+    const int lg = scale_log2(scale);
+    if (lg < 0) return fail(YORO_ERR_INVALID_ARG, "yoro_reproject_lowres: scale %d is not 1, 2, 4, 8 or 16", scale);
+    if (linear != 0 && linear != 1)
+      return fail(YORO_ERR_INVALID_ARG, "yoro_reproject_lowres: linear must be 0 or 1, got %d", linear);
+    const bool patcher = fill_mode == YORO_FILL_PATCHER;
+    if (patcher && (!dst_depth || !dst_mask))
+      return fail(YORO_ERR_INVALID_ARG, "yoro_reproject_lowres: the Patcher fill needs dst_depth and dst_mask");
+    const int ppt = pick_ppt(width);
+    if (ppt < 0) return fail(YORO_ERR_UNSUPPORTED, "yoro_reproject_lowres: width %d too wide", width);
+    yoro_job j{src_rgba, src_depth, dst_rgba, dst_depth, dst_mask, width, height, baseline_m, focal_px,
+               target_eye, patcher ? (int32_t)YORO_FILL_NONE : fill_mode};
+    const yoro::DevJob dj = make_job(j, 0);
+    // Units of G rows: as many rows per unit as still leave two units per
+    // resident workgroup.
+    DeviceFacts f;
+    const int cus = device_facts(&f) ? f.cus : 256;
+    const long long full = (long long)cus * yoro::lowres_blocks_per_cu(width, lg, false);
+    const long long blocks = ((long long)height + (1 << lg) - 1) >> lg;
+    int glg = lg;
+    while (glg > 0 && blocks * (1ll << (lg - glg)) < 2 * full) --glg;
+    const long long units = blocks << (lg - glg);
+    const int grid = (int)std::max<long long>(1, std::min(units, full));
+    hipError_t e = yoro::launch_lowres(&dj, nullptr, nullptr, width, lg, glg, linear, grid, (hipStream_t)hip_stream);
+    if (e == hipSuccess && patcher)
+      e = yoro::launch_fill(reinterpret_cast<uint32_t*>(dst_rgba), dst_depth, dst_mask, width, height, target_eye,
+                            fill_mode, ppt, grid_for(height, yoro::fill_blocks_per_cu(width, fill_mode)),
+                            (hipStream_t)hip_stream);
+    if (e != hipSuccess)
+      return fail(YORO_ERR_DEVICE, "yoro_reproject_lowres: launch failed: %s", hipGetErrorString(e));
+    return ok();
+  } catch (...) {
+    return fail(YORO_ERR_DEVICE, "yoro_reproject_lowres: internal error");
   }
 }
 
@@ -290,6 +340,31 @@ int32_t yoro_stereo_batch_launch(const void* dev_workspace, int32_t max_width, v
     return ok();
   } catch (...) {
     return fail(YORO_ERR_DEVICE, "yoro_stereo_batch_launch: internal error");
+  }
+}
+
+int32_t yoro_stereo_batch_launch_lowres(const void* dev_workspace, int32_t max_width, int32_t scale, int32_t linear,
+                                        void* hip_stream) {
+  try {
+    if (!dev_workspace) return fail(YORO_ERR_INVALID_ARG, "yoro_stereo_batch_launch_lowres: null workspace");
+    if (max_width <= 0 || max_width > YORO_MAX_WIDTH)
+      return fail(YORO_ERR_INVALID_ARG, "yoro_stereo_batch_launch_lowres: max_width %d out of range", max_width);
+    const int lg = scale_log2(scale);
+    if (lg < 0)
+      return fail(YORO_ERR_INVALID_ARG, "yoro_stereo_batch_launch_lowres: scale %d is not 1, 2, 4, 8 or 16", scale);
+    if (linear != 0 && linear != 1)
+      return fail(YORO_ERR_INVALID_ARG, "yoro_stereo_batch_launch_lowres: linear must be 0 or 1, got %d", linear);
+    const auto* hdr = reinterpret_cast<const yoro::BatchHeader*>(dev_workspace);
+    const auto* dj = reinterpret_cast<const yoro::DevJob*>(hdr + 1);
+    DeviceFacts f;
+    const int cus = device_facts(&f) ? f.cus : 256;
+    const int grid = cus * yoro::lowres_blocks_per_cu(max_width, lg, true);
+    hipError_t e = yoro::launch_lowres(nullptr, hdr, dj, max_width, lg, lg, linear, grid, (hipStream_t)hip_stream);
+    if (e != hipSuccess)
+      return fail(YORO_ERR_DEVICE, "yoro_stereo_batch_launch_lowres: launch failed: %s", hipGetErrorString(e));
+    return ok();
+  } catch (...) {
+    return fail(YORO_ERR_DEVICE, "yoro_stereo_batch_launch_lowres: internal error");
   }
 }
 

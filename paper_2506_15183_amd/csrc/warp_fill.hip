@@ -31,77 +31,10 @@
 //
 // HBM traffic per target pixel: 4 B depth + 4 B RGBA read, 4 B RGBA written
 // (+4 B depth, +1 B mask when asked for).
-#include "yoro_internal.h"
+#include "row_common.h"
 
 namespace yoro {
 namespace {
-
-constexpr uint64_t kEmpty = ~0ull;
-
-#define YORO_GLOBAL __attribute__((address_space(1)))
-
-template <class T>
-__device__ __forceinline__ YORO_GLOBAL T* gmem(T* p) {
-  return (YORO_GLOBAL T*)p;
-}
-
-// Per-row LDS of the warp kernel, laid out for rows up to wl columns (wl: a
-// multiple of 64, uniform for the launch).
-struct RowLds {
-  uint64_t* key;     // [wl + 64] target keys: depth bits << 32 | RGBA; the
-                     //           last 64 are per-lane sinks for lanes with
-                     //           nothing to splat
-  uint64_t* mask;    // [wl/64]   hit masks, one per 64 columns
-  uint32_t* nholes;  // [4]
-  uint16_t* holes;   // [wl]      columns of the row's holes (unordered)
-  __device__ RowLds(unsigned char* base, int wl) {
-    key = reinterpret_cast<uint64_t*>(base);
-    mask = key + wl + 64;
-    nholes = reinterpret_cast<uint32_t*>(mask + (wl >> 6));
-    holes = reinterpret_cast<uint16_t*>(nholes + 4);
-  }
-};
-
-// Runs body(i, x) for every column x = threadIdx.x + i*kThreads < W.  Chunks
-// that lie wholly inside the row take a uniform (scalar) branch with no
-// per-lane test; only the one ragged chunk tests x < W per lane.
-template <int PPT, class F>
-__device__ __forceinline__ void for_cols(int W, F&& body) {
-  const int nfull = W / kThreads;
-  const int x0 = threadIdx.x;
-#pragma unroll
-  for (int i = 0; i < PPT; ++i) {
-    if (i < nfull) {
-      body(i, x0 + i * kThreads);
-    } else if (i == nfull) {
-      if (x0 + i * kThreads < W) body(i, x0 + i * kThreads);
-    }
-  }
-}
-
-// Nearest hits strictly left (L, or -1) and strictly right (R, or W) of
-// column x, walking the hit masks word by word from x's own word (hole runs
-// are short: most walks end in the first or second word).
-__device__ __forceinline__ void nearest_hits_walk(const uint64_t* mask, int nw, int W, int x, int& L, int& R) {
-  const int w0 = x >> 6, b = x & 63;
-  int w = w0;
-  uint64_t m = mask[w] & ((1ull << b) - 1ull);
-  while (m == 0 && w > 0) m = mask[--w];
-  L = m ? (w * 64 + 63 - __clzll((long long)m)) : -1;
-  w = w0;
-  m = (b == 63) ? 0ull : (mask[w] >> (b + 1)) << (b + 1);
-  while (m == 0 && w + 1 < nw) m = mask[++w];
-  R = m ? (w * 64 + __ffsll((long long)m) - 1) : W;
-}
-
-// Which of the nearest hits fills a hole: the farther one; on equal depth
-// the one opposite the shift (right when synthesising the right eye).
-// zl, zr: depth bits of the hits (depths in (0, +inf] order like their bits).
-__device__ __forceinline__ int pick_side(int L, int R, int W, uint32_t zl, uint32_t zr, bool target_right) {
-  if (L < 0) return R < W ? R : -1;
-  if (R >= W) return L;
-  return zl > zr ? L : (zr > zl ? R : (target_right ? R : L));
-}
 
 // One row's inputs held in registers: thread t owns columns t + i*kThreads.
 template <int PPT>
@@ -127,17 +60,6 @@ __device__ __forceinline__ void load_row(const DevJob& J, int y, RowIn<PPT>& in)
   });
 }
 
-// roundf(q) for 0 <= q < 2^23 without a float-to-int conversion (whose result
-// is undefined for the lanes that do not splat): adding 2^23 rounds q to the
-// nearest integer, ties to even, in the low mantissa bits; a tie that went
-// down (q - r == 0.5 exactly) is then moved up, giving ties away from zero.
-// Any other q gives an unspecified but harmless value.
-__device__ __forceinline__ int round_half_away(float q) {
-  const float y = q + 0x1p23f;
-  const float r = y - 0x1p23f;
-  return (__float_as_int(y) - 0x4B000000) + ((q - r) == 0.5f ? 1 : 0);
-}
-
 // Phases A-E for row y of job J, whose inputs are in registers.  EXTRA:
 // the job also asks for the depth and/or mask outputs.
 template <int PPT, bool EXTRA>
@@ -152,7 +74,6 @@ __device__ __forceinline__ void warp_fill_row(const DevJob& J, int y, const RowI
   const bool target_right = J.target_eye == 0;
   // x_t = x - d (target right) or x + d (target left), as x + ((d ^ m) - m).
   const int m = target_right ? -1 : 0;
-  const int nw = (W + 63) >> 6;
   const bool fill = J.fill_mode != 0;
   const int nfull = W / kThreads;
   const size_t row = (size_t)y * (size_t)W;
@@ -182,86 +103,11 @@ __device__ __forceinline__ void warp_fill_row(const DevJob& J, int y, const RowI
   }
   __syncthreads();
 
-  // C: store every column (holes get RGBA 0 / +inf / mask 1 for now), build
-  // the hit masks, count holes.  A hit's high word holds the bits of a depth
-  // in (0, +inf], never the all-ones of EMPTY.
-  uint32_t cnt = 0;
-  uint64_t mword = 0;  // lane i: hit mask of chunk i's 64 columns of this wave
-#pragma unroll
-  for (int i = 0; i < PPT; ++i) {
-    if (i <= nfull && i * kThreads < W) {
-      const int x = tid + i * kThreads;
-      const uint64_t k = s.key[min(x, W - 1)];
-      const bool inrow = x < W;
-      const bool hit = inrow & ((uint32_t)(k >> 32) != 0xFFFFFFFFu);
-      const uint32_t c = hit ? (uint32_t)k : 0u;
-      const float zo = hit ? __uint_as_float((uint32_t)(k >> 32)) : __builtin_inff();
-      if (i < nfull) {
-        orow[x] = c;
-        if (zrow) zrow[x] = zo;
-        if (mrow) mrow[x] = hit ? 0 : 1;
-      } else if (inrow) {
-        orow[x] = c;
-        if (zrow) zrow[x] = zo;
-        if (mrow) mrow[x] = hit ? 0 : 1;
-      }
-      const uint64_t hm = __ballot(hit);
-      const uint64_t valid = (i < nfull) ? ~0ull : __ballot(inrow);
-      cnt += (uint32_t)__popcll(valid & ~hm);
-      // Park this chunk's mask in lane i (lo/hi halves) for one store below.
-      mword = (lane == i) ? hm : mword;
-    }
-  }
-  if (fill) {
-    // One LDS store per lane that parked a mask: word (i*4 + wave) holds
-    // chunk i's columns of this wave.
-    const int wave = tid >> 6;
-    const int nchunks = (W + kThreads - 1) / kThreads;
-    const int word = lane * (kThreads / 64) + wave;
-    if (lane < nchunks && word < nw) s.mask[word] = mword;
-    if (cnt) {
-      uint32_t base = 0;
-      if (lane == 0) base = atomicAdd(s.nholes, cnt);
-      base = __builtin_amdgcn_readfirstlane(base);
-#pragma unroll
-      for (int i = 0; i < PPT; ++i) {
-        if (i <= nfull && i * kThreads < W) {
-          const int x = tid + i * kThreads;
-          // readlane returns a signed int: widen through uint32_t, never sign-extend.
-          const uint64_t hm = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mword, i) |
-                              ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(mword >> 32), i) << 32);
-          const uint64_t valid = (i < nfull) ? ~0ull : __ballot(x < W);
-          const uint64_t om = valid & ~hm;
-          if ((om >> lane) & 1ull) {
-            const uint32_t below =
-                __builtin_amdgcn_mbcnt_hi((uint32_t)(om >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)om, 0u));
-            s.holes[base + below] = (uint16_t)x;
-          }
-          base += (uint32_t)__popcll(om);
-        }
-      }
-    }
-    __syncthreads();
-    // E: fill the listed holes.  Only hits are read, only holes written.
-    const int nh = (int)*s.nholes;
-    for (int h0 = tid - lane; h0 < nh; h0 += kThreads) {  // whole waves: the scan reads need every lane
-      const int h = h0 + lane;
-      int x = h < nh ? (int)s.holes[h] : 0;
-      const bool act = (h < nh) & (x < W);  // every listed column is < W; guard the store anyway
-      x = act ? x : 0;
-      int L, R;
-      nearest_hits_walk(s.mask, nw, W, x, L, R);
-      const uint32_t zl = (uint32_t)(s.key[max(L, 0)] >> 32);
-      const uint32_t zr = (uint32_t)(s.key[min(R, W - 1)] >> 32);
-      const int p = pick_side(L, R, W, zl, zr, target_right);
-      const uint64_t k = s.key[max(p, 0)];
-      if (act) {
-        orow[x] = p >= 0 ? (uint32_t)k : 0u;
-        if (zrow) zrow[x] = p >= 0 ? __uint_as_float((uint32_t)(k >> 32)) : __builtin_inff();
-        if (mrow) mrow[x] = p >= 0 ? 1 : 2;
-      }
-    }
-  }
+  resolve_fill_row<PPT>(s, W, target_right, fill, [&](int x, uint32_t c, uint32_t zb, uint8_t mk) {
+    orow[x] = c;
+    if (zrow) zrow[x] = __uint_as_float(zb);
+    if (mrow) mrow[x] = mk;
+  });
   __syncthreads();  // the next row reuses the LDS
 }
 

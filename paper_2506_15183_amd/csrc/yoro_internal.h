@@ -70,6 +70,13 @@ inline size_t fill_lds_bytes(int wl) {
   return w * 4 + w * 4 + (w / 64) * 8;
 }
 
+// Texel slots the low-resolution kernel keeps in LDS for rows up to
+// max_width columns at k = 1 << lg: ceil(max_width / k) rounded up to 64.
+inline int lowres_texel_slots(int max_width, int lg) {
+  const int wk = (max_width + (1 << lg) - 1) >> lg;
+  return (wk + 63) & ~63;
+}
+
 // Launchers (defined in warp_fill.hip).  They return hipSuccess or the launch error.
 hipError_t launch_warp_single(const DevJob& job, int ppt, int grid, hipStream_t stream);
 hipError_t launch_warp_batch(const BatchHeader* hdr, const DevJob* jobs, int max_width, int grid,
@@ -121,5 +128,13 @@ hipError_t nn_composite_tiles(const float* res, const int* plan, int k, int crop
 // Occupancy-derived workgroups per CU for the row kernels.
 int warp_blocks_per_cu(int max_width, bool batch);
 int fill_blocks_per_cu(int width, int fill_mode);
+
+// Reprojection through a downsampled intermediate buffer (lowres.hip):
+// k = 1 << lg (lg 0..4), units of G = 1 << glg rows (glg <= lg).  one != NULL
+// launches that single frame; otherwise the batch table (hdr, jobs).
+size_t lowres_lds_bytes(int max_width, int lg);
+int lowres_blocks_per_cu(int max_width, int lg, bool batch);
+hipError_t launch_lowres(const DevJob* one, const BatchHeader* hdr, const DevJob* jobs, int max_width, int lg,
+                         int glg, int linear, int grid, hipStream_t stream);
 
 }  // namespace yoro

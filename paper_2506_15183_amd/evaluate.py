@@ -1,6 +1,7 @@
 """Hole PSNR of the plain nearest-background fill, the paper's Patcher and
 the learned fill against the ray-cast target eye on held-out full frames,
-and the learned fill's inference throughput.
+the learned fill's inference throughput, and the whole-image error of the
+reprojection through a downsampled intermediate buffer at scales 2-16.
 
     python -m paper_2506_15183_amd.evaluate --frames 16
 
@@ -24,6 +25,7 @@ from . import train, unet, yoro
 from .scenes.configs import config4_test_frames
 
 BF16_PEAK_TFLOPS = 2500.0  # MI355X dense bf16 matrix peak, vendor figure
+LOWRES_SCALES = (2, 4, 8, 16)  # intermediate-buffer scales measured beside the direct path
 
 
 def algorithmic_flops(h: int, w: int, n: int = 1) -> float:
@@ -52,6 +54,10 @@ def evaluate(net: unet.UNet, n_frames: int = 16, log=None, timing_reps: int = 5)
     patch_times = []
     blocks, blocks_total, hole_frac = 0, 0, []
     times = []
+    # Downsampled intermediate buffer: whole-image error against the ray-cast
+    # eye and against the direct path, and its hole count, per (scale, linear).
+    low = {(k, lin): np.zeros(5, dtype=np.int64) for k in LOWRES_SCALES for lin in (False, True)}
+    direct_full = np.zeros(2, dtype=np.int64)
     for i, spec in enumerate(config4_test_frames(n_frames)):
         s_rgba, s_depth = spec.render_source()
         t_rgba, _ = spec.render_target()
@@ -81,6 +87,14 @@ def evaluate(net: unet.UNet, n_frames: int = 16, log=None, timing_reps: int = 5)
         ev[1].record()
         torch.cuda.synchronize()
         patch_times.append(ev[0].elapsed_time(ev[1]))
+        direct_full += _sse(rgba, tgt, None)
+        lbuf = (torch.empty_like(rgba), None, torch.empty_like(mask))
+        for (k, lin), acc in low.items():
+            lr, _, lm = yoro.reproject_lowres(src, srd, spec.baseline_m, spec.focal_px, spec.target_eye,
+                                              yoro.FILL_NEAREST_BG, k, lin, out=lbuf)
+            acc[0:2] += _sse(lr, tgt, None)
+            acc[2:4] += _sse(lr, rgba, None)
+            acc[4] += int((lm != 0).sum().item())
         sp = _sse(rgba, tgt, mask)
         sl = _sse(out, tgt, mask)
         sq = _sse(prgba, tgt, mask)
@@ -112,6 +126,11 @@ def evaluate(net: unet.UNet, n_frames: int = 16, log=None, timing_reps: int = 5)
         "learned_tflops": round(fl / (ms * 1e-3) / 1e12, 2),
         "learned_frac_of_bf16_peak": round(fl / (ms * 1e-3) / 1e12 / BF16_PEAK_TFLOPS, 4),
         "learned_flops_per_frame": fl,
+        "image_psnr_direct_db": round(_psnr(*direct_full), 3),
+        "lowres": [{"scale": k, "linear": lin,
+                    "image_psnr_db": round(_psnr(int(a[0]), int(a[1])), 3),
+                    "psnr_vs_direct_db": round(_psnr(int(a[2]), int(a[3])), 3),
+                    "hole_fraction": round(int(a[4]) / int(a[1]), 4)} for (k, lin), a in low.items()],
     }
 
 

@@ -22,15 +22,19 @@ import sqlite3
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCE = os.path.join(HERE, "csrc", "warp_fill.hip")
+# The warp kernel's source: its own file and the row machinery it includes.
+KERNEL_SOURCES = (os.path.join(HERE, "csrc", "warp_fill.hip"), os.path.join(HERE, "csrc", "row_common.h"))
 WARP_KERNEL = "warp_batch_kernel"
 COPY_BYTES = 1 << 30
 
 
 def kernel_source_sha() -> str:
     """Short hash of the kernel source the counters were taken on."""
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def counters_workload(launches: int = 5) -> None:

@@ -24,10 +24,12 @@ MAX_WIDTH, MAX_HEIGHT = 8192, 16384
 # include/yoro_nn.h are bound in unet.py).
 EXPORTS = (
     "yoro_reproject",
+    "yoro_reproject_lowres",
     "yoro_fill_holes",
     "yoro_stereo_batch_workspace_bytes",
     "yoro_stereo_batch_prepare",
     "yoro_stereo_batch_launch",
+    "yoro_stereo_batch_launch_lowres",
     "yoro_stereo_batch",
     "yoro_stereo_batch_errors",
     "yoro_hole_sse",
@@ -74,6 +76,10 @@ def load():
     vp, i32, f32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_float
     L.yoro_reproject.argtypes = [vp, vp, i32, i32, f32, f32, i32, i32, vp, vp, vp, vp]
     L.yoro_reproject.restype = i32
+    L.yoro_reproject_lowres.argtypes = [vp, vp, i32, i32, f32, f32, i32, i32, i32, i32, vp, vp, vp, vp]
+    L.yoro_reproject_lowres.restype = i32
+    L.yoro_stereo_batch_launch_lowres.argtypes = [vp, i32, i32, i32, vp]
+    L.yoro_stereo_batch_launch_lowres.restype = i32
     L.yoro_fill_holes.argtypes = [vp, vp, vp, i32, i32, i32, i32, vp]
     L.yoro_fill_holes.restype = i32
     L.yoro_stereo_batch_workspace_bytes.argtypes = [i32]
@@ -135,6 +141,26 @@ def reproject(src_rgba, src_depth, baseline_m: float, focal_px: float, target_ey
     return rgba, depth, mask
 
 
+def reproject_lowres(src_rgba, src_depth, baseline_m: float, focal_px: float, target_eye: int = TARGET_RIGHT,
+                     fill_mode: int = FILL_NEAREST_BG, scale: int = 4, linear: bool = True, out=None,
+                     with_depth: bool = True, with_mask: bool = True, stream=None):
+    """Warp one frame to the other eye through a 1/scale intermediate buffer.
+    Returns (rgba, depth or None, mask or None)."""
+    H, W = src_depth.shape
+    _need(src_rgba, torch.uint8, (H, W, 4), "src_rgba")
+    _need(src_depth, torch.float32, (H, W), "src_depth")
+    if out is None:
+        dev = src_depth.device
+        out = (torch.empty((H, W, 4), dtype=torch.uint8, device=dev),
+               torch.empty((H, W), dtype=torch.float32, device=dev) if with_depth else None,
+               torch.empty((H, W), dtype=torch.uint8, device=dev) if with_mask else None)
+    rgba, depth, mask = out
+    _check(load().yoro_reproject_lowres(_ptr(src_rgba), _ptr(src_depth), W, H, float(baseline_m), float(focal_px),
+                                        int(target_eye), int(fill_mode), int(scale), int(bool(linear)), _ptr(rgba),
+                                        _ptr(depth), _ptr(mask), _stream(stream)))
+    return rgba, depth, mask
+
+
 def fill_holes(rgba, depth, mask, target_eye: int = TARGET_RIGHT, fill_mode: int = FILL_NEAREST_BG, stream=None):
     """Fill holes (mask != 0) of a warped frame in place."""
     H, W = depth.shape
@@ -180,6 +206,11 @@ class StereoBatch:
     def launch(self, stream=None, max_width=None):
         _check(load().yoro_stereo_batch_launch(_ptr(self.workspace), int(max_width or self.max_width),
                                                _stream(stream)))
+
+    def launch_lowres(self, scale: int, linear: bool = True, stream=None, max_width=None):
+        """Run the prepared jobs through a 1/scale intermediate buffer."""
+        _check(load().yoro_stereo_batch_launch_lowres(_ptr(self.workspace), int(max_width or self.max_width),
+                                                      int(scale), int(bool(linear)), _stream(stream)))
 
     def run(self, stream=None):
         _check(load().yoro_stereo_batch(self.jobs, self.n, _ptr(self.workspace), self.workspace.numel(),

@@ -102,3 +102,16 @@ def test_host_validation_rejects_without_launching():
     assert b"overlap" in L.yoro_last_error()
     assert L.yoro_stereo_batch_prepare(jobs, 2, ws, 8, None) == yoro.ERR_WORKSPACE_TOO_SMALL
     assert L.yoro_stereo_batch_launch(ws, 0, None) == yoro.ERR_INVALID_ARG
+    # the downsampled-buffer calls: scale and linear are checked too
+    for scale in (0, 3, 32, -1):
+        assert L.yoro_reproject_lowres(fake, fake2, 8, 8, 0.06, 900.0, 0, 1, scale, 1, fake3, None, None,
+                                       None) == yoro.ERR_INVALID_ARG
+        assert L.yoro_stereo_batch_launch_lowres(ws, 8, scale, 1, None) == yoro.ERR_INVALID_ARG
+    assert L.yoro_reproject_lowres(fake, fake2, 8, 8, 0.06, 900.0, 0, 1, 4, 2, fake3, None, None,
+                                   None) == yoro.ERR_INVALID_ARG
+    assert L.yoro_reproject_lowres(None, fake2, 8, 8, 0.06, 900.0, 0, 1, 4, 1, fake3, None, None,
+                                   None) == yoro.ERR_INVALID_ARG
+    assert L.yoro_reproject_lowres(fake, fake2, 8, 8, 0.06, 900.0, 0, 3, 4, 1, fake3, None, None,
+                                   None) == yoro.ERR_INVALID_ARG   # the Patcher needs depth and mask
+    assert L.yoro_stereo_batch_launch_lowres(None, 8, 4, 1, None) == yoro.ERR_INVALID_ARG
+    assert L.yoro_stereo_batch_launch_lowres(ws, 8193, 4, 1, None) == yoro.ERR_INVALID_ARG
