@@ -6,6 +6,7 @@ Workflow (each step its own process; the GPU steps under rocprofv3):
   2. rocprofv3 --pmc FETCH_SIZE -d OUT/fetch -o f -- python -m paper_2506_15183_amd.profiling counters
   3. rocprofv3 --pmc WRITE_SIZE -d OUT/write -o w -- python -m paper_2506_15183_amd.profiling counters
   4. python -m paper_2506_15183_amd.profiling summarize OUT > profiles/<kernel>_<workload>.md
+     (summarize-lowres OUT for the downsampled-buffer kernel)
 
 The ``counters`` workload launches the batched warp kernel a few times on the
 64-frame batch and, for calibration, a plain elementwise kernel that reads
@@ -25,6 +26,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # The warp kernel's source: its own file and the row machinery it includes.
 KERNEL_SOURCES = (os.path.join(HERE, "csrc", "warp_fill.hip"), os.path.join(HERE, "csrc", "row_common.h"))
 WARP_KERNEL = "warp_batch_kernel"
+LOWRES_KERNEL = "lowres_batch_kernel"
+LOWRES_SOURCES = (os.path.join(HERE, "csrc", "lowres.hip"), os.path.join(HERE, "csrc", "row_common.h"))
+LOWRES_COUNTED = (4, 16)  # scales whose HBM counters the counters workload takes
 COPY_BYTES = 1 << 30
 
 
@@ -35,6 +39,22 @@ def kernel_source_sha() -> str:
         with open(path, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
+
+
+def _sha(paths) -> str:
+    h = hashlib.sha256()
+    for path in paths:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def lowres_lds_bytes(max_width: int, k: int) -> int:
+    """Dynamic LDS of the downsampled-buffer kernel (as the library sizes it):
+    the row's keys, hit masks, hole counter and list, plus the texel slots."""
+    wl = (max_width + 63) & ~63
+    slots = (((max_width + k - 1) // k) + 63) & ~63
+    return (wl + 64) * 8 + (wl // 64) * 8 + 16 + wl * 2 + slots * 8
 
 
 def counters_workload(launches: int = 5) -> None:
@@ -54,6 +74,10 @@ def counters_workload(launches: int = 5) -> None:
     batch.prepare()
     for _ in range(launches):
         batch.launch()
+    # The same batch through the downsampled intermediate buffer.
+    for k in LOWRES_COUNTED:
+        for _ in range(launches):
+            batch.launch_lowres(k, True)
     # The calibration kernel: an elementwise pass that reads and writes
     # COPY_BYTES each (torch's bitwise_not on int32).
     a = torch.ones(COPY_BYTES // 4, dtype=torch.int32, device=dev)
@@ -245,6 +269,72 @@ def summarize(out_dir: str, pixels: int, algo_bytes_per_px: int = 12) -> str:
     return "\n".join(lines)
 
 
+def summarize_lowres(out_dir: str, pixels: int, max_width: int = 2160) -> str:
+    """The downsampled-buffer kernel per scale: durations from the bench trace
+    (dispatches told apart by their LDS size, which depends on the scale) and
+    HBM bytes from the counter runs."""
+    scales = (1, 2, 4, 8, 16)
+    lds = {lowres_lds_bytes(max_width, k): k for k in scales}
+
+    def scale_of(size):
+        return lds[min(lds, key=lambda b: abs(b - size))]
+
+    c = _db(os.path.join(out_dir, "trace"))
+    dur = {k: [] for k in scales}
+    for name, size, d in c.execute("select name, lds_size, duration from kernels"):
+        if LOWRES_KERNEL in name:
+            dur[scale_of(size)].append(float(d))
+    counted = {}
+    for cname, sub in (("FETCH_SIZE", "fetch"), ("WRITE_SIZE", "write")):
+        cc = _db(os.path.join(out_dir, sub))
+        vals, copy = {k: [] for k in scales}, []
+        for name, size, cn, v in cc.execute(
+                "select kernel_name, lds_block_size, counter_name, value from counters_collection"):
+            if cn != cname:
+                continue
+            if LOWRES_KERNEL in name:
+                vals[scale_of(size)].append(v)
+            elif "bitwise_not" in name.lower() or "bitwisenot" in name.lower():
+                copy.append(v)
+        scale = COPY_BYTES / (sum(copy) / len(copy) * 1024.0)
+        for k in scales:
+            if vals[k]:
+                counted.setdefault(k, {})[cname] = sum(vals[k]) / len(vals[k]) * 1024.0 * scale
+    lines = [
+        "# lowres_batch_kernel (downsampled intermediate buffer) on the 64-frame mixed-resolution batch",
+        "",
+        "Commands (from the repository root, on one MI355X; OUT=gpurun_out/prof):",
+        "",
+        "```",
+        "rocprofv3 --kernel-trace --stats -d $OUT/trace -o t -- python bench.py --no-cpu-baseline --no-single-frame --serve-seconds 0 --eval-frames 0",
+        "rocprofv3 --pmc FETCH_SIZE -d $OUT/fetch -o f -- python -m paper_2506_15183_amd.profiling counters",
+        "rocprofv3 --pmc WRITE_SIZE -d $OUT/write -o w -- python -m paper_2506_15183_amd.profiling counters",
+        "python -m paper_2506_15183_amd.profiling summarize-lowres $OUT",
+        "```",
+        "",
+        "RGBA output only, interpolated shift, one unit = one block row of k rows.",
+        "Algorithmic bytes per pixel: 4 B gathered + 4 B written + 4/k^2 B of block-centre depth.",
+        "Counter bytes are scaled as for the warp kernel (copy-kernel calibration).",
+        "",
+        "| k | dispatches | median us | mean us | algorithmic GB | algorithmic TB/s (mean) | HBM read GB | HBM written GB | HBM / algorithmic |",
+        "|---|---|---|---|---|---|---|---|---|",
+    ]
+    for k in scales:
+        d = sorted(dur[k])
+        if not d:
+            continue
+        mean = sum(d) / len(d)
+        algo = (8.0 + 4.0 / (k * k)) * pixels
+        cnt = counted.get(k, {})
+        rd, wr = cnt.get("FETCH_SIZE"), cnt.get("WRITE_SIZE")
+        ratio = f"{(rd + wr) / algo:.3f}" if rd is not None and wr is not None else "-"
+        lines.append(f"| {k} | {len(d)} | {d[len(d) // 2] / 1e3:.1f} | {mean / 1e3:.1f} | {algo / 1e9:.4f} | "
+                     f"{algo / (mean * 1e-9) / 1e12:.2f} | {'-' if rd is None else f'{rd / 1e9:.4f}'} | "
+                     f"{'-' if wr is None else f'{wr / 1e9:.4f}'} | {ratio} |")
+    lines += ["", f"kernel_source_sha: {_sha(LOWRES_SOURCES)}", ""]
+    return "\n".join(lines)
+
+
 def read_summary(path: str):
     """(traffic bytes per launch, kernel source sha) from a committed summary, or (None, None)."""
     if not os.path.exists(path):
@@ -262,6 +352,11 @@ if __name__ == "__main__":
         learned_workload()
     elif len(sys.argv) >= 3 and sys.argv[1] == "summarize-learned":
         print(summarize_learned(sys.argv[2]))
+    elif len(sys.argv) >= 3 and sys.argv[1] == "summarize-lowres":
+        sys.path.insert(0, os.path.dirname(HERE))
+        from paper_2506_15183_amd.scenes import config3_frames
+
+        print(summarize_lowres(sys.argv[2], sum(s.pixels for s in config3_frames())))
     elif len(sys.argv) >= 3 and sys.argv[1] == "summarize":
         sys.path.insert(0, os.path.dirname(HERE))
         from paper_2506_15183_amd.scenes import config3_frames
