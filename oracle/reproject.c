@@ -468,6 +468,154 @@ int oracle_reproject_lowres(const uint8_t* src_rgba, const float* src_depth, int
 }
 
 /*
+ * Reprojection through a general pose (Section 6: the rotation matrix of a
+ * unit quaternion, Equation rmatrix; the view and projection matrices; the
+ * reprojection M = (VP_src)^-1 VP_tgt).  The printed view matrix has a zero
+ * bottom row and the printed projection has no perspective divide, so the
+ * cameras are taken as the pinholes the rest of the method assumes.
+ * Readings:
+ *   cameras: x right, y down, z forward; focal length f px, principal point
+ *   (cx, cy); pixel (x, y) with planar depth z is the point
+ *   ((x - cx) z / f, (y - cy) z / f, z) of its eye's camera;
+ *   the pose (q, t): the target eye's orientation (unit quaternion,
+ *   q[0] = r_x the scalar part, as Equation rmatrix places it) and position,
+ *   both in the source eye's camera frame; a source-camera point X is
+ *   X_t = R^T (X - t) in the target camera (for parallel stereo the right
+ *   eye is q = (1, 0, 0, 0), t = (B, 0, 0), and this is the direct path);
+ *   A = R^T and b = -(R^T t) are formed in double from Equation rmatrix, in
+ *   the order written below, and rounded to FP32;
+ *   per source pixel, in FP32 with each operation rounded once:
+ *     a = (x - cx) / f, c = (y - cy) / f;
+ *     finite z > 0:  X = a z, Y = c z,
+ *                    X_t = ((A00 X + A01 Y) + A02 z) + b0 (Y_t, Z_t alike),
+ *                    target depth Z_t;
+ *     z = +inf (a point at infinity: only the rotation moves it):
+ *                    X_t = (A00 a + A01 c) + A02 (Y_t, Z_t alike),
+ *                    target depth +inf;
+ *     any other z (NaN, <= 0) is not splatted;
+ *     skipped unless Z_t > 0; xf = f (X_t / Z_t) + cx, yf = f (Y_t / Z_t) + cy,
+ *     the target pixel (roundf(xf), roundf(yf)), skipped unless inside the
+ *     frame;
+ *   two-dimensional depth test over the whole frame: the least key
+ *   (target depth bits << 32) | source index wins (equal depths can meet
+ *   here, and the lower source index then wins);
+ *   resolve as the direct path (the source pixel's RGBA, the target depth);
+ *   fill per target row as the direct path, the tie side opposite the shift
+ *   read from the translation: right when t_x >= 0, else left.
+ */
+static void pose_matrix(const float* q, const float* t, float* A, float* b) {
+  const double rx = q[0], ry = q[1], rz = q[2], rw = q[3];
+  double R[3][3];
+  R[0][0] = 1.0 - 2.0 * rz * rz - 2.0 * rw * rw;
+  R[0][1] = 2.0 * ry * rz - 2.0 * rx * rw;
+  R[0][2] = 2.0 * ry * rw + 2.0 * rx * rz;
+  R[1][0] = 2.0 * ry * rz + 2.0 * rx * rw;
+  R[1][1] = 1.0 - 2.0 * ry * ry - 2.0 * rw * rw;
+  R[1][2] = 2.0 * rz * rw - 2.0 * rx * ry;
+  R[2][0] = 2.0 * ry * rw - 2.0 * rx * rz;
+  R[2][1] = 2.0 * rz * rw + 2.0 * rx * ry;
+  R[2][2] = 1.0 - 2.0 * ry * ry - 2.0 * rz * rz;
+  for (int i = 0; i < 3; ++i) {
+    for (int j = 0; j < 3; ++j) A[3 * i + j] = (float)R[j][i];
+    b[i] = (float)(-((R[0][i] * (double)t[0] + R[1][i] * (double)t[1]) + R[2][i] * (double)t[2]));
+  }
+}
+
+/* Target pixel and depth of one source pixel; returns 0 when it is splatted. */
+int oracle_project_pose(float z, int32_t x, int32_t y, int32_t width, int32_t height, float focal_px, float cx,
+                        float cy, const float* q, const float* t, int32_t* xt, int32_t* yt, float* zt) {
+  float A[9], b[3];
+  pose_matrix(q, t, A, b);
+  const float a = ((float)x - cx) / focal_px;
+  const float c = ((float)y - cy) / focal_px;
+  float Xt, Yt, Zt, depth;
+  if (z == INFINITY) {
+    Xt = (A[0] * a + A[1] * c) + A[2];
+    Yt = (A[3] * a + A[4] * c) + A[5];
+    Zt = (A[6] * a + A[7] * c) + A[8];
+    depth = INFINITY;
+  } else if (z > 0.0f) {
+    const float X = a * z, Y = c * z;
+    Xt = ((A[0] * X + A[1] * Y) + A[2] * z) + b[0];
+    Yt = ((A[3] * X + A[4] * Y) + A[5] * z) + b[1];
+    Zt = ((A[6] * X + A[7] * Y) + A[8] * z) + b[2];
+    depth = Zt;
+  } else {
+    return -1;
+  }
+  if (!(Zt > 0.0f)) return -1;
+  const float xf = focal_px * (Xt / Zt) + cx;
+  const float yf = focal_px * (Yt / Zt) + cy;
+  const float rxf = roundf(xf), ryf = roundf(yf);
+  if (!(rxf >= 0.0f && rxf < (float)width && ryf >= 0.0f && ryf < (float)height)) return -1;
+  *xt = (int32_t)rxf;
+  *yt = (int32_t)ryf;
+  *zt = depth;
+  return 0;
+}
+
+int oracle_reproject_pose(const uint8_t* src_rgba, const float* src_depth, int32_t width, int32_t height,
+                          float focal_px, float cx, float cy, const float* q, const float* t, int32_t fill_mode,
+                          uint8_t* dst_rgba, float* dst_depth, uint8_t* dst_mask) {
+  if (width <= 0 || height <= 0 || !src_rgba || !src_depth || !dst_rgba || !q || !t) return -1;
+  if (fill_mode != OR_FILL_NONE && fill_mode != OR_FILL_NEAREST_BG) return -1;
+  const size_t n = (size_t)width * (size_t)height;
+  uint64_t* K = (uint64_t*)malloc(sizeof(uint64_t) * n);
+  for (size_t i = 0; i < n; ++i) K[i] = OR_EMPTY;
+  /* Scatter with the depth test over the whole frame. */
+  for (int32_t y = 0; y < height; ++y)
+    for (int32_t x = 0; x < width; ++x) {
+      const size_t i = (size_t)y * (size_t)width + (size_t)x;
+      int32_t xt, yt;
+      float zt;
+      if (oracle_project_pose(src_depth[i], x, y, width, height, focal_px, cx, cy, q, t, &xt, &yt, &zt) != 0)
+        continue;
+      const size_t o = (size_t)yt * (size_t)width + (size_t)xt;
+      const uint64_t key = ((uint64_t)float_bits(zt) << 32) | (uint64_t)(uint32_t)i;
+      if (key < K[o]) K[o] = key;
+    }
+  /* Resolve and fill, row by row of the target. */
+  const int32_t s = (t[0] >= 0.0f) ? -1 : +1;
+  uint8_t* hit = (uint8_t*)malloc((size_t)width);
+  float* zr = (float*)malloc(sizeof(float) * (size_t)width);
+  uint8_t* col = (uint8_t*)malloc(4 * (size_t)width);
+  float* dz = (float*)malloc(sizeof(float) * (size_t)width);
+  uint8_t* mk = (uint8_t*)malloc((size_t)width);
+  for (int32_t y = 0; y < height; ++y) {
+    const size_t row = (size_t)y * (size_t)width;
+    for (int32_t x = 0; x < width; ++x) {
+      const uint64_t k = K[row + (size_t)x];
+      if (k == OR_EMPTY) {
+        hit[x] = 0;
+        zr[x] = INFINITY;
+        memset(&col[4 * x], 0, 4);
+        dz[x] = INFINITY;
+        mk[x] = 1;
+      } else {
+        const size_t i = (size_t)(uint32_t)k;
+        hit[x] = 1;
+        zr[x] = bits_float((uint32_t)(k >> 32));
+        memcpy(&col[4 * x], &src_rgba[4 * i], 4);
+        dz[x] = zr[x];
+        mk[x] = 0;
+      }
+    }
+    uint8_t* orow = &dst_rgba[4 * row];
+    memcpy(orow, col, 4 * (size_t)width);
+    if (fill_mode != OR_FILL_NONE) fill_row(orow, dz, mk, hit, zr, col, width, s, fill_mode);
+    if (dst_depth) memcpy(&dst_depth[row], dz, sizeof(float) * (size_t)width);
+    if (dst_mask) memcpy(&dst_mask[row], mk, (size_t)width);
+  }
+  free(K);
+  free(hit);
+  free(zr);
+  free(col);
+  free(dz);
+  free(mk);
+  return 0;
+}
+
+/*
  * Hole error against a reference image (Section 9, PSNR): the sum of squared
  * RGB differences over pixels with mask != 0, and the number of such pixels.
  * Integer arithmetic, so the sum is exact.

@@ -47,6 +47,16 @@ def lib():
                                               ctypes.c_float, ctypes.c_float, ctypes.c_int32, ctypes.c_int32,
                                               ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                               ctypes.c_void_p]
+        L.oracle_reproject_pose.restype = ctypes.c_int
+        L.oracle_reproject_pose.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                            ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_void_p]
+        L.oracle_project_pose.restype = ctypes.c_int
+        L.oracle_project_pose.argtypes = [ctypes.c_float, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                          ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float)]
         L.oracle_fill_holes.restype = ctypes.c_int
         L.oracle_fill_holes.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                         ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
@@ -106,6 +116,42 @@ def reproject_lowres(src_rgba: np.ndarray, src_depth: np.ndarray, baseline_m: fl
     if rc != 0:
         raise ValueError("oracle_reproject_lowres: bad arguments")
     return dst, dz, mk
+
+
+def _pose_arrays(q, t):
+    q = np.ascontiguousarray(q, dtype=np.float32).reshape(4)
+    t = np.ascontiguousarray(t, dtype=np.float32).reshape(3)
+    return q, t
+
+
+def reproject_pose(src_rgba: np.ndarray, src_depth: np.ndarray, focal_px: float, cx: float, cy: float, q, t,
+                   fill_mode: int = FILL_NEAREST_BG):
+    """Reprojection to an eye at pose (q = (r_x scalar, r_y, r_z, r_w), t) in the
+    source eye's camera frame (Section 6): (dst_rgba, dst_depth, dst_mask)."""
+    src_rgba = np.ascontiguousarray(src_rgba, dtype=np.uint8)
+    src_depth = np.ascontiguousarray(src_depth, dtype=np.float32)
+    H, W = src_depth.shape
+    assert src_rgba.shape == (H, W, 4)
+    q, t = _pose_arrays(q, t)
+    dst = np.empty_like(src_rgba)
+    dz = np.empty_like(src_depth)
+    mk = np.empty((H, W), dtype=np.uint8)
+    rc = lib().oracle_reproject_pose(src_rgba.ctypes.data, src_depth.ctypes.data, W, H, float(np.float32(focal_px)),
+                                     float(np.float32(cx)), float(np.float32(cy)), q.ctypes.data, t.ctypes.data,
+                                     fill_mode, dst.ctypes.data, dz.ctypes.data, mk.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle_reproject_pose: bad arguments")
+    return dst, dz, mk
+
+
+def project_pose(z: float, x: int, y: int, width: int, height: int, focal_px: float, cx: float, cy: float, q, t):
+    """(target x, target y, target depth) of one source pixel, or None when it is not splatted."""
+    q, t = _pose_arrays(q, t)
+    xt, yt, zt = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_float(0)
+    rc = lib().oracle_project_pose(float(np.float32(z)), x, y, width, height, float(np.float32(focal_px)),
+                                   float(np.float32(cx)), float(np.float32(cy)), q.ctypes.data, t.ctypes.data,
+                                   ctypes.byref(xt), ctypes.byref(yt), ctypes.byref(zt))
+    return None if rc != 0 else (int(xt.value), int(yt.value), float(np.float32(zt.value)))
 
 
 def fill_holes(rgba: np.ndarray, depth: np.ndarray, mask: np.ndarray, target_eye: int = TARGET_RIGHT,
