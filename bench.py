@@ -9,9 +9,9 @@ by ONE persistent kernel launch replayed from a captured HIP graph.
 Beside the timed step the same run reports the other parts of the metric:
 hole PSNR of the plain and learned fills against the ray-cast target eye on
 held-out 1832x1920 frames (with the learned fill's matrix-core throughput),
-and p50/p99 frame latency of the serving loop for 32 headsets; and the same
+and p50/p99 frame latency of the serving loop for 32 headsets; the same
 batch through a downsampled intermediate buffer (scales 1-16), whose image
-error the evaluation reports.
+error the evaluation reports; and one frame reprojected to a general pose.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--serve-seconds S] [--eval-frames F]
 Prints one JSON line.
@@ -187,6 +187,46 @@ def main():
         assert batch.errors() == 0
         log(f"downsampled buffer: {lowres}")
 
+    # ----------------------------- one frame through a general pose (head motion)
+    pose = None
+    if not args.no_single_frame:
+        import math
+
+        spec2 = config2_frame(0)
+        r2, d2 = spec2.render_source()
+        sets = 8
+        p_src = [(torch.from_numpy(r2).to(dev), torch.from_numpy(d2).to(dev)) for _ in range(sets)]
+        p_dst = [torch.empty((spec2.height, spec2.width, 4), dtype=torch.uint8, device=dev) for _ in range(sets)]
+        ws_bytes = int(yoro.load().yoro_reproject_pose_workspace_bytes(spec2.width, spec2.height))
+        p_ws = [torch.empty(ws_bytes, dtype=torch.uint8, device=dev) for _ in range(sets)]
+        h = math.radians(3.0) / 2
+        axis = np.array([0.2, 1.0, 0.1]) / np.linalg.norm([0.2, 1.0, 0.1])
+        q = (math.cos(h), *(math.sin(h) * axis))
+        t = (0.02, -0.01, 0.05)
+        cx, cy = spec2.width / 2.0, spec2.height / 2.0
+
+        def run_pose(k):
+            yoro.reproject_pose(*p_src[k], spec2.focal_px, cx, cy, q, t, yoro.FILL_NEAREST_BG,
+                                out=(p_dst[k], None, None), workspace=p_ws[k], stream=stream)
+
+        for _ in range(3):
+            for k in range(sets):
+                run_pose(k)
+        torch.cuda.synchronize()
+        n_rep = 40
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n_rep)]
+        with torch.cuda.stream(stream):
+            for i in range(n_rep):
+                evs[i][0].record(stream)
+                run_pose(i % sets)
+                evs[i][1].record(stream)
+        torch.cuda.synchronize()
+        ms = float(np.median([a.elapsed_time(b) for a, b in evs]))
+        pose = {"workload": "one 1832x1920 frame, head motion (3 degrees about a tilted axis, 5.5 cm), "
+                            "RGBA output, 8 rotated buffer sets; clear + 2-D scatter + row resolve/fill",
+                "launch_ms_median": round(ms, 4), "mpix_s": round(spec2.pixels / (ms * 1e-3) / 1e6, 1)}
+        log(f"general pose: {pose}")
+
     # ------------------------------------------------------ CPU oracle baseline
     cpu = None
     parity = None
@@ -305,6 +345,7 @@ def main():
         "parity_vs_oracle": parity,
         "single_frame": single,
         "lowres_batch": lowres,
+        "pose_single_frame": pose,
         "hole_psnr": quality,
         "learned_fill_roofline": learned_roof,
         "serving": serving,

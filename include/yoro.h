@@ -216,6 +216,47 @@ int32_t yoro_stereo_batch_launch_lowres(const void* dev_workspace, int32_t max_w
                                         int32_t linear, void* hip_stream);
 
 /*
+ * yoro_reproject_pose -- warp one frame to an eye at a general pose (Section
+ * 6: the rotation matrix of a unit quaternion, the view and projection
+ * matrices and the reprojection M = (VP_src)^-1 VP_tgt), for rotated or
+ * toed-in eyes and head motion, and fill its disocclusions.
+ *
+ * Cameras are pinholes: focal_px, principal point (cx, cy), x right, y
+ * down, z forward; pixel (x, y) with planar depth z is the point
+ * ((x - cx) z / f, (y - cy) z / f, z) of its eye.  rotation (host, 4 floats:
+ * r_x the scalar part, then r_y, r_z, r_w, as Equation rmatrix places them;
+ * |q| within 1e-4 of 1) and translation (host, 3 floats, metres) are the
+ * target eye's orientation and position in the source eye's camera frame,
+ * so a point X maps to X_t = R^T (X - t); parallel stereo's right eye is
+ * rotation (1, 0, 0, 0), translation (B, 0, 0).  The library forms
+ * A = R^T and b = -R^T t in double and rounds them to FP32; then per source
+ * pixel, in FP32 with each operation rounded once:
+ *   a = (x - cx) / f, c = (y - cy) / f;
+ *   finite z > 0: X = a z, Y = c z, X_t = ((A00 X + A01 Y) + A02 z) + b0
+ *                 (Y_t, Z_t alike), target depth Z_t;
+ *   z = +inf:     X_t = (A00 a + A01 c) + A02 (alike), target depth +inf;
+ *   other z:      not splatted;
+ *   skipped unless Z_t > 0; xf = f (X_t / Z_t) + cx, yf = f (Y_t / Z_t) + cy;
+ *   target (roundf(xf), roundf(yf)), skipped unless inside the frame;
+ *   over the whole frame the least (target depth bits << 32 | source index)
+ *   wins.
+ * Hits take the source pixel's RGBA and the target depth; holes are filled
+ * per fill_mode along target rows as yoro_reproject fills them, with the
+ * tie side (and the Patcher's orientation) of YORO_TARGET_RIGHT when
+ * translation[0] >= 0 and of YORO_TARGET_LEFT otherwise.
+ *
+ * workspace: device, >= yoro_reproject_pose_workspace_bytes(width, height)
+ * (one u64 per pixel), 16-byte aligned, not overlapping any other buffer;
+ * overwritten.  Other arguments, ownership, outputs and errors as
+ * yoro_reproject.
+ */
+size_t yoro_reproject_pose_workspace_bytes(int32_t width, int32_t height);
+int32_t yoro_reproject_pose(const uint8_t* src_rgba, const float* src_depth, int32_t width, int32_t height,
+                            float focal_px, float cx, float cy, const float* rotation, const float* translation,
+                            int32_t fill_mode, uint8_t* dst_rgba, float* dst_depth, uint8_t* dst_mask,
+                            void* workspace, size_t workspace_bytes, void* hip_stream);
+
+/*
  * yoro_hole_sse -- hole error of a synthesised eye against a reference image
  * (Section 9, PSNR = 10 log10(255^2 / MSE)).  Writes to dev_out[0] the sum
  * of squared R, G, B differences over pixels with mask != 0 (over all

@@ -55,6 +55,28 @@ bool device_facts(DeviceFacts* out) {
 
 int pick_ppt(int width) { return yoro::ppt_for(width); }
 
+// A = R^T and b = -R^T t for the target eye's pose (q, t) in the source
+// eye's frame, R the rotation matrix of the unit quaternion q with q[0] the
+// scalar part (Section 6, Equation rmatrix), formed in double and rounded
+// to FP32 once.
+void pose_affine(const float* q, const float* t, float* A, float* b) {
+  const double w = q[0], x = q[1], y = q[2], z = q[3];
+  double R[3][3];
+  R[0][0] = 1.0 - 2.0 * y * y - 2.0 * z * z;
+  R[0][1] = 2.0 * x * y - 2.0 * w * z;
+  R[0][2] = 2.0 * x * z + 2.0 * w * y;
+  R[1][0] = 2.0 * x * y + 2.0 * w * z;
+  R[1][1] = 1.0 - 2.0 * x * x - 2.0 * z * z;
+  R[1][2] = 2.0 * y * z - 2.0 * w * x;
+  R[2][0] = 2.0 * x * z - 2.0 * w * y;
+  R[2][1] = 2.0 * y * z + 2.0 * w * x;
+  R[2][2] = 1.0 - 2.0 * x * x - 2.0 * y * y;
+  for (int r = 0; r < 3; ++r) {
+    for (int c = 0; c < 3; ++c) A[3 * r + c] = (float)R[c][r];
+    b[r] = (float)(-((R[0][r] * (double)t[0] + R[1][r] * (double)t[1]) + R[2][r] * (double)t[2]));
+  }
+}
+
 // log2 of an intermediate-buffer scale of 1, 2, 4, 8 or 16; -1 otherwise.
 int scale_log2(int32_t scale) {
   for (int lg = 0; lg <= 4; ++lg)
@@ -208,6 +230,77 @@ int32_t yoro_reproject_lowres(const uint8_t* src_rgba, const float* src_depth, i
     return ok();
   } catch (...) {
     return fail(YORO_ERR_DEVICE, "yoro_reproject_lowres: internal error");
+  }
+}
+
+size_t yoro_reproject_pose_workspace_bytes(int32_t width, int32_t height) {
+  if (width <= 0 || height <= 0 || width > YORO_MAX_WIDTH || height > YORO_MAX_HEIGHT) return 0;
+  return (size_t)width * (size_t)height * sizeof(uint64_t);
+}
+
+int32_t yoro_reproject_pose(const uint8_t* src_rgba, const float* src_depth, int32_t width, int32_t height,
+                            float focal_px, float cx, float cy, const float* rotation, const float* translation,
+                            int32_t fill_mode, uint8_t* dst_rgba, float* dst_depth, uint8_t* dst_mask,
+                            void* workspace, size_t workspace_bytes, void* hip_stream) {
+  try {
+    const char* who = "yoro_reproject_pose";
+    // The frame checks of yoro_reproject (baseline and eye do not apply here).
+    int32_t st = check_frame(src_rgba, src_depth, width, height, 1.0f, focal_px, YORO_TARGET_RIGHT, fill_mode,
+                             dst_rgba, dst_depth, dst_mask, who);
+    if (st != YORO_OK) return st;
+    if (!std::isfinite(cx) || !std::isfinite(cy))
+      return fail(YORO_ERR_INVALID_ARG, "%s: principal point (%g, %g) must be finite", who, (double)cx, (double)cy);
+    if (!rotation || !translation) return fail(YORO_ERR_INVALID_ARG, "%s: rotation and translation are required", who);
+    double n2 = 0.0;
+    for (int i = 0; i < 4; ++i) {
+      if (!std::isfinite(rotation[i])) return fail(YORO_ERR_INVALID_ARG, "%s: rotation must be finite", who);
+      n2 += (double)rotation[i] * (double)rotation[i];
+    }
+    if (std::fabs(n2 - 1.0) > 1e-4)
+      return fail(YORO_ERR_INVALID_ARG, "%s: rotation must be a unit quaternion (|q|^2 = %g)", who, n2);
+    for (int i = 0; i < 3; ++i)
+      if (!std::isfinite(translation[i])) return fail(YORO_ERR_INVALID_ARG, "%s: translation must be finite", who);
+    const size_t need = yoro_reproject_pose_workspace_bytes(width, height);
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) & 15u))
+      return fail(YORO_ERR_INVALID_ARG, "%s: workspace must be non-null and 16-byte aligned", who);
+    if (workspace_bytes < need)
+      return fail(YORO_ERR_WORKSPACE_TOO_SMALL, "%s: workspace %zu < %zu bytes", who, workspace_bytes, need);
+    const uintptr_t n = (uintptr_t)width * (uintptr_t)height;
+    const Range ws{(uintptr_t)workspace, (uintptr_t)workspace + need, true};
+    const Range others[] = {{(uintptr_t)src_rgba, (uintptr_t)src_rgba + 4 * n, false},
+                            {(uintptr_t)src_depth, (uintptr_t)src_depth + 4 * n, false},
+                            {(uintptr_t)dst_rgba, (uintptr_t)dst_rgba + 4 * n, true},
+                            {(uintptr_t)dst_depth, dst_depth ? (uintptr_t)dst_depth + 4 * n : 0, true},
+                            {(uintptr_t)dst_mask, dst_mask ? (uintptr_t)dst_mask + n : 0, true}};
+    for (const Range& r : others)
+      if (r.hi > r.lo && overlaps(ws, r)) return fail(YORO_ERR_INVALID_ARG, "%s: the workspace overlaps a buffer", who);
+    const bool patcher = fill_mode == YORO_FILL_PATCHER;
+    if (patcher && (!dst_depth || !dst_mask))
+      return fail(YORO_ERR_INVALID_ARG, "%s: the Patcher fill needs dst_depth and dst_mask", who);
+    yoro::PoseGeom g{};
+    pose_affine(rotation, translation, g.A, g.b);
+    g.f = focal_px;
+    g.cx = cx;
+    g.cy = cy;
+    g.width = width;
+    g.height = height;
+    // The fill's tie side (and the Patcher's orientation) follows the
+    // translation: the side opposite a shift to the right is the right.
+    const int32_t eye = translation[0] >= 0.0f ? YORO_TARGET_RIGHT : YORO_TARGET_LEFT;
+    DeviceFacts f;
+    const int cus = device_facts(&f) ? f.cus : 256;
+    hipError_t e = yoro::launch_pose(reinterpret_cast<const uint32_t*>(src_rgba), src_depth, g,
+                                     patcher ? (int)YORO_FILL_NONE : fill_mode, eye == YORO_TARGET_RIGHT ? 1 : 0,
+                                     reinterpret_cast<uint32_t*>(dst_rgba), dst_depth, dst_mask,
+                                     reinterpret_cast<uint64_t*>(workspace), cus, (hipStream_t)hip_stream);
+    if (e == hipSuccess && patcher)
+      e = yoro::launch_fill(reinterpret_cast<uint32_t*>(dst_rgba), dst_depth, dst_mask, width, height, eye, fill_mode,
+                            pick_ppt(width), grid_for(height, yoro::fill_blocks_per_cu(width, fill_mode)),
+                            (hipStream_t)hip_stream);
+    if (e != hipSuccess) return fail(YORO_ERR_DEVICE, "%s: launch failed: %s", who, hipGetErrorString(e));
+    return ok();
+  } catch (...) {
+    return fail(YORO_ERR_DEVICE, "yoro_reproject_pose: internal error");
   }
 }
 

@@ -129,6 +129,20 @@ hipError_t nn_composite_tiles(const float* res, const int* plan, int k, int crop
 int warp_blocks_per_cu(int max_width, bool batch);
 int fill_blocks_per_cu(int width, int fill_mode);
 
+// Reprojection through a general pose (pose.hip): X_t = A X + b per pinhole
+// point, A = R^T and b = -R^T t of the target eye's pose in the source eye's
+// frame, rounded to FP32 by the host.
+struct PoseGeom {
+  float A[9];
+  float b[3];
+  float f, cx, cy;
+  int32_t width, height;
+};
+// keys: the caller's workspace, width * height u64, 16-byte aligned.
+hipError_t launch_pose(const uint32_t* src_rgba, const float* src_depth, const PoseGeom& g, int fill_mode,
+                       int target_right, uint32_t* dst_rgba, float* dst_depth, uint8_t* dst_mask, uint64_t* keys,
+                       int cus, hipStream_t stream);
+
 // Reprojection through a downsampled intermediate buffer (lowres.hip):
 // k = 1 << lg (lg 0..4), units of G = 1 << glg rows (glg <= lg).  one != NULL
 // launches that single frame; otherwise the batch table (hdr, jobs).

@@ -25,6 +25,8 @@ MAX_WIDTH, MAX_HEIGHT = 8192, 16384
 EXPORTS = (
     "yoro_reproject",
     "yoro_reproject_lowres",
+    "yoro_reproject_pose_workspace_bytes",
+    "yoro_reproject_pose",
     "yoro_fill_holes",
     "yoro_stereo_batch_workspace_bytes",
     "yoro_stereo_batch_prepare",
@@ -80,6 +82,11 @@ def load():
     L.yoro_reproject_lowres.restype = i32
     L.yoro_stereo_batch_launch_lowres.argtypes = [vp, i32, i32, i32, vp]
     L.yoro_stereo_batch_launch_lowres.restype = i32
+    L.yoro_reproject_pose_workspace_bytes.argtypes = [i32, i32]
+    L.yoro_reproject_pose_workspace_bytes.restype = ctypes.c_size_t
+    L.yoro_reproject_pose.argtypes = [vp, vp, i32, i32, f32, f32, f32, vp, vp, i32, vp, vp, vp, vp,
+                                      ctypes.c_size_t, vp]
+    L.yoro_reproject_pose.restype = i32
     L.yoro_fill_holes.argtypes = [vp, vp, vp, i32, i32, i32, i32, vp]
     L.yoro_fill_holes.restype = i32
     L.yoro_stereo_batch_workspace_bytes.argtypes = [i32]
@@ -158,6 +165,34 @@ def reproject_lowres(src_rgba, src_depth, baseline_m: float, focal_px: float, ta
     _check(load().yoro_reproject_lowres(_ptr(src_rgba), _ptr(src_depth), W, H, float(baseline_m), float(focal_px),
                                         int(target_eye), int(fill_mode), int(scale), int(bool(linear)), _ptr(rgba),
                                         _ptr(depth), _ptr(mask), _stream(stream)))
+    return rgba, depth, mask
+
+
+def reproject_pose(src_rgba, src_depth, focal_px: float, cx: float, cy: float, rotation, translation,
+                   fill_mode: int = FILL_NEAREST_BG, out=None, workspace=None, with_depth: bool = True,
+                   with_mask: bool = True, stream=None):
+    """Warp one frame to an eye at pose (rotation = unit quaternion (r_x scalar,
+    r_y, r_z, r_w), translation in metres), both in the source eye's camera
+    frame.  Returns (rgba, depth or None, mask or None)."""
+    H, W = src_depth.shape
+    _need(src_rgba, torch.uint8, (H, W, 4), "src_rgba")
+    _need(src_depth, torch.float32, (H, W), "src_depth")
+    L = load()
+    if workspace is None:
+        workspace = torch.empty(int(L.yoro_reproject_pose_workspace_bytes(W, H)), dtype=torch.uint8,
+                                device=src_depth.device)
+    if out is None:
+        dev = src_depth.device
+        out = (torch.empty((H, W, 4), dtype=torch.uint8, device=dev),
+               torch.empty((H, W), dtype=torch.float32, device=dev) if with_depth else None,
+               torch.empty((H, W), dtype=torch.uint8, device=dev) if with_mask else None)
+    rgba, depth, mask = out
+    q = (ctypes.c_float * 4)(*[float(v) for v in rotation])
+    t = (ctypes.c_float * 3)(*[float(v) for v in translation])
+    _check(L.yoro_reproject_pose(_ptr(src_rgba), _ptr(src_depth), W, H, float(focal_px), float(cx), float(cy),
+                                 ctypes.cast(q, ctypes.c_void_p), ctypes.cast(t, ctypes.c_void_p), int(fill_mode),
+                                 _ptr(rgba), _ptr(depth), _ptr(mask), _ptr(workspace), workspace.numel(),
+                                 _stream(stream)))
     return rgba, depth, mask
 
 

@@ -115,3 +115,22 @@ def test_host_validation_rejects_without_launching():
                                    None) == yoro.ERR_INVALID_ARG   # the Patcher needs depth and mask
     assert L.yoro_stereo_batch_launch_lowres(None, 8, 4, 1, None) == yoro.ERR_INVALID_ARG
     assert L.yoro_stereo_batch_launch_lowres(ws, 8193, 4, 1, None) == yoro.ERR_INVALID_ARG
+    # the general-pose call: a unit quaternion, finite values, a workspace of one u64 per pixel
+    assert L.yoro_reproject_pose_workspace_bytes(8, 8) == 512
+    assert L.yoro_reproject_pose_workspace_bytes(0, 8) == 0
+    q = (ctypes.c_float * 4)(1, 0, 0, 0)
+    t = (ctypes.c_float * 3)(0.06, 0, 0)
+    wsp = ctypes.c_void_p(0x60000000)
+    args = [fake, fake2, 8, 8, 900.0, 4.0, 4.0, q, t, 1, fake3, None, None]
+    assert L.yoro_reproject_pose(*args, None, 512, None) == yoro.ERR_INVALID_ARG       # no workspace
+    assert L.yoro_reproject_pose(*args, wsp, 511, None) == yoro.ERR_WORKSPACE_TOO_SMALL
+    assert L.yoro_reproject_pose(*args, ctypes.c_void_p(0x60000008), 512, None) == yoro.ERR_INVALID_ARG  # alignment
+    assert L.yoro_reproject_pose(*args, ctypes.c_void_p(0x40000000), 512, None) == yoro.ERR_INVALID_ARG  # overlap
+    q2 = (ctypes.c_float * 4)(1, 0.1, 0, 0)
+    assert L.yoro_reproject_pose(fake, fake2, 8, 8, 900.0, 4.0, 4.0, q2, t, 1, fake3, None, None, wsp, 512,
+                                 None) == yoro.ERR_INVALID_ARG                          # not a unit quaternion
+    assert b"unit quaternion" in L.yoro_last_error()
+    assert L.yoro_reproject_pose(fake, fake2, 8, 8, 900.0, float("nan"), 4.0, q, t, 1, fake3, None, None, wsp, 512,
+                                 None) == yoro.ERR_INVALID_ARG
+    assert L.yoro_reproject_pose(fake, fake2, 8, 8, 900.0, 4.0, 4.0, q, t, 3, fake3, None, None, wsp, 512,
+                                 None) == yoro.ERR_INVALID_ARG                          # the Patcher needs depth + mask
