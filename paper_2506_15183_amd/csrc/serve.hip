@@ -3,11 +3,18 @@
 // events, and the optional hole-tile learned refinement with its fallback.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <chrono>
+#include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdint>
 #include <deque>
+#include <functional>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
 #include <vector>
 
 #include "yoro.h"
@@ -83,6 +90,62 @@ struct Batch {
 constexpr int kRecount = 8;
 
 }  // namespace
+
+// Enqueues refinements from a thread of its own: a tile fill is hundreds of
+// kernel launches (about a millisecond of host time), during which the
+// serving thread keeps taking arrivals and completions.  One job at a time;
+// `issued` turns 1 once the job's completion event is recorded (-1 if the
+// enqueueing failed, with the message in `err`), and only then may the
+// serving thread query or wait on that event.
+class Refiner {
+ public:
+  explicit Refiner(int device) : th_([this, device] { loop(device); }) {}
+  ~Refiner() {
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      stop_ = true;
+    }
+    cv_.notify_one();
+    th_.join();  // a job being enqueued is finished first
+  }
+  void submit(std::function<int32_t(std::string*)> job) {
+    issued.store(0, std::memory_order_release);
+    {
+      std::lock_guard<std::mutex> lk(mu_);
+      job_ = std::move(job);
+    }
+    cv_.notify_one();
+  }
+  std::atomic<int> issued{1};
+  std::string err;  // valid once issued == -1
+
+ private:
+  void loop(int device) {
+    const hipError_t e = hipSetDevice(device);
+    for (;;) {
+      std::function<int32_t(std::string*)> job;
+      {
+        std::unique_lock<std::mutex> lk(mu_);
+        cv_.wait(lk, [this] { return stop_ || job_; });
+        if (!job_) return;  // stop, nothing queued
+        job.swap(job_);
+      }
+      int32_t st = YORO_OK;
+      if (e != hipSuccess) {
+        err = std::string("refinement thread: ") + hipGetErrorString(e);
+        st = YORO_ERR_DEVICE;
+      } else {
+        st = job(&err);
+      }
+      issued.store(st == YORO_OK ? 1 : -1, std::memory_order_release);
+    }
+  }
+  std::mutex mu_;
+  std::condition_variable cv_;
+  bool stop_ = false;
+  std::function<int32_t(std::string*)> job_;
+  std::thread th_;
+};
 
 extern "C" {
 
@@ -197,6 +260,10 @@ int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, c
   int64_t batch_no = 0;
   std::vector<yoro_job> jobs;
   jobs.reserve(O.max_batch);
+  int device = 0;
+  (void)hipGetDevice(&device);
+  std::unique_ptr<Refiner> refiner;
+  if (L_on) refiner.reset(new Refiner(device));
   bool l_active = false;
   int64_t l_frame = -1;
   int64_t l_started = -1;  // start of the last refinement (ns), -1: none yet
@@ -231,23 +298,27 @@ int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, c
       ++kc;
     }
     const int o = out_of[k];
-    hipError_t e = hipMemcpyAsync(plan_dev, plan_host, (size_t)kc * 16, hipMemcpyHostToDevice, ls);
-    if (e != hipSuccess) {
-      status = serve_fail(YORO_ERR_DEVICE, "%s: plan upload: %s", who, hipGetErrorString(e));
-      return -1;
-    }
-    const int32_t st = yoro_model_fill_tiles(O.model_weights, H.dst_rgba[o], H.dst_depth[o], H.dst_mask[o], H.width,
-                                             H.height, plan_dev, kc, O.tile, O.halo, O.chunk, H.dst_rgba[o],
-                                             O.learned_workspace, O.learned_workspace_bytes, ls);
-    if (st != YORO_OK) {
-      status = st;
-      return -1;
-    }
-    e = hipEventRecord(lev, ls);
-    if (e != hipSuccess) {
-      status = serve_fail(YORO_ERR_DEVICE, "%s: event record: %s", who, hipGetErrorString(e));
-      return -1;
-    }
+    // The plan buffer is not touched again before this refinement completes.
+    refiner->submit([&O, &H, o, kc, plan_dev, plan_host, ls, lev](std::string* err) -> int32_t {
+      hipError_t e = hipMemcpyAsync(plan_dev, plan_host, (size_t)kc * 16, hipMemcpyHostToDevice, ls);
+      if (e != hipSuccess) {
+        *err = std::string("plan upload: ") + hipGetErrorString(e);
+        return YORO_ERR_DEVICE;
+      }
+      const int32_t st = yoro_model_fill_tiles(O.model_weights, H.dst_rgba[o], H.dst_depth[o], H.dst_mask[o], H.width,
+                                               H.height, plan_dev, kc, O.tile, O.halo, O.chunk, H.dst_rgba[o],
+                                               O.learned_workspace, O.learned_workspace_bytes, ls);
+      if (st != YORO_OK) {
+        *err = std::string("tile fill: ") + yoro_last_error();
+        return st;
+      }
+      e = hipEventRecord(lev, ls);
+      if (e != hipSuccess) {
+        *err = std::string("event record: ") + hipGetErrorString(e);
+        return YORO_ERR_DEVICE;
+      }
+      return YORO_OK;
+    });
     l_active = true, l_frame = k, l_headset = arrivals[k].headset, l_out = o;
     l_started = t_start;
     return YORO_PATH_LEARNED;
@@ -356,12 +427,17 @@ int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, c
     }
     // The refinement in flight.
     if (l_active && status == YORO_OK) {
-      const hipError_t q = hipEventQuery(lev);
-      if (q == hipSuccess) {
-        results[l_frame].done_ns = now_ns();
-        l_active = false;
-      } else if (q != hipErrorNotReady) {
-        status = serve_fail(YORO_ERR_DEVICE, "%s: refinement: %s", who, hipGetErrorString(q));
+      const int is = refiner->issued.load(std::memory_order_acquire);
+      if (is < 0) {
+        status = serve_fail(YORO_ERR_DEVICE, "%s: refinement: %s", who, refiner->err.c_str());
+      } else if (is > 0) {
+        const hipError_t q = hipEventQuery(lev);
+        if (q == hipSuccess) {
+          results[l_frame].done_ns = now_ns();
+          l_active = false;
+        } else if (q != hipErrorNotReady) {
+          status = serve_fail(YORO_ERR_DEVICE, "%s: refinement: %s", who, hipGetErrorString(q));
+        }
       }
     }
     // Launch what has arrived.
@@ -407,6 +483,12 @@ int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, c
         later.pop_back();
       }
       ++batch_no;
+      // The event must be recorded before a wait on it means anything.
+      while (wait_learned && refiner->issued.load(std::memory_order_acquire) == 0) std::this_thread::yield();
+      if (wait_learned && refiner->issued.load(std::memory_order_acquire) < 0) {
+        status = serve_fail(YORO_ERR_DEVICE, "%s: refinement: %s", who, refiner->err.c_str());
+        break;
+      }
       hipError_t e = wait_learned ? hipStreamWaitEvent(s, lev, 0) : hipSuccess;
       if (e != hipSuccess) {
         status = serve_fail(YORO_ERR_DEVICE, "%s: wait: %s", who, hipGetErrorString(e));
@@ -428,7 +510,9 @@ int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, c
     }
     if (next == n_arrivals && pending.empty() && inflight.empty() && !l_active) break;
   }
-  // Drain whatever is queued (after an error too) before the events go away.
+  // Drain whatever is queued (after an error too) before the events go away;
+  // the refinement thread first finishes enqueueing its job, if any.
+  refiner.reset();
   (void)hipStreamSynchronize(s);
   if (L_on) (void)hipStreamSynchronize(ls);
   if (cs) {

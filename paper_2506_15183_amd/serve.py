@@ -246,6 +246,20 @@ class Server:
         return res
 
 
+def run_interleaved(server, trace, policies, rounds: int = 2):
+    """Runs the trace once per policy per round, the policies alternating
+    (plain, learned, plain, learned, ...), and pools each policy's arrivals
+    and results: slow drifts of the host then affect every policy alike.
+    Returns {policy: (trace, results)} to pass to summarize with
+    seconds * rounds."""
+    runs = {p: ([], []) for p in policies}
+    for _ in range(rounds):
+        for p in policies:
+            runs[p][0].append(trace)
+            runs[p][1].append(server.run(trace, p))
+    return {p: (np.concatenate(t), np.concatenate(r)) for p, (t, r) in runs.items()}
+
+
 def summarize(trace, res, headsets, seconds: float):
     """Latency percentiles (ms, completion - arrival, over processed frames),
     throughput and frame counts by path."""
