@@ -287,3 +287,18 @@ def test_invalid_arguments_raise(cuda):
     with pytest.raises(yoro.YoroError):  # output aliases the input
         yoro.reproject(rgba, depth, 0.06, 200.0, out=(rgba, None, None))
     del out
+
+
+def test_rows_mostly_holes(cuda):
+    """Rows where most targets stay empty (more holes than the kernel's hole
+    list holds): the overflow is filled by the lanes that own it."""
+    for W in (64, 257, 1000, 2160, 4097):
+        rgba, depth = synth.random_frame(700 + W, W, 6, depth_levels=4, zmin=0.3, zmax=3.0)
+        rng = np.random.default_rng(W)
+        for y, frac in enumerate((0.55, 0.7, 0.85, 0.95, 0.999, 1.0)):
+            depth[y, rng.random(W) < frac] = np.nan
+        for eye in (R, L):
+            for fill in (orc.FILL_NONE, orc.FILL_NEAREST_BG):
+                g = run_gpu(rgba, depth, 0.063, 900.0, eye, fill)
+                o = orc.reproject(rgba, depth, 0.063, 900.0, eye, fill)
+                assert_same(g, o, f"W={W} eye={eye} fill={fill}")
