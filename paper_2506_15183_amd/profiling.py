@@ -132,7 +132,7 @@ def summarize_learned(trace_dir: str) -> str:
     fwd_at = [i for i in starts if i + 1 < len(rows)]
     # The whole-frame forwards come first, the training steps after them.
     lines = ["# Learned fill kernels: one 1832x1920 forward pass and one training step", "",
-             "Commands (from the repository root, on one MI355X; OUT=gpurun_out/prof_learned):", "", "```",
+             "Commands (from the repository root, on one MI355X; OUT=the output directory):", "", "```",
              "rocprofv3 --kernel-trace --stats -d $OUT -o l -- python -m paper_2506_15183_amd.profiling learned",
              "python -m paper_2506_15183_amd.profiling summarize-learned $OUT", "```", "",
              "## Forward pass (last whole-frame fill), in order", "",
@@ -230,7 +230,7 @@ def summarize(out_dir: str, pixels: int, algo_bytes_per_px: int = 12) -> str:
     lines = [
         "# warp_batch_kernel on the 64-frame mixed-resolution batch",
         "",
-        "Commands (from the repository root, on one MI355X; OUT=gpurun_out/prof):",
+        "Commands (from the repository root, on one MI355X; OUT=the output directory):",
         "",
         "```",
         "rocprofv3 --kernel-trace --stats -d $OUT/trace -o t -- python bench.py --no-cpu-baseline --no-single-frame --serve-seconds 0 --eval-frames 0",
@@ -303,7 +303,7 @@ def summarize_lowres(out_dir: str, pixels: int, max_width: int = 2160) -> str:
     lines = [
         "# lowres_batch_kernel (downsampled intermediate buffer) on the 64-frame mixed-resolution batch",
         "",
-        "Commands (from the repository root, on one MI355X; OUT=gpurun_out/prof):",
+        "Commands (from the repository root, on one MI355X; OUT=the output directory):",
         "",
         "```",
         "rocprofv3 --kernel-trace --stats -d $OUT/trace -o t -- python bench.py --no-cpu-baseline --no-single-frame --serve-seconds 0 --eval-frames 0",
