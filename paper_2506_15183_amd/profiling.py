@@ -335,6 +335,38 @@ def summarize_lowres(out_dir: str, pixels: int, max_width: int = 2160) -> str:
     return "\n".join(lines)
 
 
+def summarize_pose(out_dir: str) -> str:
+    """The general-pose kernels (clear, scatter, resolve) from a kernel trace
+    of the bench's single-frame pose timing."""
+    trace = _trace_stats(os.path.join(out_dir, "trace"))
+    rows = [r for r in trace if "pose_" in r[0]]
+    lines = [
+        "# pose kernels (reprojection to a general pose) on one 1832x1920 frame",
+        "",
+        "Commands (from the repository root, on one MI355X; OUT=the output directory):",
+        "",
+        "```",
+        "rocprofv3 --kernel-trace --stats -d $OUT/trace -o p -- python bench.py --no-cpu-baseline --serve-seconds 0 "
+        "--eval-frames 0 --no-lowres --steps 5 --warmup 1",
+        "python -m paper_2506_15183_amd.profiling summarize-pose $OUT",
+        "```",
+        "",
+        "Head motion of 3 degrees about a tilted axis and 5.5 cm, RGBA output, one call = the three kernels.",
+        "",
+        "| kernel | calls | median us | mean us | min us |",
+        "|---|---|---|---|---|",
+    ]
+    total = 0.0
+    for name, calls, med, mean, mn in rows:
+        short = name if len(name) < 90 else name[:87] + "..."
+        lines.append(f"| `{short}` | {calls} | {med / 1e3:.1f} | {mean / 1e3:.1f} | {mn / 1e3:.1f} |")
+        total += med
+    lines += ["", f"sum of medians per call: {total / 1e3:.1f} us", "",
+              f"kernel_source_sha: {_sha((os.path.join(HERE, 'csrc', 'pose.hip'), os.path.join(HERE, 'csrc', 'row_common.h')))}",
+              ""]
+    return "\n".join(lines)
+
+
 def read_summary(path: str):
     """(traffic bytes per launch, kernel source sha) from a committed summary, or (None, None)."""
     if not os.path.exists(path):
@@ -352,6 +384,8 @@ if __name__ == "__main__":
         learned_workload()
     elif len(sys.argv) >= 3 and sys.argv[1] == "summarize-learned":
         print(summarize_learned(sys.argv[2]))
+    elif len(sys.argv) >= 3 and sys.argv[1] == "summarize-pose":
+        print(summarize_pose(sys.argv[2]))
     elif len(sys.argv) >= 3 and sys.argv[1] == "summarize-lowres":
         sys.path.insert(0, os.path.dirname(HERE))
         from paper_2506_15183_amd.scenes import config3_frames
