@@ -316,6 +316,12 @@ def main():
             "plain": serve.summarize(*runs[serve.PLAIN], hs, sparse_s),
             "learned_policy": serve.summarize(*runs[serve.LEARNED], hs, sparse_s),
         }
+        # The same learned policy in progressive mode: every frame released
+        # with the plain fill at its warp, refined frames upgraded in place.
+        srv.cfg.progressive = True
+        prog = serve.run_interleaved(srv, trace, (serve.LEARNED,), rounds=2)
+        srv.cfg.progressive = False
+        serving["sparse_scenes"]["learned_progressive"] = serve.summarize(*prog[serve.LEARNED], hs, sparse_s)
         log(f"serving, sparse scenes ({time.time() - t1:.1f}s): {serving['sparse_scenes']}")
         del srv
 

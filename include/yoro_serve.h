@@ -90,6 +90,10 @@ typedef struct yoro_serve_options {
   int32_t tile, halo, chunk;         /* hole-tile inference (yoro_model.h) */
   void* learned_stream;              /* hipStream_t for the refinement */
   int64_t learned_min_interval_ns;   /* refinements start at least this far apart */
+  int32_t progressive;               /* learned policy: 0 holds a frame to be refined until the
+                                        refinement is done; 1 releases every frame at its warp (plain
+                                        fill, done_ns) and refines it afterwards in place, a hole tile
+                                        at a time (refined_ns) */
 } yoro_serve_options;
 
 typedef struct yoro_serve_result {   /* one per arrival */
@@ -98,6 +102,7 @@ typedef struct yoro_serve_result {   /* one per arrival */
   int32_t path;                      /* yoro_serve_path */
   int32_t batch_frames;              /* frames in its plain batch */
   int64_t holes;                     /* hole pixels (learned policy), else -1 */
+  int64_t refined_ns;                /* progressive: its refinement done (host observed), else -1 */
 } yoro_serve_result;
 
 /* Sizes for the largest headset frame max_w x max_h. */

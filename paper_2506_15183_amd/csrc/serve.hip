@@ -70,7 +70,8 @@ bool options_ok(const yoro_serve_options* o) {
   if (o->policy != YORO_SERVE_PLAIN && o->policy != YORO_SERVE_LEARNED) return false;
   if (learned(o) && (o->tile <= 0 || o->tile % 8 || o->halo < 0 || o->halo % 8 || o->chunk < 1 ||
                      !o->model_weights || !o->learned_workspace || !o->learned_stream ||
-                     !(o->learned_max_hole_fraction >= 0.0f) || o->learned_min_interval_ns < 0))
+                     !(o->learned_max_hole_fraction >= 0.0f) || o->learned_min_interval_ns < 0 ||
+                     (o->progressive != 0 && o->progressive != 1)))
     return false;
   return true;
 }
@@ -329,7 +330,7 @@ int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, c
     const int64_t t = now_ns();
     while (next < n_arrivals && arrivals[next].t_ns <= t) {
       yoro_serve_result& R = results[next];
-      R.launch_ns = -1, R.done_ns = -1, R.batch_frames = 0, R.holes = -1;
+      R.launch_ns = -1, R.done_ns = -1, R.batch_frames = 0, R.holes = -1, R.refined_ns = -1;
       if (!headsets[arrivals[next].headset].admitted) {
         R.path = YORO_PATH_REJECTED;
       } else {
@@ -364,7 +365,10 @@ int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, c
           results[k].path = YORO_PATH_BUSY, results[k].done_ns = tn;
           if (++since_count[h] >= kRecount) B.counted[i] = 1, since_count[h] = 0;
         } else {
-          B.counted[i] = 1, since_count[h] = 0;
+          // A candidate for refinement (2): held until then, or, progressive,
+          // released now with the plain fill and refined in place later.
+          B.counted[i] = 2, since_count[h] = 0;
+          if (O.progressive) results[k].path = YORO_PATH_BUSY, results[k].done_ns = tn;
         }
       }
       B.warped = true;
@@ -409,7 +413,7 @@ int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, c
           const int64_t k = B.frames[i];
           const yoro_serve_headset& H = headsets[arrivals[k].headset];
           if (!B.counted[i]) continue;
-          if (results[k].done_ns >= 0) {  // released at the warp: keep the statistics only
+          if (B.counted[i] != 2) {  // a recount of a released frame: keep the statistics only
             int64_t holes = 0;
             for (int t = 0, nt = tiles_of(H.width, H.height, O.tile); t < nt; ++t) holes += counts[i * Lay.tiles + t];
             results[k].holes = holes;
@@ -417,7 +421,12 @@ int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, c
             const int32_t p = refine(k, counts + i * Lay.tiles);
             if (p < 0) break;
             results[k].path = p;
-            if (!(p == YORO_PATH_LEARNED && l_active && l_frame == k)) results[k].done_ns = tn;
+            const bool pending_refine = p == YORO_PATH_LEARNED && l_active && l_frame == k;
+            if (!O.progressive) {
+              if (!pending_refine) results[k].done_ns = tn;
+            } else if (p == YORO_PATH_LEARNED && !pending_refine) {
+              results[k].refined_ns = tn;  // no holes: nothing to refine
+            }
           }
           last_frac[arrivals[k].headset] = (double)results[k].holes / ((double)H.width * H.height);
         }
@@ -433,7 +442,10 @@ int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, c
       } else if (is > 0) {
         const hipError_t q = hipEventQuery(lev);
         if (q == hipSuccess) {
-          results[l_frame].done_ns = now_ns();
+          if (O.progressive)
+            results[l_frame].refined_ns = now_ns();
+          else
+            results[l_frame].done_ns = now_ns();
           l_active = false;
         } else if (q != hipErrorNotReady) {
           status = serve_fail(YORO_ERR_DEVICE, "%s: refinement: %s", who, hipGetErrorString(q));

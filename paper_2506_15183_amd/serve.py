@@ -64,16 +64,17 @@ class Options(ctypes.Structure):
         ("tile", ctypes.c_int32), ("halo", ctypes.c_int32), ("chunk", ctypes.c_int32),
         ("learned_stream", ctypes.c_void_p),
         ("learned_min_interval_ns", ctypes.c_int64),
+        ("progressive", ctypes.c_int32),
     ]
 
 
 class Result(ctypes.Structure):
     _fields_ = [("launch_ns", ctypes.c_int64), ("done_ns", ctypes.c_int64), ("path", ctypes.c_int32),
-                ("batch_frames", ctypes.c_int32), ("holes", ctypes.c_int64)]
+                ("batch_frames", ctypes.c_int32), ("holes", ctypes.c_int64), ("refined_ns", ctypes.c_int64)]
 
 
 RESULT_DTYPE = np.dtype([("launch_ns", "<i8"), ("done_ns", "<i8"), ("path", "<i4"), ("batch_frames", "<i4"),
-                         ("holes", "<i8")])
+                         ("holes", "<i8"), ("refined_ns", "<i8")])
 ARRIVAL_DTYPE = np.dtype([("t_ns", "<i8"), ("headset", "<i4"), ("source", "<i4")])
 assert RESULT_DTYPE.itemsize == ctypes.sizeof(Result) and ARRIVAL_DTYPE.itemsize == ctypes.sizeof(Arrival)
 
@@ -147,6 +148,9 @@ class Config:
     chunk: int = 8
     learned_max_hole_fraction: float = 0.05
     learned_min_interval_ms: float = 0.0
+    # Learned policy: release every frame at its warp and refine it in place
+    # afterwards (latency = first delivery; refined_ns marks the upgrade).
+    progressive: bool = False
 
 
 class Server:
@@ -222,6 +226,7 @@ class Server:
         o.max_batch, o.max_in_flight, o.policy = c.max_batch, c.max_in_flight, policy
         o.learned_max_hole_fraction = c.learned_max_hole_fraction
         o.learned_min_interval_ns = int(c.learned_min_interval_ms * 1e6)
+        o.progressive = int(bool(c.progressive))
         o.tile, o.halo, o.chunk = c.tile, c.halo, c.chunk
         if policy == LEARNED:
             o.model_weights = self.model.wf.data_ptr()
@@ -279,9 +284,15 @@ def summarize(trace, res, headsets, seconds: float):
     }
     refined = res["path"][done] == PATH_LEARNED
     if refined.any():
+        out["refined_fraction"] = round(float(refined.mean()), 5)
         out["learned_frames_p50_ms"] = round(float(np.percentile(lat[refined], 50)), 4)
         out["learned_frames_max_ms"] = round(float(lat[refined].max()), 4)
         out["p99_plain_path_frames_ms"] = round(float(np.percentile(lat[~refined], 99)), 4)
+        up = res["refined_ns"][done][refined]
+        if (up >= 0).any():  # progressive: time from arrival to the refined upgrade
+            t_up = (up[up >= 0] - trace["t_ns"][done][refined][up >= 0]) / 1e6
+            out["refined_upgrade_p50_ms"] = round(float(np.percentile(t_up, 50)), 4)
+            out["refined_upgrade_max_ms"] = round(float(t_up.max()), 4)
     holes = res["holes"][done]
     if (holes >= 0).any():
         frac = holes[holes >= 0] / px[holes >= 0]
@@ -315,6 +326,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--sparse", action="store_true", help="scenes with few holes (U{20..60} objects, depth >= 2 m)")
     ap.add_argument("--learned-interval-ms", type=float, default=0.0)
+    ap.add_argument("--progressive", action="store_true",
+                    help="learned policy: release frames at the warp, refine them in place afterwards")
     a = ap.parse_args()
     log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
     hs = config5_headsets(a.headsets, a.seed)
@@ -323,7 +336,8 @@ def main():
         from . import train, unet
 
         model = unet.UNet("cuda", params=train.load_weights(a.weights or train.DEFAULT_WEIGHTS))
-    cfg = Config(budget_bytes=int(a.budget_gb * 1e9), learned_min_interval_ms=a.learned_interval_ms)
+    cfg = Config(budget_bytes=int(a.budget_gb * 1e9), learned_min_interval_ms=a.learned_interval_ms,
+                 progressive=a.progressive)
     srv = Server(hs, cfg, pool_renderer(sparse=a.sparse), model=model, log=log)
     trace = make_trace(hs, a.seconds, cfg.n_sources, seed=a.seed)
     log(f"{len(trace)} arrivals over {a.seconds} s")

@@ -163,3 +163,33 @@ def test_refinement_interval_budget(cuda):
     assert (res["path"] == serve.PATH_LEARNED).sum() == 1
     assert ((res["path"] == serve.PATH_LEARNED) | (res["path"] == serve.PATH_BUSY)).all()
     assert (res["done_ns"] >= res["launch_ns"]).all()
+
+
+def test_progressive_refinement_releases_at_the_warp(cuda):
+    """Progressive mode: every frame is released with the plain fill when its
+    warp completes (done_ns); a refined frame is upgraded in place later
+    (refined_ns), and the output it leaves equals the stand-alone tiled
+    learned fill."""
+    torch, serve, unet, yoro, HeadsetSpec, FrameSpec = _mods()
+    hs = _headsets(HeadsetSpec, 4, rates=(60.0, 50.0, 40.0))
+    net = _strong_net(unet, 8)
+    cfg = serve.Config(budget_bytes=10**10, n_sources=2, n_outputs=2, max_batch=4, max_in_flight=2, chunk=4,
+                       learned_max_hole_fraction=1.0, progressive=True)
+    srv = serve.Server(hs, cfg, _frames(FrameSpec), model=net)
+    trace = serve.make_trace(hs, 0.4, cfg.n_sources, seed=3)
+    res = srv.run(trace, serve.LEARNED)
+    paths = res["path"]
+    refined = paths == serve.PATH_LEARNED
+    assert np.isin(paths, [serve.PATH_LEARNED, serve.PATH_BUSY]).all() and refined.sum() >= 1
+    assert (res["done_ns"] >= res["launch_ns"]).all()
+    assert (res["refined_ns"][refined] > res["done_ns"][refined]).all()
+    assert (res["refined_ns"][~refined] == -1).all()
+    checked = 0
+    for (hi, o), k in _last_per_output(trace, res, cfg.n_outputs, len(hs)).items():
+        rgba, depth, mask = _plain_alone(yoro, srv, hs[hi], int(trace["source"][k]))
+        want = net.fill_tiles(rgba, depth, mask, chunk=cfg.chunk)[0] if refined[k] else rgba
+        checked += int(refined[k])
+        assert torch.equal(srv.outs[hi][o][0], want), (hi, o, k, int(paths[k]))
+    assert checked >= 1
+    s = serve.summarize(trace, res, hs, 0.4)
+    assert s["refined_upgrade_p50_ms"] > 0 and s["refined_fraction"] > 0

@@ -71,6 +71,10 @@ def test_workspace_sizes_and_option_checks():
     learned = L.yoro_serve_workspace_bytes(ctypes.byref(o), 2160, 2160)
     assert learned > plain  # tile counts per slot and the crop plan
     assert L.yoro_serve_host_bytes(ctypes.byref(o), 2160, 2160) >= 4 * 16 * 17 * 17 * 4
+    o.progressive = 2  # only 0 or 1
+    assert L.yoro_serve_workspace_bytes(ctypes.byref(o), 2160, 2160) == 0
+    o.progressive = 1
+    assert L.yoro_serve_workspace_bytes(ctypes.byref(o), 2160, 2160) == learned
     o.max_batch = 0
     assert L.yoro_serve_workspace_bytes(ctypes.byref(o), 2160, 2160) == 0
 
