@@ -63,7 +63,10 @@ __global__ __launch_bounds__(kConvThreads) void conv3x3_tiled_kernel(const uint1
   // The chunk's weights for all nine taps: [tap][output channel][32 + 8 pad].
   __shared__ __align__(16) uint16_t wlds[9 * CT * kPatchStride];
   const int tiles_x = (W + kTileW - 1) / kTileW, tiles_y = (H + kTileH - 1) / kTileH;
-  int b = blockIdx.x;
+  // XCD-aware order: workgroup w runs on XCD w % 8; each XCD takes one
+  // contiguous range of tiles, so tiles sharing halo rows share an L2.
+  const int nt = (int)gridDim.x, q8 = nt >> 3, r8 = nt & 7, xc = (int)blockIdx.x & 7;
+  int b = xc * q8 + min(xc, r8) + ((int)blockIdx.x >> 3);
   const int tx = b % tiles_x;
   b /= tiles_x;
   const int ty = b % tiles_y;
