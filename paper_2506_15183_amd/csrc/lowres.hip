@@ -96,7 +96,6 @@ __device__ __forceinline__ void block_map(const DevJob& J, int lg, bool linear, 
   const bool target_right = J.target_eye == 0;
   const int ms = target_right ? 0 : -1;  // xs = x +- r, as x + ((r ^ ms) - ms)
 
-  if (threadIdx.x == 0) *s.nholes = 0u;
   for_cols<PPT>(W, [&](int, int x) {
     const int t = x - c;
     const int i0 = t >> lg;  // floor((x - c) / k): arithmetic shift

@@ -85,7 +85,6 @@ __global__ __launch_bounds__(kThreads) void pose_resolve_kernel(const uint64_t* 
     YORO_GLOBAL uint32_t* orow = gmem(dst_rgba) + row;
     YORO_GLOBAL float* zrow = dst_depth ? gmem(dst_depth) + row : nullptr;
     YORO_GLOBAL uint8_t* mrow = dst_mask ? gmem(dst_mask) + row : nullptr;
-    if (threadIdx.x == 0) *s.nholes = 0u;
     uint64_t k[PPT];
     uint32_t col[PPT];
 #pragma unroll

@@ -26,13 +26,17 @@ struct RowLds {
                      //           last 64 are per-lane sinks for lanes with
                      //           nothing to splat
   uint64_t* mask;    // [wl/64]   hit masks, one per 64 columns
-  uint32_t* nholes;  // [4]
-  uint16_t* holes;   // [wl]      columns of the row's holes (unordered)
+  uint32_t* pad;     // [4]
+  uint16_t* holes;   // [4 seg]   columns of the row's holes, one segment per
+                     //           wave (a wave owns one 64-column block per
+                     //           kThreads columns, so seg = 64 per chunk)
+  int seg;
   __device__ RowLds(unsigned char* base, int wl) {
     key = reinterpret_cast<uint64_t*>(base);
     mask = key + wl + 64;
-    nholes = reinterpret_cast<uint32_t*>(mask + (wl >> 6));
-    holes = reinterpret_cast<uint16_t*>(nholes + 4);
+    pad = reinterpret_cast<uint32_t*>(mask + (wl >> 6));
+    holes = reinterpret_cast<uint16_t*>(pad + 4);
+    seg = ((wl + kThreads - 1) / kThreads) * 64;
   }
 };
 
@@ -92,12 +96,12 @@ __device__ __forceinline__ int round_half_away(float q) {
 // for a target nobody reached) are in s.key[0, W):
 //   C  every column is stored (a hole provisionally as RGBA 0, depth +inf,
 //      mask 1); per wave64 a ballot of "target reached" gives one 64-bit hit
-//      mask per 64 columns, and the holes are appended to a compact per-row
-//      list (one LDS atomic per wave);
-//   E  each listed hole walks the hit masks from its own word to its
-//      nearest hit on either side and takes the farther one (Section 5 O2;
-//      Section 7 Patcher figure: on equal depth, the side opposite the
-//      shift), overwriting its provisional value.
+//      mask per 64 columns, and each wave appends its holes to its own
+//      segment of the hole list as it goes;
+//   E  each wave's listed holes walk the hit masks (all waves') from their
+//      own word to their nearest hit on either side and take the farther
+//      one (Section 5 O2; Section 7 Patcher figure: on equal depth, the side
+//      opposite the shift), overwriting their provisional values.
 // Every column's result goes to emit(x, low word, depth bits, mask): a hit
 // (mask 0) and a filled hole (mask 1) carry their key's low word and depth,
 // an unfilled hole gives 0, +inf and 1 (2 when its row has no hit at all).
@@ -109,13 +113,15 @@ __device__ __forceinline__ void resolve_fill_row(const RowLds& s, int W, bool ta
                                                  Emit&& emit) {
   const int tid = threadIdx.x;
   const int lane = tid & 63;
+  const int wave = tid >> 6;
   const int nw = (W + 63) >> 6;
   const int nfull = W / kThreads;
+  uint16_t* holes = s.holes + wave * s.seg;  // this wave's segment
 
   // C: store every column (holes get RGBA 0 / +inf / mask 1 for now), build
-  // the hit masks, count holes.  A hit's high word holds the bits of a depth
-  // in (0, +inf], never the all-ones of EMPTY.
-  uint32_t cnt = 0;
+  // the hit masks, list the holes.  A hit's high word holds the bits of a
+  // depth in (0, +inf], never the all-ones of EMPTY.
+  uint32_t run = 0;    // holes listed by this wave so far (wave-uniform)
   uint64_t mword = 0;  // lane i: hit mask of chunk i's 64 columns of this wave
 #pragma unroll
   for (int i = 0; i < PPT; ++i) {
@@ -132,8 +138,16 @@ __device__ __forceinline__ void resolve_fill_row(const RowLds& s, int W, bool ta
         emit(x, c, zo, hit ? 0 : 1);
       }
       const uint64_t hm = __ballot(hit);
-      const uint64_t valid = (i < nfull) ? ~0ull : __ballot(inrow);
-      cnt += (uint32_t)__popcll(valid & ~hm);
+      if (fill) {
+        const uint64_t valid = (i < nfull) ? ~0ull : __ballot(inrow);
+        const uint64_t om = valid & ~hm;
+        if ((om >> lane) & 1ull) {
+          const uint32_t below =
+              __builtin_amdgcn_mbcnt_hi((uint32_t)(om >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)om, 0u));
+          holes[run + below] = (uint16_t)x;
+        }
+        run += (uint32_t)__popcll(om);
+      }
       // Park this chunk's mask in lane i (lo/hi halves) for one store below.
       mword = (lane == i) ? hm : mword;
     }
@@ -141,39 +155,16 @@ __device__ __forceinline__ void resolve_fill_row(const RowLds& s, int W, bool ta
   if (fill) {
     // One LDS store per lane that parked a mask: word (i*4 + wave) holds
     // chunk i's columns of this wave.
-    const int wave = tid >> 6;
     const int nchunks = (W + kThreads - 1) / kThreads;
     const int word = lane * (kThreads / 64) + wave;
     if (lane < nchunks && word < nw) s.mask[word] = mword;
-    if (cnt) {
-      uint32_t base = 0;
-      if (lane == 0) base = atomicAdd(s.nholes, cnt);
-      base = __builtin_amdgcn_readfirstlane(base);
-#pragma unroll
-      for (int i = 0; i < PPT; ++i) {
-        if (i <= nfull && i * kThreads < W) {
-          const int x = tid + i * kThreads;
-          // readlane returns a signed int: widen through uint32_t, never sign-extend.
-          const uint64_t hm = (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mword, i) |
-                              ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(mword >> 32), i) << 32);
-          const uint64_t valid = (i < nfull) ? ~0ull : __ballot(x < W);
-          const uint64_t om = valid & ~hm;
-          if ((om >> lane) & 1ull) {
-            const uint32_t below =
-                __builtin_amdgcn_mbcnt_hi((uint32_t)(om >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)om, 0u));
-            s.holes[base + below] = (uint16_t)x;
-          }
-          base += (uint32_t)__popcll(om);
-        }
-      }
-    }
     __syncthreads();
-    // E: fill the listed holes.  Only hits are read, only holes written.
-    const int nh = (int)*s.nholes;
-    for (int h0 = tid - lane; h0 < nh; h0 += kThreads) {  // whole waves: the scan reads need every lane
-      const int h = h0 + lane;
-      int x = h < nh ? (int)s.holes[h] : 0;
-      const bool act = (h < nh) & (x < W);  // every listed column is < W; guard the store anyway
+    // E: this wave fills the holes it listed.  Only hits are read, only
+    // holes written.
+    for (uint32_t h0 = 0; h0 < run; h0 += 64) {
+      const uint32_t h = h0 + lane;
+      int x = h < run ? (int)holes[h] : 0;
+      const bool act = (h < run) & (x < W);  // every listed column is < W; guard the store anyway
       x = act ? x : 0;
       int L, R;
       nearest_hits_walk(s.mask, nw, W, x, L, R);

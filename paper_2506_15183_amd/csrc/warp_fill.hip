@@ -70,7 +70,7 @@ __device__ __forceinline__ void warp_fill_row(const DevJob& J, int y, const RowI
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const float bf = J.baseline_m * J.focal_px;
-  const float Wf = (float)W;
+  const uint32_t Wbits = __float_as_uint((float)W);
   const bool target_right = J.target_eye == 0;
   // x_t = x - d (target right) or x + d (target left), as x + ((d ^ m) - m).
   const int m = target_right ? -1 : 0;
@@ -81,9 +81,9 @@ __device__ __forceinline__ void warp_fill_row(const DevJob& J, int y, const RowI
   YORO_GLOBAL float* zrow = (EXTRA && J.dst_depth) ? gmem(J.dst_depth) + row : nullptr;
   YORO_GLOBAL uint8_t* mrow = (EXTRA && J.dst_mask) ? gmem(J.dst_mask) + row : nullptr;
 
-  // A: clear keys.
-  for_cols<PPT>(W, [&](int, int x) { s.key[x] = kEmpty; });
-  if (tid == 0) *s.nholes = 0u;
+  // A: clear keys, two per 16-byte store (wl >= W is even).
+  for (int e = tid; e < (W + 1) >> 1; e += kThreads)
+    reinterpret_cast<ulonglong2*>(s.key)[e] = make_ulonglong2(kEmpty, kEmpty);
   __syncthreads();
 
   // B: scatter with the depth test.  Lanes with nothing to splat (no
@@ -97,7 +97,10 @@ __device__ __forceinline__ void warp_fill_row(const DevJob& J, int y, const RowI
       const float q = bf / z;
       const int d = round_half_away(q);
       const int xt = x + ((d ^ m) - m);
-      const bool ok = (z > 0.0f) & (q < Wf) & ((unsigned)xt < (unsigned)W) & (x < W);
+      // z > 0 and q < W together are q in [+0, W): as bf > 0, any other z
+      // (<= 0, NaN, or the 0 a column past the row's end holds) gives a
+      // negative, -0, infinite or NaN q, whose bits compare above W's.
+      const bool ok = (__float_as_uint(q) < Wbits) & ((unsigned)xt < (unsigned)W);
       atomicMin(&s.key[ok ? xt : wl + lane], ((uint64_t)__float_as_uint(z) << 32) | in.c[i]);
     }
   }

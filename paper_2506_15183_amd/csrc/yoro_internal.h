@@ -59,10 +59,12 @@ inline int ppt_for(int max_width) {
 // Width the row kernel's LDS is laid out for: max_width rounded up to 64.
 inline int lds_width(int max_width) { return (max_width + 63) & ~63; }
 // Dynamic LDS bytes of the warp kernel laid out for wl columns: 64-bit keys
-// (plus 64 sinks), hit masks, the hole counter and the u16 hole list.
+// (plus 64 sinks), hit masks, 16 bytes of padding and the u16 hole list (four
+// per-wave segments of 64 entries per kThreads columns).
 inline size_t warp_lds_bytes(int wl) {
   const size_t w = (size_t)wl;
-  return (w + 64) * 8 + (w / 64) * 8 + 16 + w * 2;
+  const size_t hl = (w + kThreads - 1) / kThreads * kThreads;
+  return (w + 64) * 8 + (w / 64) * 8 + 16 + hl * 2;
 }
 // Dynamic LDS bytes of the stand-alone fill kernel: colours, depths, masks.
 inline size_t fill_lds_bytes(int wl) {

@@ -53,8 +53,9 @@ def lowres_lds_bytes(max_width: int, k: int) -> int:
     """Dynamic LDS of the downsampled-buffer kernel (as the library sizes it):
     the row's keys, hit masks, hole counter and list, plus the texel slots."""
     wl = (max_width + 63) & ~63
+    hl = (wl + 255) // 256 * 256
     slots = (((max_width + k - 1) // k) + 63) & ~63
-    return (wl + 64) * 8 + (wl // 64) * 8 + 16 + wl * 2 + slots * 8
+    return (wl + 64) * 8 + (wl // 64) * 8 + 16 + hl * 2 + slots * 8
 
 
 def counters_workload(launches: int = 5) -> None:
