@@ -125,7 +125,7 @@ __device__ __forceinline__ void resolve_fill_row(const RowLds& s, int W, bool ta
   uint64_t mword = 0;  // lane i: hit mask of chunk i's 64 columns of this wave
 #pragma unroll
   for (int i = 0; i < PPT; ++i) {
-    if (i <= nfull && i * kThreads < W) {
+    if (i * kThreads < W) {
       const int x = tid + i * kThreads;
       const uint64_t k = s.key[min(x, W - 1)];
       const bool inrow = x < W;
@@ -139,8 +139,7 @@ __device__ __forceinline__ void resolve_fill_row(const RowLds& s, int W, bool ta
       }
       const uint64_t hm = __ballot(hit);
       if (fill) {
-        const uint64_t valid = (i < nfull) ? ~0ull : __ballot(inrow);
-        const uint64_t om = valid & ~hm;
+        const uint64_t om = __ballot(inrow) & ~hm;
         if ((om >> lane) & 1ull) {
           const uint32_t below =
               __builtin_amdgcn_mbcnt_hi((uint32_t)(om >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)om, 0u));

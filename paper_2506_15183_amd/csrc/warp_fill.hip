@@ -43,6 +43,7 @@ struct RowIn {
   uint32_t c[PPT];
 };
 
+// Columns past the row's end keep depth 0, which splats nothing.
 template <int PPT>
 __device__ __forceinline__ void load_row(const DevJob& J, int y, RowIn<PPT>& in) {
   const int W = J.width;
@@ -50,7 +51,7 @@ __device__ __forceinline__ void load_row(const DevJob& J, int y, RowIn<PPT>& in)
   YORO_GLOBAL const float* zp = gmem(J.src_depth) + row;
   YORO_GLOBAL const uint32_t* cp = gmem(J.src_rgba) + row;
 #pragma unroll
-  for (int i = 0; i < PPT; ++i) {  // columns past the row's end stay defined
+  for (int i = 0; i < PPT; ++i) {
     in.z[i] = 0.0f;
     in.c[i] = 0u;
   }
@@ -75,7 +76,6 @@ __device__ __forceinline__ void warp_fill_row(const DevJob& J, int y, const RowI
   // x_t = x - d (target right) or x + d (target left), as x + ((d ^ m) - m).
   const int m = target_right ? -1 : 0;
   const bool fill = J.fill_mode != 0;
-  const int nfull = W / kThreads;
   const size_t row = (size_t)y * (size_t)W;
   YORO_GLOBAL uint32_t* orow = gmem(J.dst_rgba) + row;
   YORO_GLOBAL float* zrow = (EXTRA && J.dst_depth) ? gmem(J.dst_depth) + row : nullptr;
@@ -91,7 +91,7 @@ __device__ __forceinline__ void warp_fill_row(const DevJob& J, int y, const RowI
   // past the row's end) hit their own sink slot instead of branching.
 #pragma unroll
   for (int i = 0; i < PPT; ++i) {
-    if (i <= nfull && i * kThreads < W) {
+    if (i * kThreads < W) {
       const int x = tid + i * kThreads;
       const float z = in.z[i];
       const float q = bf / z;
