@@ -57,24 +57,41 @@ __global__ __launch_bounds__(kConvThreads) void conv3x3_tiled_kernel(const uint1
                                                                      void* __restrict__ y, int ldy, int y_fp32,
                                                                      int cout_store, int epi,
                                                                      const uint16_t* __restrict__ msrc, int ldm,
-                                                                     int ups) {
+                                                                     int ups, int ntiles) {
   constexpr int NB = CT / 16;
   __shared__ __align__(16) uint16_t patch[kPatchH * kPatchW * kPatchStride];
   // The chunk's weights for all nine taps: [tap][output channel][32 + 8 pad].
   __shared__ __align__(16) uint16_t wlds[9 * CT * kPatchStride];
   const int tiles_x = (W + kTileW - 1) / kTileW, tiles_y = (H + kTileH - 1) / kTileH;
-  // XCD-aware order: workgroup w runs on XCD w % 8; each XCD takes one
-  // contiguous range of tiles, so tiles sharing halo rows share an L2.
-  const int nt = (int)gridDim.x, q8 = nt >> 3, r8 = nt & 7, xc = (int)blockIdx.x & 7;
-  int b = xc * q8 + min(xc, r8) + ((int)blockIdx.x >> 3);
+  const int co0 = blockIdx.y * CT;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int kg = (lane >> 4) * 8;
+  auto stage_weights = [&](int ci0) {
+    for (int e = threadIdx.x; e < 9 * CT * 4; e += kConvThreads) {
+      const int tc = e >> 2, part = e & 3;  // tc = tap * CT + output channel
+      const int t = tc / CT, co = tc - t * CT;
+      *reinterpret_cast<u32x4*>(wlds + tc * kPatchStride + part * 8) =
+          *reinterpret_cast<const u32x4*>(wgt + ((long long)t * Cout + co0 + co) * Cin + ci0 + part * 8);
+    }
+  };
+  // With one input chunk the weights stay in LDS for every tile this
+  // workgroup takes (the launch is then persistent); otherwise each chunk of
+  // each tile stages its own.
+  const bool one_chunk = Cin == 32;
+  if (one_chunk) stage_weights(0);
+  // Tiles v = blockIdx.x, + gridDim.x, ... in an XCD-aware order: workgroup
+  // w runs on XCD w % 8 (gridDim.x is a multiple of 8 or the whole tile
+  // count), and each XCD takes one contiguous range of tiles, so tiles that
+  // share halo rows share an L2.
+  const int q8 = ntiles >> 3, r8 = ntiles & 7;
+  for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
+  const int xc = v & 7;
+  int b = xc * q8 + min(xc, r8) + (v >> 3);
   const int tx = b % tiles_x;
   b /= tiles_x;
   const int ty = b % tiles_y;
   const int n = b / tiles_y;
   const int x0 = tx * kTileW, y0 = ty * kTileH;
-  const int co0 = blockIdx.y * CT;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int kg = (lane >> 4) * 8;
   const long long img = (long long)n * H * W;
   floatx4 acc[4][NB];
 #pragma unroll
@@ -83,7 +100,7 @@ __global__ __launch_bounds__(kConvThreads) void conv3x3_tiled_kernel(const uint1
     for (int nb = 0; nb < NB; ++nb) acc[m][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
 
   for (int ci0 = 0; ci0 < Cin; ci0 += 32) {
-    __syncthreads();  // the previous chunk's readers are done with the patch
+    __syncthreads();  // the previous chunk's (or tile's) readers are done with the patch
     for (int e = threadIdx.x; e < kPatchH * kPatchW * 4; e += kConvThreads) {
       const int pix = e >> 2, part = e & 3;
       const int py = pix / kPatchW, px = pix - py * kPatchW;
@@ -98,12 +115,7 @@ __global__ __launch_bounds__(kConvThreads) void conv3x3_tiled_kernel(const uint1
       }
       *reinterpret_cast<u32x4*>(patch + pix * kPatchStride + part * 8) = v;
     }
-    for (int e = threadIdx.x; e < 9 * CT * 4; e += kConvThreads) {
-      const int tc = e >> 2, part = e & 3;  // tc = tap * CT + output channel
-      const int t = tc / CT, co = tc - t * CT;
-      *reinterpret_cast<u32x4*>(wlds + tc * kPatchStride + part * 8) =
-          *reinterpret_cast<const u32x4*>(wgt + ((long long)t * Cout + co0 + co) * Cin + ci0 + part * 8);
-    }
+    if (!one_chunk) stage_weights(ci0);
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
@@ -147,6 +159,7 @@ __global__ __launch_bounds__(kConvThreads) void conv3x3_tiled_kernel(const uint1
       }
     }
   }
+  }  // tiles
 }
 
 // ---------------------------------------------------------- weight grad --
@@ -666,21 +679,54 @@ int grid_1d(long long n, int threads) {
 
 // ------------------------------------------------------------- launchers --
 namespace {
+// Compute units of the current device and resident convolution workgroups
+// per CU, queried once.
+int device_cus() {
+  static const int c = [] {
+    int d = 0, v = 0;
+    if (hipGetDevice(&d) != hipSuccess || hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, d) != hipSuccess)
+      v = 0;
+    return v > 0 ? v : 256;
+  }();
+  return c;
+}
+
+template <int CT>
+int conv_blocks_per_cu() {
+  static const int nb = [] {
+    int v = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, conv3x3_tiled_kernel<CT>, kConvThreads, 0) != hipSuccess)
+      v = 0;
+    return v > 0 ? v : 1;
+  }();
+  return nb;
+}
+
 hipError_t conv3x3_launch(const uint16_t* x, int ldx, int N, int H, int W, int Cin, const uint16_t* wgt, int Cout,
                           void* y, int ldy, int y_fp32, int cout_store, int epi, const uint16_t* msrc, int ldm, int ups,
                           hipStream_t s) {
   const long long tiles = (long long)N * ((H + kTileH - 1) / kTileH) * ((W + kTileW - 1) / kTileW);
   if (tiles > 0x7FFFFFFFLL) return hipErrorInvalidValue;
-  const unsigned gx = (unsigned)tiles;
+  const int nt = (int)tiles;
+  // One workgroup per tile, or, with one input chunk (weights staged once per
+  // workgroup), a persistent grid of the workgroups that fit, a multiple of 8.
+  auto grid_x = [&](int per_cu) -> unsigned {
+    if (Cin != 32) return (unsigned)nt;
+    const long long g = ((long long)device_cus() * per_cu) & ~7LL;
+    return (unsigned)(g >= 8 && g < nt ? g : nt);
+  };
   if (cout_store <= 16) {  // e.g. the 3-channel head: only the first 16 outputs are computed
-    hipLaunchKernelGGL(conv3x3_tiled_kernel<16>, dim3(gx, 1), dim3(kConvThreads), 0, s, x, ldx, N, H, W, Cin, wgt,
-                       Cout, y, ldy, y_fp32, cout_store, epi, msrc, ldm, ups);
+    hipLaunchKernelGGL(conv3x3_tiled_kernel<16>, dim3(grid_x(conv_blocks_per_cu<16>()), 1),
+                       dim3(kConvThreads), 0, s, x, ldx, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi,
+                       msrc, ldm, ups, nt);
   } else if (Cout % 64 == 0) {
-    hipLaunchKernelGGL(conv3x3_tiled_kernel<64>, dim3(gx, Cout / 64), dim3(kConvThreads), 0, s, x, ldx, N, H, W, Cin,
-                       wgt, Cout, y, ldy, y_fp32, cout_store, epi, msrc, ldm, ups);
+    hipLaunchKernelGGL(conv3x3_tiled_kernel<64>, dim3(grid_x(conv_blocks_per_cu<64>()), Cout / 64),
+                       dim3(kConvThreads), 0, s, x, ldx, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi,
+                       msrc, ldm, ups, nt);
   } else {
-    hipLaunchKernelGGL(conv3x3_tiled_kernel<32>, dim3(gx, Cout / 32), dim3(kConvThreads), 0, s, x, ldx, N, H, W, Cin,
-                       wgt, Cout, y, ldy, y_fp32, cout_store, epi, msrc, ldm, ups);
+    hipLaunchKernelGGL(conv3x3_tiled_kernel<32>, dim3(grid_x(conv_blocks_per_cu<32>()), Cout / 32),
+                       dim3(kConvThreads), 0, s, x, ldx, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi,
+                       msrc, ldm, ups, nt);
   }
   return hipGetLastError();
 }
