@@ -87,15 +87,18 @@ hipError_t forward(const uint16_t* wts, const uint8_t* rgba, const float* depth,
                   0, s));
   };
   ok(nn_input(reinterpret_cast<const uint32_t*>(rgba), depth, mask, (long long)n * h * w, a.x0, s));
+  // The encoders' second convolutions also write the 2x2 average pool of
+  // their output (the next level's input) in the same pass.
+  auto conv_pool = [&](int i, const uint16_t* x, int ldx, int lev, uint16_t* y, int ldy, uint16_t* pool, int ldp) {
+    const Layer L = kLayers[i];
+    ok(nn_conv3x3_pool(x, ldx, n, h >> lev, w >> lev, L.cin, wts + layer_offset(i), L.cout, y, ldy, 1, pool, ldp, s));
+  };
   conv(0, a.x0, 32, 0, a.e0a, 32);
-  conv(1, a.e0a, 32, 0, a.c0 + 32, 64);  // e0b -> the skip half of c0
-  ok(nn_avgpool2(a.c0 + 32, 64, n, h, w, 32, a.p1, 32, s));
+  conv_pool(1, a.e0a, 32, 0, a.c0 + 32, 64, a.p1, 32);  // e0b -> the skip half of c0, and its pool
   conv(2, a.p1, 32, 1, a.e1a, 64);
-  conv(3, a.e1a, 64, 1, a.c1 + 64, 128);  // e1b
-  ok(nn_avgpool2(a.c1 + 64, 128, n, h >> 1, w >> 1, 64, a.p2, 64, s));
+  conv_pool(3, a.e1a, 64, 1, a.c1 + 64, 128, a.p2, 64);  // e1b
   conv(4, a.p2, 64, 2, a.e2a, 128);
-  conv(5, a.e2a, 128, 2, a.c2 + 128, 256);  // e2b
-  ok(nn_avgpool2(a.c2 + 128, 256, n, h >> 2, w >> 2, 128, a.p3, 128, s));
+  conv_pool(5, a.e2a, 128, 2, a.c2 + 128, 256, a.p3, 128);  // e2b
   conv(6, a.p3, 128, 3, a.e3a, 256);
   conv(7, a.e3a, 256, 3, a.e3b, 256);
   // The decoders' first convolutions read the lower level's output through

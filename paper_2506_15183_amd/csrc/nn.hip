@@ -57,7 +57,8 @@ __global__ __launch_bounds__(kConvThreads) void conv3x3_tiled_kernel(const uint1
                                                                      void* __restrict__ y, int ldy, int y_fp32,
                                                                      int cout_store, int epi,
                                                                      const uint16_t* __restrict__ msrc, int ldm,
-                                                                     int ups, int ntiles) {
+                                                                     int ups, int ntiles, uint16_t* __restrict__ pool,
+                                                                     int ldp) {
   constexpr int NB = CT / 16;
   __shared__ __align__(16) uint16_t patch[kPatchH * kPatchW * kPatchStride];
   // The chunk's weights for all nine taps: [tap][output channel][32 + 8 pad].
@@ -156,6 +157,36 @@ __global__ __launch_bounds__(kConvThreads) void conv3x3_tiled_kernel(const uint1
           reinterpret_cast<float*>(y)[p * ldy + co] = v;
         else
           reinterpret_cast<uint16_t*>(y)[p * ldy + co] = to_bf16(v);
+      }
+    }
+  }
+  // Optional 2x2 average pool of the stored bf16 outputs (H, W even): a
+  // window is rows 2*wave, 2*wave + 1 (M tiles m and m + 2) and columns
+  // r, r + 1 (r even) of one lane, summed as the pooling kernel sums them.
+  if (pool) {
+    const int Ho = H >> 1, Wo = W >> 1;
+    const long long imgo = (long long)n * Ho * Wo;
+    const int yo = (y0 >> 1) + wave;
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int co = co0 + nb * 16 + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; r += 2) {
+          const int xo = (x0 + (m & 1) * 16 + (lane >> 4) * 4 + r) >> 1;
+          if (yo >= Ho || xo >= Wo || co >= cout_store) continue;
+          float q[4];
+          const float src[4] = {acc[m][nb][r], acc[m][nb][r + 1], acc[m + 2][nb][r], acc[m + 2][nb][r + 1]};
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            float v = src[u];
+            if (epi == 1) v = fmaxf(v, 0.0f);  // (a pooled launch has no masked epilogue)
+            q[u] = from_bf16(to_bf16(v));
+          }
+          const float sum = (q[0] + q[1]) + (q[2] + q[3]);
+          pool[(imgo + (long long)yo * Wo + xo) * ldp + co] = to_bf16(sum * 0.25f);
+        }
       }
     }
   }
@@ -704,7 +735,7 @@ int conv_blocks_per_cu() {
 
 hipError_t conv3x3_launch(const uint16_t* x, int ldx, int N, int H, int W, int Cin, const uint16_t* wgt, int Cout,
                           void* y, int ldy, int y_fp32, int cout_store, int epi, const uint16_t* msrc, int ldm, int ups,
-                          hipStream_t s) {
+                          hipStream_t s, uint16_t* pool = nullptr, int ldp = 0) {
   const long long tiles = (long long)N * ((H + kTileH - 1) / kTileH) * ((W + kTileW - 1) / kTileW);
   if (tiles > 0x7FFFFFFFLL) return hipErrorInvalidValue;
   const int nt = (int)tiles;
@@ -718,15 +749,15 @@ hipError_t conv3x3_launch(const uint16_t* x, int ldx, int N, int H, int W, int C
   if (cout_store <= 16) {  // e.g. the 3-channel head: only the first 16 outputs are computed
     hipLaunchKernelGGL(conv3x3_tiled_kernel<16>, dim3(grid_x(conv_blocks_per_cu<16>()), 1),
                        dim3(kConvThreads), 0, s, x, ldx, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi,
-                       msrc, ldm, ups, nt);
+                       msrc, ldm, ups, nt, pool, ldp);
   } else if (Cout % 64 == 0) {
     hipLaunchKernelGGL(conv3x3_tiled_kernel<64>, dim3(grid_x(conv_blocks_per_cu<64>()), Cout / 64),
                        dim3(kConvThreads), 0, s, x, ldx, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi,
-                       msrc, ldm, ups, nt);
+                       msrc, ldm, ups, nt, pool, ldp);
   } else {
     hipLaunchKernelGGL(conv3x3_tiled_kernel<32>, dim3(grid_x(conv_blocks_per_cu<32>()), Cout / 32),
                        dim3(kConvThreads), 0, s, x, ldx, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi,
-                       msrc, ldm, ups, nt);
+                       msrc, ldm, ups, nt, pool, ldp);
   }
   return hipGetLastError();
 }
@@ -735,6 +766,12 @@ hipError_t conv3x3_launch(const uint16_t* x, int ldx, int N, int H, int W, int C
 hipError_t nn_conv3x3(const uint16_t* x, int ldx, int N, int H, int W, int Cin, const uint16_t* wgt, int Cout, void* y,
                       int ldy, int y_fp32, int cout_store, int epi, const uint16_t* msrc, int ldm, hipStream_t s) {
   return conv3x3_launch(x, ldx, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi, msrc, ldm, 0, s);
+}
+
+hipError_t nn_conv3x3_pool(const uint16_t* x, int ldx, int N, int H, int W, int Cin, const uint16_t* wgt, int Cout,
+                           uint16_t* y, int ldy, int relu, uint16_t* pool, int ldp, hipStream_t s) {
+  if (H % 2 || W % 2 || !pool) return hipErrorInvalidValue;
+  return conv3x3_launch(x, ldx, N, H, W, Cin, wgt, Cout, y, ldy, 0, Cout, relu ? 1 : 0, nullptr, 0, 0, s, pool, ldp);
 }
 
 hipError_t nn_conv3x3_up(const uint16_t* x, int ldx, int N, int H, int W, int Cin, const uint16_t* wgt, int Cout,

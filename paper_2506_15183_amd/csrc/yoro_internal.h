@@ -99,6 +99,11 @@ constexpr int kLossBlocks = 512;   // blocks (and partial sums) of the L1 loss
 size_t nn_wgrad_chunks(long long P);
 hipError_t nn_conv3x3(const uint16_t* x, int ldx, int N, int H, int W, int Cin, const uint16_t* wgt, int Cout, void* y,
                       int ldy, int y_fp32, int cout_store, int epi, const uint16_t* msrc, int ldm, hipStream_t s);
+// The convolution (bf16 output, optional ReLU) followed by a 2x2 average
+// pool of its stored output into `pool` (H, W even), in one pass; equal to
+// nn_conv3x3 then nn_avgpool2.
+hipError_t nn_conv3x3_pool(const uint16_t* x, int ldx, int N, int H, int W, int Cin, const uint16_t* wgt, int Cout,
+                           uint16_t* y, int ldy, int relu, uint16_t* pool, int ldp, hipStream_t s);
 // The same convolution applied to the nearest x2 upsampling of x (x is
 // N x H/2 x W/2; H, W even), read in place.
 hipError_t nn_conv3x3_up(const uint16_t* x, int ldx, int N, int H, int W, int Cin, const uint16_t* wgt, int Cout,
