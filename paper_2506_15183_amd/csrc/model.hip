@@ -45,7 +45,7 @@ bool al4(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }
 
 // Activation buffers of one forward pass (bf16 NHWC; res FP32 [P0][3]).
 struct Acts {
-  uint16_t *x0, *e0a, *c0, *d0b, *d0c;
+  uint16_t *e0a, *c0, *d0b, *d0c;
   uint16_t *p1, *e1a, *c1, *d1b, *d1c;
   uint16_t *p2, *e2a, *c2, *d2b, *d2c;
   uint16_t *p3, *e3a, *e3b;
@@ -64,7 +64,7 @@ size_t carve(char* base, long long n, int h, int w, Acts* a) {
   for (int l = 0; l < 4; ++l) P[l] = n * (long long)(h >> l) * (w >> l);
   auto bf = [&](long long p, int c) { return reinterpret_cast<uint16_t*>(take(p * c, 2)); };
   Acts t;
-  t.x0 = bf(P[0], 32), t.e0a = bf(P[0], 32), t.c0 = bf(P[0], 64), t.d0b = bf(P[0], 32), t.d0c = bf(P[0], 32);
+  t.e0a = bf(P[0], 32), t.c0 = bf(P[0], 64), t.d0b = bf(P[0], 32), t.d0c = bf(P[0], 32);
   t.p1 = bf(P[1], 32), t.e1a = bf(P[1], 64), t.c1 = bf(P[1], 128), t.d1b = bf(P[1], 64), t.d1c = bf(P[1], 64);
   t.p2 = bf(P[2], 64), t.e2a = bf(P[2], 128), t.c2 = bf(P[2], 256), t.d2b = bf(P[2], 128), t.d2c = bf(P[2], 128);
   t.p3 = bf(P[3], 128), t.e3a = bf(P[3], 256), t.e3b = bf(P[3], 256);
@@ -86,14 +86,15 @@ hipError_t forward(const uint16_t* wts, const uint8_t* rgba, const float* depth,
     ok(nn_conv3x3(x, ldx, n, h >> lev, w >> lev, L.cin, wts + layer_offset(i), L.cout, y, ldy, 0, L.cout, 1, nullptr,
                   0, s));
   };
-  ok(nn_input(reinterpret_cast<const uint32_t*>(rgba), depth, mask, (long long)n * h * w, a.x0, s));
+  // The first convolution packs the frame's channels itself (no packed copy).
   // The encoders' second convolutions also write the 2x2 average pool of
   // their output (the next level's input) in the same pass.
   auto conv_pool = [&](int i, const uint16_t* x, int ldx, int lev, uint16_t* y, int ldy, uint16_t* pool, int ldp) {
     const Layer L = kLayers[i];
     ok(nn_conv3x3_pool(x, ldx, n, h >> lev, w >> lev, L.cin, wts + layer_offset(i), L.cout, y, ldy, 1, pool, ldp, s));
   };
-  conv(0, a.x0, 32, 0, a.e0a, 32);
+  ok(nn_conv3x3_input(reinterpret_cast<const uint32_t*>(rgba), depth, mask, n, h, w, wts + layer_offset(0),
+                      kLayers[0].cout, a.e0a, 32, 1, s));
   conv_pool(1, a.e0a, 32, 0, a.c0 + 32, 64, a.p1, 32);  // e0b -> the skip half of c0, and its pool
   conv(2, a.p1, 32, 1, a.e1a, 64);
   conv_pool(3, a.e1a, 64, 1, a.c1 + 64, 128, a.p2, 64);  // e1b

@@ -50,6 +50,24 @@ constexpr int kTileH = 8, kTileW = 32;
 constexpr int kPatchH = kTileH + 2, kPatchW = kTileW + 2;
 constexpr int kPatchStride = 40;
 
+constexpr float kLogZmin = -1.2039728043259361f;  // log(0.3)
+constexpr float kLogZmax = 3.912023005428146f;    // log(50)
+
+// The network's first eight input channels of one pixel as bf16 (R, G, B
+// in [0, 1], the hole mask, log depth scaled to [0, 1] with NaN -> 1, three
+// zeros); the other 24 channels are zero.
+__device__ __forceinline__ u32x4 input_channels(uint32_t c, float z, uint8_t m) {
+  float ld = (logf(z) - kLogZmin) / (kLogZmax - kLogZmin);
+  ld = (ld >= 0.0f) ? (ld <= 1.0f ? ld : 1.0f) : (ld < 0.0f ? 0.0f : 1.0f);  // NaN -> 1
+  uint16_t v[5];
+  v[0] = to_bf16((float)(c & 255u) / 255.0f);
+  v[1] = to_bf16((float)((c >> 8) & 255u) / 255.0f);
+  v[2] = to_bf16((float)((c >> 16) & 255u) / 255.0f);
+  v[3] = to_bf16(m != 0 ? 1.0f : 0.0f);
+  v[4] = to_bf16(ld);
+  return u32x4{(uint32_t)v[0] | ((uint32_t)v[1] << 16), (uint32_t)v[2] | ((uint32_t)v[3] << 16), (uint32_t)v[4], 0u};
+}
+
 template <int CT>
 __global__ __launch_bounds__(kConvThreads) void conv3x3_tiled_kernel(const uint16_t* __restrict__ x, int ldx, int N,
                                                                      int H, int W, int Cin,
@@ -58,7 +76,9 @@ __global__ __launch_bounds__(kConvThreads) void conv3x3_tiled_kernel(const uint1
                                                                      int cout_store, int epi,
                                                                      const uint16_t* __restrict__ msrc, int ldm,
                                                                      int ups, int ntiles, uint16_t* __restrict__ pool,
-                                                                     int ldp) {
+                                                                     int ldp, const uint32_t* __restrict__ raw_rgba,
+                                                                     const float* __restrict__ raw_depth,
+                                                                     const uint8_t* __restrict__ raw_mask) {
   constexpr int NB = CT / 16;
   __shared__ __align__(16) uint16_t patch[kPatchH * kPatchW * kPatchStride];
   // The chunk's weights for all nine taps: [tap][output channel][32 + 8 pad].
@@ -107,7 +127,14 @@ __global__ __launch_bounds__(kConvThreads) void conv3x3_tiled_kernel(const uint1
       const int py = pix / kPatchW, px = pix - py * kPatchW;
       const int gy = y0 + py - 1, gx = x0 + px - 1;
       u32x4 v = {0u, 0u, 0u, 0u};
-      if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+      if (raw_rgba) {
+        // The first layer reads the frame itself: its packed input (Cin 32)
+        // is built here, channel by channel as the input-packing kernel does.
+        if (part == 0 && gy >= 0 && gy < H && gx >= 0 && gx < W) {
+          const long long q = img + (long long)gy * W + gx;
+          v = input_channels(raw_rgba[q], raw_depth[q], raw_mask[q]);
+        }
+      } else if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
         // ups: x is the half-resolution image and the input is its nearest
         // x2 upsampling, read in place.
         const long long src = ups ? (img >> 2) + (long long)(gy >> 1) * (W >> 1) + (gx >> 1)
@@ -503,26 +530,13 @@ __global__ void upsample2_grad_v8_kernel(const uint16_t* __restrict__ g, int ldg
 }
 
 // --------------------------------------------------- input, loss, output --
-constexpr float kLogZmin = -1.2039728043259361f;  // log(0.3)
-constexpr float kLogZmax = 3.912023005428146f;    // log(50)
 
 // Network input, 32 channels: R, G, B / 255, hole (mask != 0), log-depth in
 // [log 0.3, log 50] -> [0, 1] (clamped; +inf and NaN -> 1), then zeros.
 __global__ void unet_input_kernel(const uint32_t* __restrict__ rgba, const float* __restrict__ depth,
                                   const uint8_t* __restrict__ mask, long long npix, uint16_t* __restrict__ x) {
   for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += (long long)gridDim.x * blockDim.x) {
-    const uint32_t c = rgba[p];
-    const float z = depth[p];
-    float ld = (logf(z) - kLogZmin) / (kLogZmax - kLogZmin);
-    ld = (ld >= 0.0f) ? (ld <= 1.0f ? ld : 1.0f) : (ld < 0.0f ? 0.0f : 1.0f);  // NaN -> 1
-    uint16_t v[8];
-    v[0] = to_bf16((float)(c & 255u) / 255.0f);
-    v[1] = to_bf16((float)((c >> 8) & 255u) / 255.0f);
-    v[2] = to_bf16((float)((c >> 16) & 255u) / 255.0f);
-    v[3] = to_bf16(mask[p] != 0 ? 1.0f : 0.0f);
-    v[4] = to_bf16(ld);
-    v[5] = v[6] = v[7] = 0;
-    u32x4 w0 = {(uint32_t)v[0] | ((uint32_t)v[1] << 16), (uint32_t)v[2] | ((uint32_t)v[3] << 16), (uint32_t)v[4], 0u};
+    const u32x4 w0 = input_channels(rgba[p], depth[p], mask[p]);
     u32x4 zero = {0u, 0u, 0u, 0u};
     u32x4* dst = reinterpret_cast<u32x4*>(x + p * 32);
     dst[0] = w0;
@@ -735,7 +749,9 @@ int conv_blocks_per_cu() {
 
 hipError_t conv3x3_launch(const uint16_t* x, int ldx, int N, int H, int W, int Cin, const uint16_t* wgt, int Cout,
                           void* y, int ldy, int y_fp32, int cout_store, int epi, const uint16_t* msrc, int ldm, int ups,
-                          hipStream_t s, uint16_t* pool = nullptr, int ldp = 0) {
+                          hipStream_t s, uint16_t* pool = nullptr, int ldp = 0,
+                          const uint32_t* raw_rgba = nullptr, const float* raw_depth = nullptr,
+                          const uint8_t* raw_mask = nullptr) {
   const long long tiles = (long long)N * ((H + kTileH - 1) / kTileH) * ((W + kTileW - 1) / kTileW);
   if (tiles > 0x7FFFFFFFLL) return hipErrorInvalidValue;
   const int nt = (int)tiles;
@@ -749,15 +765,18 @@ hipError_t conv3x3_launch(const uint16_t* x, int ldx, int N, int H, int W, int C
   if (cout_store <= 16) {  // e.g. the 3-channel head: only the first 16 outputs are computed
     hipLaunchKernelGGL(conv3x3_tiled_kernel<16>, dim3(grid_x(conv_blocks_per_cu<16>()), 1),
                        dim3(kConvThreads), 0, s, x, ldx, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi,
-                       msrc, ldm, ups, nt, pool, ldp);
+                       msrc, ldm, ups, nt, pool, ldp, raw_rgba, raw_depth,
+                       raw_mask);
   } else if (Cout % 64 == 0) {
     hipLaunchKernelGGL(conv3x3_tiled_kernel<64>, dim3(grid_x(conv_blocks_per_cu<64>()), Cout / 64),
                        dim3(kConvThreads), 0, s, x, ldx, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi,
-                       msrc, ldm, ups, nt, pool, ldp);
+                       msrc, ldm, ups, nt, pool, ldp, raw_rgba, raw_depth,
+                       raw_mask);
   } else {
     hipLaunchKernelGGL(conv3x3_tiled_kernel<32>, dim3(grid_x(conv_blocks_per_cu<32>()), Cout / 32),
                        dim3(kConvThreads), 0, s, x, ldx, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi,
-                       msrc, ldm, ups, nt, pool, ldp);
+                       msrc, ldm, ups, nt, pool, ldp, raw_rgba, raw_depth,
+                       raw_mask);
   }
   return hipGetLastError();
 }
@@ -766,6 +785,13 @@ hipError_t conv3x3_launch(const uint16_t* x, int ldx, int N, int H, int W, int C
 hipError_t nn_conv3x3(const uint16_t* x, int ldx, int N, int H, int W, int Cin, const uint16_t* wgt, int Cout, void* y,
                       int ldy, int y_fp32, int cout_store, int epi, const uint16_t* msrc, int ldm, hipStream_t s) {
   return conv3x3_launch(x, ldx, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi, msrc, ldm, 0, s);
+}
+
+hipError_t nn_conv3x3_input(const uint32_t* rgba, const float* depth, const uint8_t* mask, int N, int H, int W,
+                            const uint16_t* wgt, int Cout, uint16_t* y, int ldy, int relu, hipStream_t s) {
+  if (!rgba || !depth || !mask) return hipErrorInvalidValue;
+  return conv3x3_launch(nullptr, 32, N, H, W, 32, wgt, Cout, y, ldy, 0, Cout, relu ? 1 : 0, nullptr, 0, 0, s, nullptr, 0,
+                        rgba, depth, mask);
 }
 
 hipError_t nn_conv3x3_pool(const uint16_t* x, int ldx, int N, int H, int W, int Cin, const uint16_t* wgt, int Cout,

@@ -99,6 +99,11 @@ constexpr int kLossBlocks = 512;   // blocks (and partial sums) of the L1 loss
 size_t nn_wgrad_chunks(long long P);
 hipError_t nn_conv3x3(const uint16_t* x, int ldx, int N, int H, int W, int Cin, const uint16_t* wgt, int Cout, void* y,
                       int ldy, int y_fp32, int cout_store, int epi, const uint16_t* msrc, int ldm, hipStream_t s);
+// The first convolution (Cin 32, bf16 output, optional ReLU) reading the
+// frame's RGBA, depth and mask and packing them as nn_input does, in one
+// pass; equal to nn_input then nn_conv3x3.
+hipError_t nn_conv3x3_input(const uint32_t* rgba, const float* depth, const uint8_t* mask, int N, int H, int W,
+                            const uint16_t* wgt, int Cout, uint16_t* y, int ldy, int relu, hipStream_t s);
 // The convolution (bf16 output, optional ReLU) followed by a 2x2 average
 // pool of its stored output into `pool` (H, W even), in one pass; equal to
 // nn_conv3x3 then nn_avgpool2.
