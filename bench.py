@@ -322,8 +322,13 @@ def main():
         prog = serve.run_interleaved(srv, trace, (serve.LEARNED,), rounds=2)
         srv.cfg.progressive = False
         serving["sparse_scenes"]["learned_progressive"] = serve.summarize(*prog[serve.LEARNED], hs, sparse_s)
-        log(f"serving, sparse scenes ({time.time() - t1:.1f}s): {serving['sparse_scenes']}")
         del srv
+        # What a refinement buys on such frames: hole PSNR against the
+        # ray-cast other eye, plain and learned fill.
+        from paper_2506_15183_amd import evaluate
+
+        serving["sparse_scenes"]["hole_psnr"] = evaluate.evaluate_sparse(net, 6)
+        log(f"serving, sparse scenes ({time.time() - t1:.1f}s): {serving['sparse_scenes']}")
 
     value = pixels * args.steps / wall / 1e6
     result = {

@@ -134,6 +134,37 @@ def evaluate(net: unet.UNet, n_frames: int = 16, log=None, timing_reps: int = 5)
     }
 
 
+def evaluate_sparse(net: unet.UNet, n_frames: int = 8):
+    """Hole PSNR of the plain and the learned fill against the ray-cast target
+    eye on the serving loop's sparse-scene frames (the frames its learned
+    policy refines: 1-3 % holes), whole frames, the three serving sizes and
+    both eyes in turn."""
+    from .scenes.configs import SERVE_SIZES, config5_pool_frame
+
+    dev = net.device
+    pooled = np.zeros((2, 2), dtype=np.int64)  # [plain, learned] x [sse, count]
+    fracs = []
+    for i in range(n_frames):
+        w, h = SERVE_SIZES[i % len(SERVE_SIZES)]
+        spec = config5_pool_frame(w, h, i % 2, 100 + i, sparse=True)
+        s_rgba, s_depth = spec.render_source()
+        t_rgba, _ = spec.render_target()
+        src = torch.from_numpy(s_rgba).to(dev)
+        srd = torch.from_numpy(s_depth).to(dev)
+        tgt = torch.from_numpy(t_rgba).to(dev)
+        rgba, depth, mask = yoro.reproject(src, srd, spec.baseline_m, spec.focal_px, spec.target_eye,
+                                           yoro.FILL_NEAREST_BG)
+        out = net.fill_native(rgba[None], depth[None], mask[None])[0]
+        sp = _sse(rgba, tgt, mask)
+        pooled[0] += sp
+        pooled[1] += _sse(out, tgt, mask)
+        fracs.append(sp[1] / spec.pixels)
+    return {"frames": n_frames, "sizes": [f"{w}x{h}" for w, h in SERVE_SIZES],
+            "hole_fraction_mean": round(float(np.mean(fracs)), 4),
+            "hole_psnr_plain_db": round(_psnr(*pooled[0]), 3),
+            "hole_psnr_learned_db": round(_psnr(*pooled[1]), 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--frames", type=int, default=16)
