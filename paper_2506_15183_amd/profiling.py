@@ -129,9 +129,10 @@ def summarize_learned(trace_dir: str) -> str:
         n = n.replace("void ", "").replace("yoro::(anonymous namespace)::", "")
         return n.split("(")[0]
 
+    # The whole-frame forwards come first (each ends with the composite), the
+    # training steps after them (each starts by packing its input).
+    ends = [i for i, (n, _) in enumerate(rows) if short(n).startswith("composite_kernel")]
     starts = [i for i, (n, _) in enumerate(rows) if short(n).startswith("unet_input")]
-    fwd_at = [i for i in starts if i + 1 < len(rows)]
-    # The whole-frame forwards come first, the training steps after them.
     lines = ["# Learned fill kernels: one 1832x1920 forward pass and one training step", "",
              "Commands (from the repository root, on one MI355X; OUT=the output directory):", "", "```",
              "rocprofv3 --kernel-trace --stats -d $OUT -o l -- python -m paper_2506_15183_amd.profiling learned",
@@ -139,15 +140,17 @@ def summarize_learned(trace_dir: str) -> str:
              "## Forward pass (last whole-frame fill), in order", "",
              "FLOPs per convolution over the channels the kernels compute (padded to 32, the head's 16-wide tile).",
              "", "| # | step | kernel | us | TFLOP/s |", "|---|---|---|---|---|"]
-    steps = ["input", "e0a", "e0b", "pool", "e1a", "e1b", "pool", "e2a", "e2b", "pool", "e3a", "e3b",
-             "d2a (upsampling load)", "d2b", "d2c", "d1a (upsampling load)", "d1b", "d1c", "d0a (upsampling load)",
-             "d0b", "d0c", "head", "composite"]
+    steps = ["e0a (packs the input)", "e0b (+ 2x2 pool)", "e1a", "e1b (+ 2x2 pool)", "e2a", "e2b (+ 2x2 pool)", "e3a",
+             "e3b", "d2a (upsampling load)", "d2b", "d2c", "d1a (upsampling load)", "d1b", "d1c",
+             "d0a (upsampling load)", "d0b", "d0c", "head", "composite"]
     lev = {"e0": 0, "e1": 1, "e2": 2, "e3": 3, "d2": 2, "d1": 1, "d0": 0, "he": 0}
     cin = {"e0a": 32, "e0b": 32, "e1a": 32, "e1b": 64, "e2a": 64, "e2b": 128, "e3a": 128, "e3b": 256, "d2a": 256,
            "d2b": 256, "d2c": 128, "d1a": 128, "d1b": 128, "d1c": 64, "d0a": 64, "d0b": 64, "d0c": 32, "head": 32}
     cout = {"e0a": 32, "e0b": 32, "e1a": 64, "e1b": 64, "e2a": 128, "e2b": 128, "e3a": 256, "e3b": 256, "d2a": 128,
             "d2b": 128, "d2c": 128, "d1a": 64, "d1b": 64, "d1c": 64, "d0a": 32, "d0b": 32, "d0c": 32, "head": 16}
-    i0 = fwd_at[3] if len(fwd_at) > 4 else fwd_at[0]
+    # The last whole-frame forward: the kernels after the previous composite.
+    n_fwd = len([e for e in ends if not starts or e < starts[0]])
+    i0 = ends[n_fwd - 2] + 1 if n_fwd >= 2 else 0
     total = 0.0
     k = 0
     for name, dur in rows[i0:]:
@@ -165,7 +168,7 @@ def summarize_learned(trace_dir: str) -> str:
             break
     lines += ["", f"forward total: {total / 1000:.1f} us", "", "## Training step (last), kernel totals", "",
               "| kernel | calls | us |", "|---|---|---|"]
-    last = fwd_at[-1]
+    last = starts[-1]
     agg = {}
     for name, dur in rows[last:]:
         nm = short(name)
