@@ -59,7 +59,7 @@ def main():
     ap.add_argument("--no-lowres", action="store_true", help="skip the downsampled-buffer batch timings")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the plain path shards "
+        print(f"bench.py: the library runs on one GPU only (asked for {args.gpus}); the plain path shards "
               "frames or row bands across GPUs with no exchange, so per-GPU throughput is the figure.",
               file=sys.stderr)
         sys.exit(2)
