@@ -371,6 +371,21 @@ def summarize_pose(out_dir: str) -> str:
     return "\n".join(lines)
 
 
+def summarize_warp_counters(path_dir: str) -> str:
+    """Mean of every counter per dispatch of the warp batch kernel (a --pmc run
+    of the counters workload), one line each."""
+    c = _db(path_dir)
+    acc = {}
+    for name, cname, val in c.execute("select kernel_name, counter_name, value from counters_collection"):
+        if WARP_KERNEL in name:
+            acc.setdefault(cname, []).append(float(val))
+    lines = [f"kernel_source_sha: {kernel_source_sha()}"]
+    for k in sorted(acc):
+        v = acc[k]
+        lines.append(f"{k}: {sum(v) / len(v):.4g} (mean of {len(v)} dispatches)")
+    return "\n".join(lines)
+
+
 def read_summary(path: str):
     """(traffic bytes per launch, kernel source sha) from a committed summary, or (None, None)."""
     if not os.path.exists(path):
@@ -388,6 +403,8 @@ if __name__ == "__main__":
         learned_workload()
     elif len(sys.argv) >= 3 and sys.argv[1] == "summarize-learned":
         print(summarize_learned(sys.argv[2]))
+    elif len(sys.argv) >= 3 and sys.argv[1] == "summarize-counters":
+        print(summarize_warp_counters(sys.argv[2]))
     elif len(sys.argv) >= 3 and sys.argv[1] == "summarize-pose":
         print(summarize_pose(sys.argv[2]))
     elif len(sys.argv) >= 3 and sys.argv[1] == "summarize-lowres":
