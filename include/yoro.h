@@ -195,7 +195,8 @@ const uint32_t* yoro_stereo_batch_errors(const void* dev_workspace);
  *   pixel's RGBA (its own row) and the depth z of texel n, mask 0.
  * All FP32, each operation rounded once.  Holes are then filled per
  * fill_mode exactly as yoro_reproject fills them.  With scale 1 the result
- * is yoro_reproject's, bit for bit.  Arguments, ownership, outputs and
+ * is yoro_reproject's, bit for bit, and the call runs yoro_reproject's
+ * kernels.  Arguments, ownership, outputs and
  * errors as yoro_reproject; scale outside {1, 2, 4, 8, 16} or linear
  * outside {0, 1} is YORO_ERR_INVALID_ARG.
  */
@@ -208,7 +209,8 @@ int32_t yoro_reproject_lowres(const uint8_t* src_rgba, const float* src_depth, i
  * yoro_stereo_batch_launch_lowres -- run the jobs that the last prepare on
  * this workspace uploaded, each as yoro_reproject_lowres with the given
  * scale and linear flag, as one persistent kernel.  A workgroup takes
- * scale rows of one block row at a time.  max_width and the error counter
+ * scale rows of one block row at a time; scale 1 runs
+ * yoro_stereo_batch_launch's kernel.  max_width and the error counter
  * as in yoro_stereo_batch_launch.  Capture-safe: no allocation, copy or
  * sync.
  */

@@ -209,6 +209,19 @@ int32_t yoro_reproject_lowres(const uint8_t* src_rgba, const float* src_depth, i
     if (ppt < 0) return fail(YORO_ERR_UNSUPPORTED, "yoro_reproject_lowres: width %d too wide", width);
     yoro_job j{src_rgba, src_depth, dst_rgba, dst_depth, dst_mask, width, height, baseline_m, focal_px,
                target_eye, patcher ? (int32_t)YORO_FILL_NONE : fill_mode};
+    if (lg == 0) {
+      // One texel per pixel samples its own shift: the direct path, with or
+      // without interpolation (the shift is read at the texel itself).
+      const int grid = grid_for(height, yoro::warp_blocks_per_cu(width, false));
+      hipError_t e = yoro::launch_warp_single(make_job(j, 0), ppt, grid, (hipStream_t)hip_stream);
+      if (e == hipSuccess && patcher)
+        e = yoro::launch_fill(reinterpret_cast<uint32_t*>(dst_rgba), dst_depth, dst_mask, width, height, target_eye,
+                              fill_mode, ppt, grid_for(height, yoro::fill_blocks_per_cu(width, fill_mode)),
+                              (hipStream_t)hip_stream);
+      if (e != hipSuccess)
+        return fail(YORO_ERR_DEVICE, "yoro_reproject_lowres: launch failed: %s", hipGetErrorString(e));
+      return ok();
+    }
     const yoro::DevJob dj = make_job(j, 0);
     // Units of G rows: as many rows per unit as still leave two units per
     // resident workgroup.
@@ -451,6 +464,13 @@ int32_t yoro_stereo_batch_launch_lowres(const void* dev_workspace, int32_t max_w
     const auto* dj = reinterpret_cast<const yoro::DevJob*>(hdr + 1);
     DeviceFacts f;
     const int cus = device_facts(&f) ? f.cus : 256;
+    if (lg == 0) {  // scale 1 is the direct path
+      const int grid = cus * yoro::warp_blocks_per_cu(max_width, true);
+      hipError_t e = yoro::launch_warp_batch(hdr, dj, max_width, grid, (hipStream_t)hip_stream);
+      if (e != hipSuccess)
+        return fail(YORO_ERR_DEVICE, "yoro_stereo_batch_launch_lowres: launch failed: %s", hipGetErrorString(e));
+      return ok();
+    }
     const int grid = cus * yoro::lowres_blocks_per_cu(max_width, lg, true);
     hipError_t e = yoro::launch_lowres(nullptr, hdr, dj, max_width, lg, lg, linear, grid, (hipStream_t)hip_stream);
     if (e != hipSuccess)
