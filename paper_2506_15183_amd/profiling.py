@@ -317,6 +317,7 @@ def summarize_lowres(out_dir: str, pixels: int, max_width: int = 2160) -> str:
         "```",
         "",
         "RGBA output only, interpolated shift, one unit = one block row of k rows.",
+        "Scale 1 runs the direct warp kernel (its own summary), so its row is absent here.",
         "Algorithmic bytes per pixel: 4 B gathered + 4 B written + 4/k^2 B of block-centre depth.",
         "Counter bytes are scaled as for the warp kernel (copy-kernel calibration).",
         "",
