@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdint>
+#include <functional>
 
 #include "yoro.h"
 #include "yoro_internal.h"
@@ -217,6 +218,18 @@ int32_t yoro_model_fill_tiles(const void* weights, const uint8_t* rgba, const fl
                               int32_t w, int32_t h, const int32_t* plan, int32_t k, int32_t tile, int32_t halo,
                               int32_t chunk, uint8_t* out, void* workspace, size_t workspace_bytes,
                               void* hip_stream) {
+  return yoro::model_fill_tiles_paced(weights, rgba, depth, mask, w, h, plan, k, tile, halo, chunk, out, workspace,
+                                      workspace_bytes, hip_stream, std::function<hipError_t()>());
+}
+
+}  // extern "C"
+
+namespace yoro {
+
+int32_t model_fill_tiles_paced(const void* weights, const uint8_t* rgba, const float* depth, const uint8_t* mask,
+                               int32_t w, int32_t h, const int32_t* plan, int32_t k, int32_t tile, int32_t halo,
+                               int32_t chunk, uint8_t* out, void* workspace, size_t workspace_bytes,
+                               void* hip_stream, const std::function<hipError_t()>& between) {
   const char* who = "yoro_model_fill_tiles";
   if (!weights || !rgba || !depth || !mask || !plan || !out || !workspace)
     return model_fail(YORO_ERR_INVALID_ARG, "%s: null pointer", who);
@@ -248,8 +261,9 @@ int32_t yoro_model_fill_tiles(const void* weights, const uint8_t* rgba, const fl
     if (e == hipSuccess)
       e = yoro::nn_composite_tiles(a.res, plan + 4 * c0, kc, crop, tile, w, h, reinterpret_cast<const uint32_t*>(rgba),
                                    mask, reinterpret_cast<uint32_t*>(out), s);
+    if (e == hipSuccess && between && c0 + cmax < k) e = between();
   }
   return launched(e, who);
 }
 
-}  // extern "C"
+}  // namespace yoro

@@ -306,9 +306,22 @@ int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, c
         *err = std::string("plan upload: ") + hipGetErrorString(e);
         return YORO_ERR_DEVICE;
       }
-      const int32_t st = yoro_model_fill_tiles(O.model_weights, H.dst_rgba[o], H.dst_depth[o], H.dst_mask[o], H.width,
-                                               H.height, plan_dev, kc, O.tile, O.halo, O.chunk, H.dst_rgba[o],
-                                               O.learned_workspace, O.learned_workspace_bytes, ls);
+      // One chunk of crops in flight at a time: streams can share a hardware
+      // queue, and a warp batch queued behind the refinement then waits for
+      // the chunk ahead of it, not for the whole refinement.
+      hipEvent_t pev = nullptr;
+      e = hipEventCreateWithFlags(&pev, hipEventDisableTiming);
+      if (e != hipSuccess) {
+        *err = std::string("pacing event: ") + hipGetErrorString(e);
+        return YORO_ERR_DEVICE;
+      }
+      const int32_t st = yoro::model_fill_tiles_paced(
+          O.model_weights, H.dst_rgba[o], H.dst_depth[o], H.dst_mask[o], H.width, H.height, plan_dev, kc, O.tile,
+          O.halo, O.chunk, H.dst_rgba[o], O.learned_workspace, O.learned_workspace_bytes, ls, [pev, ls]() {
+            hipError_t r = hipEventRecord(pev, ls);
+            return r == hipSuccess ? hipEventSynchronize(pev) : r;
+          });
+      (void)hipEventDestroy(pev);
       if (st != YORO_OK) {
         *err = std::string("tile fill: ") + yoro_last_error();
         return st;

@@ -1,6 +1,8 @@
 // Internal definitions shared by the HIP kernels and the C-ABI host code.
 #pragma once
 
+#include <functional>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -102,6 +104,16 @@ hipError_t nn_conv3x3(const uint16_t* x, int ldx, int N, int H, int W, int Cin, 
 // The first convolution (Cin 32, bf16 output, optional ReLU) reading the
 // frame's RGBA, depth and mask and packing them as nn_input does, in one
 // pass; equal to nn_input then nn_conv3x3.
+// yoro_model_fill_tiles with a host call between chunks of crops (after each
+// chunk's composite is enqueued, before the next chunk's forward pass): the
+// caller may wait there, so that work queued behind the fill on the same
+// hardware queue waits for one chunk at most.  Same arguments, results and
+// errors as yoro_model_fill_tiles otherwise; an empty between is that call.
+int32_t model_fill_tiles_paced(const void* weights, const uint8_t* rgba, const float* depth, const uint8_t* mask,
+                               int32_t w, int32_t h, const int32_t* plan, int32_t k, int32_t tile, int32_t halo,
+                               int32_t chunk, uint8_t* out, void* workspace, size_t workspace_bytes,
+                               void* hip_stream, const std::function<hipError_t()>& between);
+
 hipError_t nn_conv3x3_input(const uint32_t* rgba, const float* depth, const uint8_t* mask, int N, int H, int W,
                             const uint16_t* wgt, int Cout, uint16_t* y, int ldy, int relu, hipStream_t s);
 // The convolution (bf16 output, optional ReLU) followed by a 2x2 average
