@@ -32,8 +32,12 @@
  * given below.  yoro_serve_admit picks the headsets that fit an HBM budget.
  *
  * Streams: the plain work runs on hip_stream, the refinement on
- * options->learned_stream (both of default priority).  The call returns when
- * every admitted frame is final; it synchronises both streams at the end.
+ * options->learned_stream (both of default priority).  A worker thread of
+ * the call enqueues each refinement one chunk of crops at a time and waits
+ * for a chunk before it enqueues the next, so a warp that shares a hardware
+ * queue with the refinement waits for one chunk at most.  The call returns
+ * when every admitted frame is final; it synchronises both streams at the
+ * end.
  */
 #ifndef YORO_SERVE_H
 #define YORO_SERVE_H
