@@ -158,8 +158,9 @@ __device__ __forceinline__ void resolve_fill_row(const RowLds& s, int W, bool ta
     const int word = lane * (kThreads / 64) + wave;
     if (lane < nchunks && word < nw) s.mask[word] = mword;
     __syncthreads();
-    // E: this wave fills the holes it listed.  Only hits are read, only
-    // holes written.
+    // E (at the lowest wave priority): this wave fills the holes it listed.
+    // Only hits are read, only holes written.
+    __builtin_amdgcn_s_setprio(0);
     for (uint32_t h0 = 0; h0 < run; h0 += 64) {
       const uint32_t h = h0 + lane;
       int x = h < run ? (int)holes[h] : 0;

@@ -29,6 +29,10 @@
 // issues at the same per-SIMD rate as the vector ALU, so exec-mask juggling
 // costs as much as arithmetic.
 //
+// Wave priorities step down through a row: loads 3, scatter 2, resolve 1,
+// fill 0.  A workgroup that starts a row gets its memory requests out
+// first; the later phases, which wait only on LDS, fill the issue gaps.
+//
 // HBM traffic per target pixel: 4 B depth + 4 B RGBA read, 4 B RGBA written
 // (+4 B depth, +1 B mask when asked for).
 #include "row_common.h"
@@ -86,6 +90,7 @@ __device__ __forceinline__ void warp_fill_row(const DevJob& J, int y, const RowI
     reinterpret_cast<ulonglong2*>(s.key)[e] = make_ulonglong2(kEmpty, kEmpty);
   __syncthreads();
 
+  __builtin_amdgcn_s_setprio(2);
   // B: scatter with the depth test.  Lanes with nothing to splat (no
   // geometry, a shift of a full row or more, a target off the row, a column
   // past the row's end) hit their own sink slot instead of branching.
@@ -106,6 +111,7 @@ __device__ __forceinline__ void warp_fill_row(const DevJob& J, int y, const RowI
   }
   __syncthreads();
 
+  __builtin_amdgcn_s_setprio(1);
   resolve_fill_row<PPT>(s, W, target_right, fill, [&](int x, uint32_t c, uint32_t zb, uint8_t mk) {
     orow[x] = c;
     if (zrow) zrow[x] = __uint_as_float(zb);
@@ -123,7 +129,9 @@ __global__ __launch_bounds__(kThreads) void warp_single_kernel(DevJob J, int wl)
   for (; y < J.height; y += gridDim.x) {
     const RowIn<PPT> cur = in;
     const int yn = y + gridDim.x;
+    __builtin_amdgcn_s_setprio(3);
     if (yn < J.height) load_row<PPT>(J, yn, in);
+    __builtin_amdgcn_s_setprio(0);
     warp_fill_row<PPT, true>(J, y, cur, smem, wl);
   }
 }
@@ -147,7 +155,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
     j = job_of(r, j);
     const DevJob J = jobs[j];
     RowIn<PPT> cur;
+    __builtin_amdgcn_s_setprio(3);
     if (J.width <= wl) load_row<PPT>(J, (int)(r - J.row_start), cur);
+    __builtin_amdgcn_s_setprio(0);
     if (J.width <= wl) {
       if (J.dst_depth || J.dst_mask)
         warp_fill_row<PPT, true>(J, (int)(r - J.row_start), cur, smem, wl);
