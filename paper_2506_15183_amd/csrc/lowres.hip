@@ -219,9 +219,16 @@ __device__ __forceinline__ void lowres_units(const DevJob& one, const BatchHeade
       if (BATCH && threadIdx.x == 0) atomicAdd(&const_cast<BatchHeader*>(hdr)->errors, (uint32_t)(y1 - y0));
       continue;
     }
+    // Wave priorities: the texel row's loads and scatter first (3), the
+    // gathers of the unit's rows next (2), the map's resolve last (1; its
+    // fill runs at 0), so a unit's memory requests leave early.
+    __builtin_amdgcn_s_setprio(3);
     scatter_texel_row(J, j, g.lg, tk);
+    __builtin_amdgcn_s_setprio(1);
     block_map<PPT>(J, g.lg, g.linear != 0, tk, s);
+    __builtin_amdgcn_s_setprio(2);
     block_rows<PPT>(J, y0, y1, s);
+    __builtin_amdgcn_s_setprio(0);
   }
 }
 
