@@ -34,8 +34,12 @@
  *   yoro_last_error() returns this thread's message for the last non-OK
  *   status.  No C++ exception crosses this interface.
  * - Determinism: collisions are resolved by a 64-bit atomicMin on
- *   (depth bits << 32 | source column); equal depths in one row never
- *   collide, so every output bit is independent of thread order.
+ *   (depth bits << 32 | source RGBA word).  Two sources of one row with
+ *   bitwise-equal depth have equal disparity and so never reach the same
+ *   target column: every collision is decided by the depth bits alone, the
+ *   low word only carries the winner's colour, and every output bit is
+ *   independent of thread order.  (The general-pose call, whose depth test
+ *   spans the frame, keys on (target depth bits << 32 | source index).)
  */
 #ifndef YORO_H
 #define YORO_H
@@ -71,7 +75,8 @@ typedef enum yoro_fill_mode {
   YORO_FILL_NEAREST_BG = 1,
   /* The weighted Patcher (Section 7, Algorithm 3 with Equation 7): from the
    * nearest-background hit e of a hole at x (chosen as above, nearest hits L
-   * and R), samples outward from e over min(R - L - 1, 16) columns and rows
+   * and R), samples outward from e over R - L - 1 columns (the
+   * disocclusion's width, no cap; stopping at the frame's edge) and rows
    * y, y-1, y+1 that are hits not nearer than e; each takes
    * w_rem/2 + 0.3 w_rem |x - e| / (R - L - 1) of the remaining weight w_rem
    * (starting at 1); the hole gets rint(sum(C w) / (1 - w_rem)) per RGB

@@ -45,10 +45,11 @@
  *   hole at (x, y) with nearest row hits L and R (as above, L = -1 or R = W
  *   when absent) the kernel starts at the nearest-background hit e chosen as
  *   above, with depth ze, and runs outward from the hole, away from it, over
- *   n = min(R - L - 1, 16) columns (the disocclusion width, capped; past 16
- *   accepted samples the remaining weight is below 2^-16) and, per column,
- *   rows y, y - 1, y + 1.  A sample is used only if it lies in the frame, is
- *   a hit (mask 0, never a filled hole) and is not nearer than the edge
+ *   n = R - L - 1 columns (the kernel is as wide as the disocclusion in the
+ *   hole's row, Section 7, text before Equation 7; no cap), stopping at the
+ *   frame's edge, and, per column, rows y, y - 1, y + 1 (h = 3).  A sample
+ *   is used only if it lies in the frame, is a hit (mask 0, never a filled
+ *   hole) and is not nearer than the edge
  *   (depth >= ze: the foreground skip).  With t = |x - e| / (R - L - 1),
  *   the position in the disocclusion (u - r_x) / r_z measured from the
  *   background edge (in the paper's own orientation, the left eye made
@@ -80,7 +81,6 @@
 
 enum { OR_TARGET_RIGHT = 0, OR_TARGET_LEFT = 1 };
 enum { OR_FILL_NONE = 0, OR_FILL_NEAREST_BG = 1, OR_FILL_PATCHER = 3, OR_FILL_SIDE_ONLY = 101 };
-#define OR_PATCH_MAX_COLS 16
 
 #define OR_EMPTY 0xFFFFFFFFFFFFFFFFull
 
@@ -169,7 +169,7 @@ static void patcher_pixel(const uint8_t* rgba, const float* depth, const uint8_t
   const int32_t rz = R - L - 1;
   const float t = (float)abs(x - e) / (float)rz;
   const int32_t dir = (e == R) ? 1 : -1;
-  const int32_t n = rz < OR_PATCH_MAX_COLS ? rz : OR_PATCH_MAX_COLS;
+  const int32_t n = rz; /* the disocclusion's width */
   static const int32_t dys[3] = {0, -1, 1};
   float w_rem = 1.0f, acc[3] = {0.0f, 0.0f, 0.0f};
   for (int32_t k = 0; k < n; ++k) {

@@ -223,15 +223,21 @@ __global__ __launch_bounds__(kThreads) void fill_kernel(uint32_t* rgba, float* d
 // weight function of Equation 7).  For a hole at (x, y): the nearest hits L
 // and R of its row and the nearest-background edge e among them (as in the
 // plain fill), then samples outward from e, away from the hole, over
-// n = min(R - L - 1, kPatchCols) columns and rows y, y - 1, y + 1; a sample
-// counts if it is a hit not nearer than the edge.  Each counted sample takes
+// n = R - L - 1 columns (the kernel is as wide as the disocclusion) and rows
+// y, y - 1, y + 1; a sample counts if it is a hit not nearer than the edge.
+// Each counted sample takes
 // w = w_rem/2 + 0.3 w_rem t of the remaining weight, t = |x - e| / (R - L - 1)
 // the hole's position measured from the edge, and the hole becomes
 // rint(sum(C w) / (1 - w_rem)) per channel, with the edge's alpha and depth.
 // FP32 in exactly that order (the arithmetic decides 8-bit values).  Row y
 // is staged in LDS; rows y +- 1 are read from memory, hits only (a hole's
-// mask stays nonzero when it is filled, so in place is safe).
-constexpr int kPatchCols = 16;
+// mask stays nonzero when it is filled, so in place is safe).  The walk stops
+// early at the first counted sample whose weight rounds to exactly zero (the
+// remaining weight shrinks by a factor in [0.2, 0.5] per counted sample, down
+// through the subnormals, which this code keeps, so this happens within about
+// 150 counted samples): a zero weight leaves w_rem unchanged, so every later
+// weight is zero as well and adds exactly nothing; the sums and the result
+// are those of the full-width walk, bit for bit.
 
 template <int PPT>
 __global__ __launch_bounds__(kThreads) void patcher_kernel(uint32_t* rgba, float* depth, uint8_t* mask, int W, int H,
@@ -280,9 +286,10 @@ __global__ __launch_bounds__(kThreads) void patcher_kernel(uint32_t* rgba, float
         const int rz = R - L - 1;
         const float t = (float)abs(x - e) / (float)rz;
         const int dir = e == R ? 1 : -1;
-        const int n = rz < kPatchCols ? rz : kPatchCols;
+        const int n = rz;
         float w_rem = 1.0f, a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
-        for (int k = 0; k < n; ++k) {
+        bool spent = false;  // a counted sample had weight exactly zero
+        for (int k = 0; k < n && !spent; ++k) {
           const int cx = e + dir * k;
           if (cx < 0 || cx >= W) break;
           for (int j = 0; j < 3; ++j) {
@@ -304,6 +311,10 @@ __global__ __launch_bounds__(kThreads) void patcher_kernel(uint32_t* rgba, float
             const float wa = w_rem * 0.5f;
             const float wb = 0.3f * w_rem;
             const float w = wa + wb * t;
+            if (w == 0.0f) {
+              spent = true;
+              break;
+            }
             a0 = a0 + (float)(c & 255u) * w;
             a1 = a1 + (float)((c >> 8) & 255u) * w;
             a2 = a2 + (float)((c >> 16) & 255u) * w;

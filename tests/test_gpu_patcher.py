@@ -1,8 +1,8 @@
 """GPU parity of the Patcher fill (YORO_FILL_PATCHER) against the oracle,
 bit-exact: through yoro_reproject (warp, then the Patcher) and through
 yoro_fill_holes in place, on ray-cast scenes, random frames with forced
-collisions and ragged widths, both eyes, and the hand-worked rows of the
-oracle's pins."""
+collisions and ragged widths, rows with disocclusions hundreds of columns
+wide, both eyes, and the hand-worked rows of the oracle's pins."""
 from __future__ import annotations
 
 import numpy as np
@@ -91,6 +91,54 @@ def test_fill_in_place_matches_oracle(cuda):
     mask = np.array([[0, 1, 1, 0, 0, 0]], np.uint8)
     out = run_fill(rgba, depth, mask, R)[0]
     assert out[0, 1, 0] == 183 and out[0, 2, 0] == 174
+
+
+def _wide_runs(seed, W, H, max_run):
+    """Rows with wide disocclusions (runs of up to max_run columns) over a
+    few depth levels, so kernels span hundreds of columns, skip foreground
+    samples and run their weights down to zero."""
+    rng = np.random.default_rng(seed)
+    rgba = rng.integers(0, 256, size=(H, W, 4), dtype=np.uint8)
+    depth = np.array([1.0, 4.0, 20.0], np.float32)[rng.integers(0, 3, size=(H, W))]
+    mask = np.zeros((H, W), np.uint8)
+    for y in range(H):
+        x = int(rng.integers(0, 8))
+        while x < W:
+            run = int(rng.integers(1, max_run))
+            mask[y, x:x + run] = 1
+            x += run + int(rng.integers(1, 40))
+    rgba[mask != 0] = 0
+    depth[mask != 0] = np.inf
+    return rgba, depth, mask
+
+
+@pytest.mark.parametrize("W", [300, 2160])
+def test_wide_disocclusions(cuda, W):
+    # The kernel is as wide as the disocclusion (Section 7): runs of up to
+    # several hundred columns, both eyes, in place.
+    for seed, max_run in ((1, 64), (2, 400)):
+        rows = _wide_runs(seed + W, W, 12, max_run)
+        for eye in (R, L):
+            assert_same(run_fill(*rows, eye), orc.fill_holes(*rows, eye, orc.FILL_PATCHER),
+                        f"W={W} max_run={max_run} eye={eye}")
+    # The closed-form rows of the oracle's pins: a lone background sample
+    # 250 columns past the edge of a 300-pixel hole still counts.
+    Wc = 600
+    cols = np.full(Wc, 100, np.uint8)
+    depths = np.full(Wc, 2.0, np.float32)
+    mk = np.zeros(Wc, np.uint8)
+    cols[0], depths[0] = 50, 1.0
+    mk[1:301] = 1
+    depths[301], cols[301] = 10.0, 200
+    depths[551], cols[551] = 10.0, 0
+    rgba = np.repeat(cols[None, :, None], 4, axis=-1)
+    rgba[..., 3] = 255
+    rgba[0, 1:301] = 0
+    depths[1:301] = np.inf
+    rows = (rgba, depths[None].copy(), mk[None].copy())
+    g = run_fill(*rows, R)
+    assert_same(g, orc.fill_holes(*rows, R, orc.FILL_PATCHER), "closed-form row")
+    assert (g[0][0, 1:301, 0] < 200).all()
 
 
 def test_argument_checks(cuda):

@@ -2,7 +2,8 @@
 function of Equation 7, under the readings stated in oracle/reproject.c):
 closed forms on hand-built rows, the foreground skip, the neighbouring rows,
 agreement with the nearest-background fill on everything but the colour,
-and mirror symmetry between the eyes."""
+mirror symmetry between the eyes, and a kernel as wide as the
+disocclusion (no cap on its width)."""
 from __future__ import annotations
 
 import numpy as np
@@ -54,15 +55,20 @@ def test_foreground_samples_are_skipped():
     assert out[0, 1, 0] == 200 and out[0, 2, 0] == 200
 
 
-def test_kernel_width_follows_the_disocclusion_and_is_capped():
+def test_kernel_width_is_the_disocclusion_width():
+    # Section 7: the kernel is as wide as the disocclusion in the hole's row.
     # One-pixel hole: the kernel is one column wide, so the far sample (40)
     # never counts.
     rgba, depth, mask = frame([50, 0, 200, 40], [1.0, np.inf, 10.0, 10.0], [0, 1, 0, 0])
     assert patch(rgba, depth, mask)[0][0, 1, 0] == 200
-    # A 20-pixel hole reaches 16 columns at most.  Past the edge every column
-    # is foreground (skipped) except one background sample: at edge + 15 it
-    # is inside the kernel and changes the fill, at edge + 16 it is not.
-    W = 40
+    # A 20-pixel hole (columns 1..20) whose background edge is column 21:
+    # every column past the edge is foreground (depth 2, skipped) except one
+    # background sample of level 0 at edge + k.  The kernel spans columns
+    # edge .. edge + 19, so for k <= 19 the hole at distance dist from the
+    # edge is the closed form 200 f / (f + (1 - f) f) = 200 / (2 - f) with
+    # f = 0.5 + 0.3 dist / 20, and for k = 20 the sample is outside the
+    # kernel and the fill is the edge alone.
+    W = 64
     edge = 21
 
     def run(bg_col):
@@ -75,8 +81,64 @@ def test_kernel_width_follows_the_disocclusion_and_is_capped():
         depths[bg_col], cols[bg_col] = 10.0, 0
         return patch(*frame(cols, depths, mk))[0][0, 1:21, 0]
 
-    assert (run(edge + 16) == 200).all()
-    assert (run(edge + 15) < 200).all()
+    dist = edge - np.arange(1, 21)
+    want = np.array([np.round(200.0 / (2.0 - (0.5 + 0.3 * d / 20.0))) for d in dist])
+    for k in (1, 15, 16, 19):
+        assert np.array_equal(run(edge + k), want), k
+    assert (run(edge + 20) == 200).all()
+    assert (want < 200).all() and (want != want[0]).any()
+
+
+def test_wide_disocclusion_reaches_far_samples():
+    # A 300-pixel hole: a lone background sample 250 columns past the edge
+    # is still inside the kernel, and the closed form above holds with
+    # t = dist / 300 (the FP32 arithmetic can move a value by at most one
+    # level against the real-valued closed form, at exact halves).
+    W = 600
+    cols = np.full(W, 100)
+    depths = np.full(W, 2.0, np.float32)
+    mk = np.zeros(W, np.uint8)
+    cols[0], depths[0] = 50, 1.0
+    mk[1:301] = 1
+    edge = 301
+    depths[edge], cols[edge] = 10.0, 200
+    depths[edge + 250], cols[edge + 250] = 10.0, 0
+    got = patch(*frame(cols, depths, mk))[0][0, 1:301, 0].astype(int)
+    dist = edge - np.arange(1, 301)
+    exact = 200.0 / (2.0 - (0.5 + 0.3 * dist / 300.0))
+    assert np.abs(got - exact).max() <= 0.5 + 1e-4
+    assert (got < 200).all()
+
+
+def test_deep_kernel_weights_underflow_to_exact_zero():
+    # A 400-pixel hole over a background whose rows y, y - 1, y + 1 are all
+    # hits: the remaining weight shrinks by a factor in [0.2, 0.5] per
+    # accepted sample, into the subnormals, until a sample's weight rounds to
+    # exactly zero, after which every further weight is zero.  Levels 255 / 0
+    # in alternating columns give a geometric series with a closed form.
+    W, H = 900, 3
+    cols = np.zeros((H, W), np.int64)
+    cols[:, ::2] = 255
+    depths = np.full((H, W), 10.0, np.float32)
+    mk = np.zeros((H, W), np.uint8)
+    mk[1, 0:400] = 1                  # hole run at the row's start: edge is R = 400
+    rgba, depth, mask = frame(cols, depths, mk)
+    rgba[1, 0:400] = 0
+    out, z, m = patch(rgba, depth, mask)
+    assert (m[1, :400] == 1).all() and (z[1, :400] == 10.0).all()
+    # The edge column 400 holds 255 in all three rows; the next columns
+    # alternate.  With f = 0.5 + 0.3 t the weights of the first three
+    # samples (all 255) sum to 1 - (1 - f)^3, and the next three (0) only
+    # add to the normaliser.  Check the leading terms against the closed
+    # form of the infinite sum, which the FP32 loop reaches to within one
+    # level.
+    for x in (0, 100, 399):
+        t = (400 - x) / 400.0
+        r = 1.0 - (0.5 + 0.3 * t)      # w_rem factor per accepted sample
+        # level 255 on columns 400, 402, ... (3 samples per column), 0 between:
+        # sum over column pairs of r^(6p) (1 - r^3) 255, normalised by 1.
+        exact = 255.0 * (1.0 - r ** 3) / (1.0 - r ** 6)
+        assert abs(int(out[1, x, 0]) - exact) <= 0.5 + 1e-3, (x, out[1, x, 0], exact)
 
 
 def test_uniform_background_is_reproduced_exactly():
