@@ -67,8 +67,8 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2506_15183_amd import yoro
-    from paper_2506_15183_amd.scenes import config2_frame, config3_frames
+    from paper_2506_15183_amd import workloads, yoro
+    from paper_2506_15183_amd.scenes import config2_frame
 
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
@@ -77,15 +77,10 @@ def main():
 
     # ---------------------------------------------------------------- inputs
     t0 = time.time()
-    specs = config3_frames()
-    frames = [s.render_source() for s in specs]
+    wl = workloads.rgba_only_batch(dev)
+    specs, frames, src, dst, batch = wl.specs, wl.frames, wl.src, wl.dst, wl.batch
     log(f"rendered {len(specs)} frames in {time.time() - t0:.1f}s")
-    pixels = sum(s.pixels for s in specs)
-    src = [(torch.from_numpy(r).to(dev), torch.from_numpy(d).to(dev)) for r, d in frames]
-    dst = [torch.empty((s.height, s.width, 4), dtype=torch.uint8, device=dev) for s in specs]
-    jobs = [yoro.make_job(a, b, o, None, None, s.baseline_m, s.focal_px, s.target_eye, yoro.FILL_NEAREST_BG)
-            for s, (a, b), o in zip(specs, src, dst)]
-    batch = yoro.StereoBatch(jobs, device=dev)
+    pixels = wl.pixels
     stream = torch.cuda.Stream(device=dev)
     with torch.cuda.stream(stream):
         batch.prepare(stream=stream)

@@ -256,6 +256,46 @@ def test_batch_graph_replay_and_order_independence(cuda):
             assert_same(tuple(x.cpu().numpy() for x in d[2:]), w, f"replay {rep}")
 
 
+def test_timed_batch_configuration_matches_oracle(cuda):
+    """The configuration the benchmark times, built by the same function:
+    the 64-frame batch with RGBA output only (no depth or mask, which selects
+    the row code without extra outputs), the table upload and the launch
+    captured into a HIP graph, replayed three times; and the launch alone
+    captured, as the benchmark replays it.  Every frame's RGBA, byte for
+    byte, against the oracle."""
+    torch, yoro = _gpu()
+    from paper_2506_15183_amd import workloads
+
+    wl = workloads.rgba_only_batch(torch.device("cuda:0"))
+    want = [orc.reproject(r, d, s.baseline_m, s.focal_px, s.target_eye, orc.FILL_NEAREST_BG, nthreads=0)[0]
+            for s, (r, d) in zip(wl.specs, wl.frames)]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        wl.batch.prepare(stream=s)
+        wl.batch.launch(stream=s)
+    torch.cuda.synchronize()
+    assert wl.batch.errors() == 0
+    for k, (spec, w, o) in enumerate(zip(wl.specs, want, wl.dst)):
+        assert np.array_equal(o.cpu().numpy(), w), f"eager frame {k} {spec.width}x{spec.height}"
+    full, launch_only = torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(full, stream=s):
+            wl.batch.prepare(stream=s)
+            wl.batch.launch(stream=s)
+        with torch.cuda.graph(launch_only, stream=s):
+            wl.batch.launch(stream=s)
+    torch.cuda.synchronize()
+    for rep, g in enumerate((full, full, full, launch_only, launch_only)):
+        for o in wl.dst:
+            o.fill_(0x5A)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for k, (spec, w, o) in enumerate(zip(wl.specs, want, wl.dst)):
+            assert np.array_equal(o.cpu().numpy(), w), f"replay {rep} frame {k} {spec.width}x{spec.height}"
+    assert wl.batch.errors() == 0
+
+
 def test_batch_too_narrow_launch_counts_skipped_rows(cuda):
     torch, yoro = _gpu()
     specs = config3_frames(n_per_size=1)
