@@ -73,6 +73,14 @@ typedef enum yoro_fill_mode {
    * YORO_TARGET_LEFT); with one neighbour take it (Section 5 O2; Section 7,
    * Patcher figure). */
   YORO_FILL_NEAREST_BG = 1,
+  /* Learned fill: the nearest-background fill above, then the learned
+   * filler of yoro_model.h refines the hole pixels (mask != 0) of the whole
+   * frame (non-hole pixels are left bit for bit).  Section 7 sets
+   * data-driven inpainting aside as too heavy for a phone; the network is
+   * this library's extension.  Needs a yoro_model, so only yoro_fill_holes
+   * and yoro_stereo_batch take it (elsewhere YORO_ERR_UNSUPPORTED), and only
+   * for frames whose width and height are multiples of 8. */
+  YORO_FILL_LEARNED = 2,
   /* The weighted Patcher (Section 7, Algorithm 3 with Equation 7): from the
    * nearest-background hit e of a hole at x (chosen as above, nearest hits L
    * and R), samples outward from e over R - L - 1 columns (the
@@ -85,6 +93,21 @@ typedef enum yoro_fill_mode {
    * call does not take it (YORO_ERR_UNSUPPORTED). */
   YORO_FILL_PATCHER = 3
 } yoro_fill_mode;
+
+/*
+ * The learned filler as the fill calls take it.  weights: device, the bf16
+ * model weights of yoro_model.h (yoro_model_weights_bytes(), 16-byte
+ * aligned).  workspace: device, 16-byte aligned, at least
+ * yoro_model_workspace_bytes(1, h, w) bytes for the largest frame it fills
+ * (the network's activations; overwritten by every learned fill, so calls
+ * that share one workspace must be ordered on one stream).  Caller-owned;
+ * the library only reads the struct during the call.
+ */
+typedef struct yoro_model {
+  const void* weights;
+  void* workspace;
+  size_t workspace_bytes;
+} yoro_model;
 
 typedef enum yoro_status {
   YORO_OK = 0,
@@ -119,11 +142,15 @@ int32_t yoro_reproject(const uint8_t* src_rgba, const float* src_depth, int32_t 
  * yoro_fill_holes -- fill the disocclusions of an already warped frame in
  * place (Section 7; Section 5 O2).  Pixels with mask == 0 are hits and are
  * left unchanged; every other pixel is a hole and is refilled per fill_mode
- * from the hits of its row only (so the result does not depend on order).
- * rgba, depth, mask: in/out, all required.  YORO_FILL_NONE is a no-op.
+ * from the hits of its row only (so the result does not depend on order),
+ * and with YORO_FILL_LEARNED then refined by the network, which reads the
+ * whole plain-filled frame.  rgba, depth, mask: in/out, all required.
+ * model: required for YORO_FILL_LEARNED (YORO_ERR_INVALID_ARG if NULL,
+ * YORO_ERR_WORKSPACE_TOO_SMALL if its workspace is short), ignored
+ * otherwise.  YORO_FILL_NONE is a no-op.
  */
 int32_t yoro_fill_holes(uint8_t* rgba, float* depth, uint8_t* mask, int32_t width, int32_t height,
-                        int32_t target_eye, int32_t fill_mode, void* hip_stream);
+                        int32_t target_eye, int32_t fill_mode, const yoro_model* model, void* hip_stream);
 
 /*
  * Batched stereo synthesis: many frames of mixed sizes in one persistent
@@ -156,7 +183,9 @@ size_t yoro_stereo_batch_workspace_bytes(int32_t n_jobs);
  * dev_workspace (device memory, >= yoro_stereo_batch_workspace_bytes,
  * 16-byte aligned) on hip_stream.  The upload is done by small kernels that
  * carry the table in their arguments, so jobs_host may be freed on return
- * and the call may be captured into a HIP graph.
+ * and the call may be captured into a HIP graph.  YORO_FILL_LEARNED jobs
+ * need the model and so go through yoro_stereo_batch
+ * (YORO_ERR_UNSUPPORTED here).
  */
 int32_t yoro_stereo_batch_prepare(const yoro_job* jobs_host, int32_t n_jobs, void* dev_workspace,
                                   size_t workspace_bytes, void* hip_stream);
@@ -170,13 +199,24 @@ int32_t yoro_stereo_batch_prepare(const yoro_job* jobs_host, int32_t n_jobs, voi
  */
 int32_t yoro_stereo_batch_launch(const void* dev_workspace, int32_t max_width, void* hip_stream);
 
-/* prepare + launch. */
+/*
+ * yoro_stereo_batch -- prepare + launch, then the learned fill of the jobs
+ * whose fill_mode is YORO_FILL_LEARNED.  Those jobs are warped with the
+ * nearest-background fill in the batched launch, so plain and learned jobs
+ * share it; each learned job then runs yoro_fill_holes's network pass on
+ * its output, in job order on hip_stream.  A learned job needs dst_depth
+ * and dst_mask (the network's inputs) and width and height that are
+ * multiples of 8; model is required when any job is learned (its
+ * workspace sized for the largest learned job) and ignored otherwise.
+ * Capture-safe like prepare and launch.
+ */
 int32_t yoro_stereo_batch(const yoro_job* jobs_host, int32_t n_jobs, void* dev_workspace,
-                          size_t workspace_bytes, void* hip_stream);
+                          size_t workspace_bytes, const yoro_model* model, void* hip_stream);
 
 /* Device address of the workspace's u32 error counter (rows skipped by the
  * last launch because max_width was too small); reset by prepare. */
 const uint32_t* yoro_stereo_batch_errors(const void* dev_workspace);
+
 
 /*
  * yoro_reproject_lowres -- yoro_reproject through a downsampled intermediate

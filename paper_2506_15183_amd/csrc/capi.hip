@@ -13,6 +13,7 @@
 
 #include "yoro.h"
 #include "yoro_internal.h"
+#include "yoro_model.h"
 
 namespace {
 
@@ -86,6 +87,18 @@ int scale_log2(int32_t scale) {
 
 bool aligned4(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }
 
+bool known_mode(int32_t m) {
+  return m == YORO_FILL_NONE || m == YORO_FILL_NEAREST_BG || m == YORO_FILL_LEARNED || m == YORO_FILL_PATCHER;
+}
+
+// The entry points without a model argument cannot run the learned fill.
+int32_t reject_learned(int32_t fill_mode, const char* who) {
+  if (fill_mode == YORO_FILL_LEARNED)
+    return fail(YORO_ERR_UNSUPPORTED, "%s: the learned fill needs a model; use yoro_fill_holes or yoro_stereo_batch",
+                who);
+  return YORO_OK;
+}
+
 struct Range {
   uintptr_t lo, hi;  // [lo, hi)
   bool out;
@@ -108,8 +121,7 @@ int32_t check_frame(const void* src_rgba, const void* src_depth, int32_t width, 
                 (double)baseline_m, (double)focal_px);
   if (target_eye != YORO_TARGET_RIGHT && target_eye != YORO_TARGET_LEFT)
     return fail(YORO_ERR_INVALID_ARG, "%s: unknown target eye %d", who, target_eye);
-  if (fill_mode != YORO_FILL_NONE && fill_mode != YORO_FILL_NEAREST_BG && fill_mode != YORO_FILL_PATCHER)
-    return fail(YORO_ERR_INVALID_ARG, "%s: unknown fill mode %d", who, fill_mode);
+  if (!known_mode(fill_mode)) return fail(YORO_ERR_INVALID_ARG, "%s: unknown fill mode %d", who, fill_mode);
   if (!aligned4(src_rgba) || !aligned4(src_depth) || !aligned4(dst_rgba) || (dst_depth && !aligned4(dst_depth)))
     return fail(YORO_ERR_INVALID_ARG, "%s: RGBA and depth pointers must be 4-byte aligned", who);
   const uintptr_t n = (uintptr_t)width * (uintptr_t)height;
@@ -122,6 +134,30 @@ int32_t check_frame(const void* src_rgba, const void* src_depth, int32_t width, 
     for (size_t j = i + 1; j < r.size(); ++j)
       if ((r[i].out || r[j].out) && overlaps(r[i], r[j]))
         return fail(YORO_ERR_INVALID_ARG, "%s: an output buffer overlaps another buffer", who);
+  return YORO_OK;
+}
+
+// A model for the learned fill of frames up to w x h: weights and workspace
+// present and 16-byte aligned, sizes multiples of 8, the workspace large
+// enough and clear of every buffer in `frames`.
+int32_t check_model(const yoro_model* m, int32_t w, int32_t h, const std::vector<Range>& frames, const char* who) {
+  if (!m || !m->weights || !m->workspace)
+    return fail(YORO_ERR_INVALID_ARG, "%s: the learned fill needs a model with weights and a workspace", who);
+  if ((reinterpret_cast<uintptr_t>(m->weights) & 15u) || (reinterpret_cast<uintptr_t>(m->workspace) & 15u))
+    return fail(YORO_ERR_INVALID_ARG, "%s: model weights and workspace must be 16-byte aligned", who);
+  if (w % 8 || h % 8)
+    return fail(YORO_ERR_UNSUPPORTED, "%s: the learned fill needs width and height multiples of 8 (got %dx%d)", who,
+                w, h);
+  const size_t need = yoro_model_workspace_bytes(1, h, w);
+  if (need == 0) return fail(YORO_ERR_UNSUPPORTED, "%s: frame %dx%d too large for the learned fill", who, w, h);
+  if (m->workspace_bytes < need)
+    return fail(YORO_ERR_WORKSPACE_TOO_SMALL, "%s: model workspace %zu < %zu bytes", who, m->workspace_bytes, need);
+  const Range ws{(uintptr_t)m->workspace, (uintptr_t)m->workspace + m->workspace_bytes, true};
+  const Range wt{(uintptr_t)m->weights, (uintptr_t)m->weights + yoro_model_weights_bytes(), false};
+  if (overlaps(ws, wt)) return fail(YORO_ERR_INVALID_ARG, "%s: the model workspace overlaps its weights", who);
+  for (const Range& r : frames)
+    if (r.hi > r.lo && (overlaps(ws, r) || (r.out && overlaps(wt, r))))
+      return fail(YORO_ERR_INVALID_ARG, "%s: the model's buffers overlap a frame buffer", who);
   return YORO_OK;
 }
 
@@ -150,6 +186,107 @@ int grid_for(int rows, int blocks_per_cu) {
   return (int)std::max<long long>(1, std::min<long long>(rows, g));
 }
 
+// yoro_stereo_batch_prepare, and the first half of yoro_stereo_batch, which
+// alone accepts learned jobs (it has the model).  queue = false only checks.
+int32_t prepare_batch(const yoro_job* jobs, int32_t n_jobs, void* dev_workspace, size_t workspace_bytes,
+                      void* hip_stream, bool allow_learned, bool queue = true) {
+  try {
+    if (!jobs || n_jobs <= 0 || n_jobs > YORO_MAX_BATCH_JOBS)
+      return fail(YORO_ERR_INVALID_ARG, "yoro_stereo_batch_prepare: need 1..%d jobs", YORO_MAX_BATCH_JOBS);
+    if (!dev_workspace || (reinterpret_cast<uintptr_t>(dev_workspace) & 15u))
+      return fail(YORO_ERR_INVALID_ARG, "yoro_stereo_batch_prepare: workspace must be non-null and 16-byte aligned");
+    if (workspace_bytes < yoro_stereo_batch_workspace_bytes(n_jobs))
+      return fail(YORO_ERR_WORKSPACE_TOO_SMALL, "yoro_stereo_batch_prepare: workspace %zu < %zu bytes",
+                  workspace_bytes, yoro_stereo_batch_workspace_bytes(n_jobs));
+    std::vector<Range> ranges;
+    ranges.reserve((size_t)n_jobs * 5);
+    uint64_t rows = 0;
+    int32_t max_w = 0;
+    for (int32_t i = 0; i < n_jobs; ++i) {
+      const yoro_job& j = jobs[i];
+      char who[64];
+      snprintf(who, sizeof(who), "yoro_stereo_batch_prepare: job %d", i);
+      int32_t st = check_frame(j.src_rgba, j.src_depth, j.width, j.height, j.baseline_m, j.focal_px, j.target_eye,
+                               j.fill_mode, j.dst_rgba, j.dst_depth, j.dst_mask, who);
+      if (st != YORO_OK) return st;
+      if (j.fill_mode == YORO_FILL_PATCHER)
+        return fail(YORO_ERR_UNSUPPORTED, "%s: the Patcher fill reads neighbouring rows; use yoro_reproject", who);
+      if (j.fill_mode == YORO_FILL_LEARNED && !allow_learned)
+        return fail(YORO_ERR_UNSUPPORTED, "%s: the learned fill needs a model; use yoro_stereo_batch", who);
+      const uintptr_t n = (uintptr_t)j.width * (uintptr_t)j.height;
+      ranges.push_back({(uintptr_t)j.src_rgba, (uintptr_t)j.src_rgba + 4 * n, false});
+      ranges.push_back({(uintptr_t)j.src_depth, (uintptr_t)j.src_depth + 4 * n, false});
+      ranges.push_back({(uintptr_t)j.dst_rgba, (uintptr_t)j.dst_rgba + 4 * n, true});
+      if (j.dst_depth) ranges.push_back({(uintptr_t)j.dst_depth, (uintptr_t)j.dst_depth + 4 * n, true});
+      if (j.dst_mask) ranges.push_back({(uintptr_t)j.dst_mask, (uintptr_t)j.dst_mask + n, true});
+      rows += (uint64_t)j.height;
+      max_w = std::max(max_w, j.width);
+    }
+    if (rows > 0xFFFFFFFFull) return fail(YORO_ERR_UNSUPPORTED, "yoro_stereo_batch_prepare: too many rows");
+    // No output may overlap anything else: sort by start; an output must not
+    // overlap its sorted neighbours' spans (track the furthest end so far).
+    std::sort(ranges.begin(), ranges.end(), [](const Range& a, const Range& b) { return a.lo < b.lo; });
+    uintptr_t far_hi = 0;
+    bool far_out = false;
+    for (size_t i = 0; i < ranges.size(); ++i) {
+      if (i > 0 && ranges[i].lo < far_hi && (ranges[i].out || far_out))
+        return fail(YORO_ERR_INVALID_ARG, "yoro_stereo_batch_prepare: an output buffer overlaps another buffer");
+      if (ranges[i].hi > far_hi) {
+        far_hi = ranges[i].hi;
+        far_out = ranges[i].out;
+      } else if (ranges[i].out) {
+        far_out = true;
+      }
+    }
+    if (!queue) return ok();
+    hipStream_t s = (hipStream_t)hip_stream;
+    auto* hdr = reinterpret_cast<yoro::BatchHeader*>(dev_workspace);
+    auto* dj = reinterpret_cast<yoro::DevJob*>(hdr + 1);
+    yoro::BatchHeader h{};
+    h.n_jobs = (uint32_t)n_jobs;
+    h.total_rows = (uint32_t)rows;
+    h.max_width = (uint32_t)max_w;
+    h.errors = 0;
+    hipError_t e = yoro::launch_header(h, hdr, s);
+    uint32_t row = 0;
+    for (int32_t first = 0; e == hipSuccess && first < n_jobs; first += yoro::kUploadChunk) {
+      yoro::UploadChunk c{};
+      c.first = (uint32_t)first;
+      c.count = (uint32_t)std::min(yoro::kUploadChunk, n_jobs - first);
+      for (uint32_t k = 0; k < c.count; ++k) {
+        c.jobs[k] = make_job(jobs[first + k], row);
+        row += (uint32_t)jobs[first + k].height;
+      }
+      e = yoro::launch_upload(c, dj, s);
+    }
+    if (e != hipSuccess)
+      return fail(YORO_ERR_DEVICE, "yoro_stereo_batch_prepare: upload failed: %s", hipGetErrorString(e));
+    return ok();
+  } catch (...) {
+    return fail(YORO_ERR_DEVICE, "yoro_stereo_batch_prepare: internal error");
+  }
+}
+
+int32_t launch_batch(const void* dev_workspace, int32_t max_width, void* hip_stream, const char* who) {
+  try {
+    if (!dev_workspace) return fail(YORO_ERR_INVALID_ARG, "%s: null workspace", who);
+    if (max_width <= 0 || max_width > YORO_MAX_WIDTH)
+      return fail(YORO_ERR_INVALID_ARG, "%s: max_width %d out of range", who, max_width);
+    const auto* hdr = reinterpret_cast<const yoro::BatchHeader*>(dev_workspace);
+    const auto* dj = reinterpret_cast<const yoro::DevJob*>(hdr + 1);
+    // Persistent grid: as many workgroups as fit on the chip at once.
+    DeviceFacts f;
+    const int cus = device_facts(&f) ? f.cus : 256;
+    const int grid = cus * yoro::warp_blocks_per_cu(max_width, true);
+    hipError_t e = yoro::launch_warp_batch(hdr, dj, max_width, grid, (hipStream_t)hip_stream);
+    if (e != hipSuccess)
+      return fail(YORO_ERR_DEVICE, "%s: launch failed: %s", who, hipGetErrorString(e));
+    return ok();
+  } catch (...) {
+    return fail(YORO_ERR_DEVICE, "%s: internal error", who);
+  }
+}
+
 }  // namespace
 
 namespace yoro {
@@ -168,6 +305,7 @@ int32_t yoro_reproject(const uint8_t* src_rgba, const float* src_depth, int32_t 
   try {
     int32_t st = check_frame(src_rgba, src_depth, width, height, baseline_m, focal_px, target_eye, fill_mode,
                              dst_rgba, dst_depth, dst_mask, "yoro_reproject");
+    if (st == YORO_OK) st = reject_learned(fill_mode, "yoro_reproject");
     if (st != YORO_OK) return st;
     const bool patcher = fill_mode == YORO_FILL_PATCHER;
     if (patcher && (!dst_depth || !dst_mask))
@@ -197,6 +335,7 @@ int32_t yoro_reproject_lowres(const uint8_t* src_rgba, const float* src_depth, i
   try {
     int32_t st = check_frame(src_rgba, src_depth, width, height, baseline_m, focal_px, target_eye, fill_mode,
                              dst_rgba, dst_depth, dst_mask, "yoro_reproject_lowres");
+    if (st == YORO_OK) st = reject_learned(fill_mode, "yoro_reproject_lowres");
     if (st != YORO_OK) return st;
     const int lg = scale_log2(scale);
     if (lg < 0) return fail(YORO_ERR_INVALID_ARG, "yoro_reproject_lowres: scale %d is not 1, 2, 4, 8 or 16", scale);
@@ -260,6 +399,7 @@ int32_t yoro_reproject_pose(const uint8_t* src_rgba, const float* src_depth, int
     // The frame checks of yoro_reproject (baseline and eye do not apply here).
     int32_t st = check_frame(src_rgba, src_depth, width, height, 1.0f, focal_px, YORO_TARGET_RIGHT, fill_mode,
                              dst_rgba, dst_depth, dst_mask, who);
+    if (st == YORO_OK) st = reject_learned(fill_mode, who);
     if (st != YORO_OK) return st;
     if (!std::isfinite(cx) || !std::isfinite(cy))
       return fail(YORO_ERR_INVALID_ARG, "%s: principal point (%g, %g) must be finite", who, (double)cx, (double)cy);
@@ -318,7 +458,7 @@ int32_t yoro_reproject_pose(const uint8_t* src_rgba, const float* src_depth, int
 }
 
 int32_t yoro_fill_holes(uint8_t* rgba, float* depth, uint8_t* mask, int32_t width, int32_t height,
-                        int32_t target_eye, int32_t fill_mode, void* hip_stream) {
+                        int32_t target_eye, int32_t fill_mode, const yoro_model* model, void* hip_stream) {
   try {
     if (!rgba || !depth || !mask) return fail(YORO_ERR_INVALID_ARG, "yoro_fill_holes: rgba, depth, mask required");
     if (width <= 0 || height <= 0)
@@ -327,8 +467,7 @@ int32_t yoro_fill_holes(uint8_t* rgba, float* depth, uint8_t* mask, int32_t widt
       return fail(YORO_ERR_UNSUPPORTED, "yoro_fill_holes: %dx%d exceeds the supported size", width, height);
     if (target_eye != YORO_TARGET_RIGHT && target_eye != YORO_TARGET_LEFT)
       return fail(YORO_ERR_INVALID_ARG, "yoro_fill_holes: unknown target eye %d", target_eye);
-    if (fill_mode != YORO_FILL_NONE && fill_mode != YORO_FILL_NEAREST_BG && fill_mode != YORO_FILL_PATCHER)
-      return fail(YORO_ERR_INVALID_ARG, "yoro_fill_holes: unknown fill mode %d", fill_mode);
+    if (!known_mode(fill_mode)) return fail(YORO_ERR_INVALID_ARG, "yoro_fill_holes: unknown fill mode %d", fill_mode);
     if (!aligned4(rgba) || !aligned4(depth))
       return fail(YORO_ERR_INVALID_ARG, "yoro_fill_holes: rgba and depth must be 4-byte aligned");
     const uintptr_t n = (uintptr_t)width * (uintptr_t)height;
@@ -336,12 +475,22 @@ int32_t yoro_fill_holes(uint8_t* rgba, float* depth, uint8_t* mask, int32_t widt
         c{(uintptr_t)mask, (uintptr_t)mask + n, true};
     if (overlaps(a, b) || overlaps(a, c) || overlaps(b, c))
       return fail(YORO_ERR_INVALID_ARG, "yoro_fill_holes: buffers overlap");
+    const bool learned = fill_mode == YORO_FILL_LEARNED;
+    if (learned) {
+      const int32_t st = check_model(model, width, height, {a, b, c}, "yoro_fill_holes");
+      if (st != YORO_OK) return st;
+    }
     if (fill_mode == YORO_FILL_NONE) return ok();
+    // The learned fill refines the plain nearest-background fill.
+    const int32_t row_mode = learned ? (int32_t)YORO_FILL_NEAREST_BG : fill_mode;
     const int ppt = pick_ppt(width);
-    const int grid = grid_for(height, yoro::fill_blocks_per_cu(width, fill_mode));
+    const int grid = grid_for(height, yoro::fill_blocks_per_cu(width, row_mode));
     hipError_t e = yoro::launch_fill(reinterpret_cast<uint32_t*>(rgba), depth, mask, width, height, target_eye,
-                                     fill_mode, ppt, grid, (hipStream_t)hip_stream);
+                                     row_mode, ppt, grid, (hipStream_t)hip_stream);
     if (e != hipSuccess) return fail(YORO_ERR_DEVICE, "yoro_fill_holes: launch failed: %s", hipGetErrorString(e));
+    if (learned)
+      return yoro_model_fill(model->weights, rgba, depth, mask, 1, height, width, rgba, model->workspace,
+                             model->workspace_bytes, hip_stream);
     return ok();
   } catch (...) {
     return fail(YORO_ERR_DEVICE, "yoro_fill_holes: internal error");
@@ -355,98 +504,11 @@ size_t yoro_stereo_batch_workspace_bytes(int32_t n_jobs) {
 
 int32_t yoro_stereo_batch_prepare(const yoro_job* jobs, int32_t n_jobs, void* dev_workspace, size_t workspace_bytes,
                                   void* hip_stream) {
-  try {
-    if (!jobs || n_jobs <= 0 || n_jobs > YORO_MAX_BATCH_JOBS)
-      return fail(YORO_ERR_INVALID_ARG, "yoro_stereo_batch_prepare: need 1..%d jobs", YORO_MAX_BATCH_JOBS);
-    if (!dev_workspace || (reinterpret_cast<uintptr_t>(dev_workspace) & 15u))
-      return fail(YORO_ERR_INVALID_ARG, "yoro_stereo_batch_prepare: workspace must be non-null and 16-byte aligned");
-    if (workspace_bytes < yoro_stereo_batch_workspace_bytes(n_jobs))
-      return fail(YORO_ERR_WORKSPACE_TOO_SMALL, "yoro_stereo_batch_prepare: workspace %zu < %zu bytes",
-                  workspace_bytes, yoro_stereo_batch_workspace_bytes(n_jobs));
-    std::vector<Range> ranges;
-    ranges.reserve((size_t)n_jobs * 5);
-    uint64_t rows = 0;
-    int32_t max_w = 0;
-    for (int32_t i = 0; i < n_jobs; ++i) {
-      const yoro_job& j = jobs[i];
-      char who[64];
-      snprintf(who, sizeof(who), "yoro_stereo_batch_prepare: job %d", i);
-      int32_t st = check_frame(j.src_rgba, j.src_depth, j.width, j.height, j.baseline_m, j.focal_px, j.target_eye,
-                               j.fill_mode, j.dst_rgba, j.dst_depth, j.dst_mask, who);
-      if (st != YORO_OK) return st;
-      if (j.fill_mode == YORO_FILL_PATCHER)
-        return fail(YORO_ERR_UNSUPPORTED, "%s: the Patcher fill reads neighbouring rows; use yoro_reproject", who);
-      const uintptr_t n = (uintptr_t)j.width * (uintptr_t)j.height;
-      ranges.push_back({(uintptr_t)j.src_rgba, (uintptr_t)j.src_rgba + 4 * n, false});
-      ranges.push_back({(uintptr_t)j.src_depth, (uintptr_t)j.src_depth + 4 * n, false});
-      ranges.push_back({(uintptr_t)j.dst_rgba, (uintptr_t)j.dst_rgba + 4 * n, true});
-      if (j.dst_depth) ranges.push_back({(uintptr_t)j.dst_depth, (uintptr_t)j.dst_depth + 4 * n, true});
-      if (j.dst_mask) ranges.push_back({(uintptr_t)j.dst_mask, (uintptr_t)j.dst_mask + n, true});
-      rows += (uint64_t)j.height;
-      max_w = std::max(max_w, j.width);
-    }
-    if (rows > 0xFFFFFFFFull) return fail(YORO_ERR_UNSUPPORTED, "yoro_stereo_batch_prepare: too many rows");
-    // No output may overlap anything else: sort by start; an output must not
-    // overlap its sorted neighbours' spans (track the furthest end so far).
-    std::sort(ranges.begin(), ranges.end(), [](const Range& a, const Range& b) { return a.lo < b.lo; });
-    uintptr_t far_hi = 0;
-    bool far_out = false;
-    for (size_t i = 0; i < ranges.size(); ++i) {
-      if (i > 0 && ranges[i].lo < far_hi && (ranges[i].out || far_out))
-        return fail(YORO_ERR_INVALID_ARG, "yoro_stereo_batch_prepare: an output buffer overlaps another buffer");
-      if (ranges[i].hi > far_hi) {
-        far_hi = ranges[i].hi;
-        far_out = ranges[i].out;
-      } else if (ranges[i].out) {
-        far_out = true;
-      }
-    }
-    hipStream_t s = (hipStream_t)hip_stream;
-    auto* hdr = reinterpret_cast<yoro::BatchHeader*>(dev_workspace);
-    auto* dj = reinterpret_cast<yoro::DevJob*>(hdr + 1);
-    yoro::BatchHeader h{};
-    h.n_jobs = (uint32_t)n_jobs;
-    h.total_rows = (uint32_t)rows;
-    h.max_width = (uint32_t)max_w;
-    h.errors = 0;
-    hipError_t e = yoro::launch_header(h, hdr, s);
-    uint32_t row = 0;
-    for (int32_t first = 0; e == hipSuccess && first < n_jobs; first += yoro::kUploadChunk) {
-      yoro::UploadChunk c{};
-      c.first = (uint32_t)first;
-      c.count = (uint32_t)std::min(yoro::kUploadChunk, n_jobs - first);
-      for (uint32_t k = 0; k < c.count; ++k) {
-        c.jobs[k] = make_job(jobs[first + k], row);
-        row += (uint32_t)jobs[first + k].height;
-      }
-      e = yoro::launch_upload(c, dj, s);
-    }
-    if (e != hipSuccess)
-      return fail(YORO_ERR_DEVICE, "yoro_stereo_batch_prepare: upload failed: %s", hipGetErrorString(e));
-    return ok();
-  } catch (...) {
-    return fail(YORO_ERR_DEVICE, "yoro_stereo_batch_prepare: internal error");
-  }
+  return prepare_batch(jobs, n_jobs, dev_workspace, workspace_bytes, hip_stream, false);
 }
 
 int32_t yoro_stereo_batch_launch(const void* dev_workspace, int32_t max_width, void* hip_stream) {
-  try {
-    if (!dev_workspace) return fail(YORO_ERR_INVALID_ARG, "yoro_stereo_batch_launch: null workspace");
-    if (max_width <= 0 || max_width > YORO_MAX_WIDTH)
-      return fail(YORO_ERR_INVALID_ARG, "yoro_stereo_batch_launch: max_width %d out of range", max_width);
-    const auto* hdr = reinterpret_cast<const yoro::BatchHeader*>(dev_workspace);
-    const auto* dj = reinterpret_cast<const yoro::DevJob*>(hdr + 1);
-    // Persistent grid: as many workgroups as fit on the chip at once.
-    DeviceFacts f;
-    const int cus = device_facts(&f) ? f.cus : 256;
-    const int grid = cus * yoro::warp_blocks_per_cu(max_width, true);
-    hipError_t e = yoro::launch_warp_batch(hdr, dj, max_width, grid, (hipStream_t)hip_stream);
-    if (e != hipSuccess)
-      return fail(YORO_ERR_DEVICE, "yoro_stereo_batch_launch: launch failed: %s", hipGetErrorString(e));
-    return ok();
-  } catch (...) {
-    return fail(YORO_ERR_DEVICE, "yoro_stereo_batch_launch: internal error");
-  }
+  return launch_batch(dev_workspace, max_width, hip_stream, "yoro_stereo_batch_launch");
 }
 
 int32_t yoro_stereo_batch_launch_lowres(const void* dev_workspace, int32_t max_width, int32_t scale, int32_t linear,
@@ -482,12 +544,56 @@ int32_t yoro_stereo_batch_launch_lowres(const void* dev_workspace, int32_t max_w
 }
 
 int32_t yoro_stereo_batch(const yoro_job* jobs, int32_t n_jobs, void* dev_workspace, size_t workspace_bytes,
-                          void* hip_stream) {
-  int32_t st = yoro_stereo_batch_prepare(jobs, n_jobs, dev_workspace, workspace_bytes, hip_stream);
-  if (st != YORO_OK) return st;
-  int32_t max_w = 0;
-  for (int32_t i = 0; i < n_jobs; ++i) max_w = std::max(max_w, jobs[i].width);
-  return yoro_stereo_batch_launch(dev_workspace, max_w, hip_stream);
+                          const yoro_model* model, void* hip_stream) {
+  const char* who = "yoro_stereo_batch";
+  try {
+    // prepare's checks, then the learned jobs', all before anything is
+    // queued.
+    int32_t st = prepare_batch(jobs, n_jobs, dev_workspace, workspace_bytes, hip_stream, true, false);
+    if (st != YORO_OK) return st;
+    int32_t max_w = 0, lw = 0, lh = 0;
+    bool any_learned = false;
+    std::vector<Range> frames;
+    frames.push_back({(uintptr_t)dev_workspace, (uintptr_t)dev_workspace + workspace_bytes, true});
+    for (int32_t i = 0; i < n_jobs; ++i) {
+      const yoro_job& j = jobs[i];
+      max_w = std::max(max_w, j.width);
+      const uintptr_t n = (uintptr_t)j.width * (uintptr_t)j.height;
+      frames.push_back({(uintptr_t)j.src_rgba, (uintptr_t)j.src_rgba + 4 * n, false});
+      frames.push_back({(uintptr_t)j.src_depth, (uintptr_t)j.src_depth + 4 * n, false});
+      frames.push_back({(uintptr_t)j.dst_rgba, (uintptr_t)j.dst_rgba + 4 * n, true});
+      if (j.dst_depth) frames.push_back({(uintptr_t)j.dst_depth, (uintptr_t)j.dst_depth + 4 * n, true});
+      if (j.dst_mask) frames.push_back({(uintptr_t)j.dst_mask, (uintptr_t)j.dst_mask + n, true});
+      if (j.fill_mode != YORO_FILL_LEARNED) continue;
+      if (!j.dst_depth || !j.dst_mask)
+        return fail(YORO_ERR_INVALID_ARG, "%s: job %d: the learned fill needs dst_depth and dst_mask", who, i);
+      if (j.width % 8 || j.height % 8)
+        return fail(YORO_ERR_UNSUPPORTED, "%s: job %d: the learned fill needs width and height multiples of 8", who, i);
+      any_learned = true;
+      if ((int64_t)j.width * j.height > (int64_t)lw * lh) lw = j.width, lh = j.height;
+    }
+    if (any_learned) {
+      // The workspace must hold the largest learned frame's activations.
+      st = check_model(model, lw, lh, frames, who);
+      if (st != YORO_OK) return st;
+      for (int32_t i = 0; i < n_jobs; ++i)
+        if (jobs[i].fill_mode == YORO_FILL_LEARNED &&
+            model->workspace_bytes < yoro_model_workspace_bytes(1, jobs[i].height, jobs[i].width))
+          return fail(YORO_ERR_WORKSPACE_TOO_SMALL, "%s: job %d: model workspace too small", who, i);
+    }
+    st = prepare_batch(jobs, n_jobs, dev_workspace, workspace_bytes, hip_stream, true);
+    if (st == YORO_OK) st = launch_batch(dev_workspace, max_w, hip_stream, who);
+    if (st != YORO_OK || !any_learned) return st;
+    for (int32_t i = 0; i < n_jobs && st == YORO_OK; ++i) {
+      const yoro_job& j = jobs[i];
+      if (j.fill_mode != YORO_FILL_LEARNED) continue;
+      st = yoro_model_fill(model->weights, j.dst_rgba, j.dst_depth, j.dst_mask, 1, j.height, j.width, j.dst_rgba,
+                           model->workspace, model->workspace_bytes, hip_stream);
+    }
+    return st;
+  } catch (...) {
+    return fail(YORO_ERR_DEVICE, "%s: internal error", who);
+  }
 }
 
 const uint32_t* yoro_stereo_batch_errors(const void* dev_workspace) {

@@ -519,7 +519,7 @@ int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, c
         status = serve_fail(YORO_ERR_DEVICE, "%s: wait: %s", who, hipGetErrorString(e));
         break;
       }
-      const int32_t st = yoro_stereo_batch(jobs.data(), (int32_t)jobs.size(), ws + Lay.table * B.slot, Lay.table, s);
+      const int32_t st = yoro_stereo_batch(jobs.data(), (int32_t)jobs.size(), ws + Lay.table * B.slot, Lay.table, nullptr, s);
       if (st != YORO_OK) {
         status = st;
         break;

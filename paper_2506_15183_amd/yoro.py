@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libyoro.so")
 
 TARGET_RIGHT, TARGET_LEFT = 0, 1
-FILL_NONE, FILL_NEAREST_BG, FILL_PATCHER = 0, 1, 3
+FILL_NONE, FILL_NEAREST_BG, FILL_LEARNED, FILL_PATCHER = 0, 1, 2, 3
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE_TOO_SMALL, ERR_DEVICE = 0, 1, 2, 3, 4
 MAX_WIDTH, MAX_HEIGHT = 8192, 16384
 
@@ -64,6 +64,26 @@ class Job(ctypes.Structure):
     ]
 
 
+class Model(ctypes.Structure):
+    """yoro_model: bf16 model weights and the network's workspace (device)."""
+
+    _fields_ = [
+        ("weights", ctypes.c_void_p),
+        ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_size_t),
+    ]
+
+
+def make_model(weights, workspace) -> Model:
+    """A yoro_model over a bf16 weights tensor and a uint8 workspace tensor
+    (the caller keeps both alive while the calls that use it are queued)."""
+    return Model(weights.data_ptr(), workspace.data_ptr(), workspace.numel() * workspace.element_size())
+
+
+def _model(model):
+    return None if model is None else ctypes.byref(model)
+
+
 _lib = None
 
 
@@ -87,7 +107,7 @@ def load():
     L.yoro_reproject_pose.argtypes = [vp, vp, i32, i32, f32, f32, f32, vp, vp, i32, vp, vp, vp, vp,
                                       ctypes.c_size_t, vp]
     L.yoro_reproject_pose.restype = i32
-    L.yoro_fill_holes.argtypes = [vp, vp, vp, i32, i32, i32, i32, vp]
+    L.yoro_fill_holes.argtypes = [vp, vp, vp, i32, i32, i32, i32, ctypes.POINTER(Model), vp]
     L.yoro_fill_holes.restype = i32
     L.yoro_stereo_batch_workspace_bytes.argtypes = [i32]
     L.yoro_stereo_batch_workspace_bytes.restype = ctypes.c_size_t
@@ -95,7 +115,7 @@ def load():
     L.yoro_stereo_batch_prepare.restype = i32
     L.yoro_stereo_batch_launch.argtypes = [vp, i32, vp]
     L.yoro_stereo_batch_launch.restype = i32
-    L.yoro_stereo_batch.argtypes = [ctypes.POINTER(Job), i32, vp, ctypes.c_size_t, vp]
+    L.yoro_stereo_batch.argtypes = [ctypes.POINTER(Job), i32, vp, ctypes.c_size_t, ctypes.POINTER(Model), vp]
     L.yoro_stereo_batch.restype = i32
     L.yoro_stereo_batch_errors.argtypes = [vp]
     L.yoro_stereo_batch_errors.restype = vp
@@ -196,14 +216,16 @@ def reproject_pose(src_rgba, src_depth, focal_px: float, cx: float, cy: float, r
     return rgba, depth, mask
 
 
-def fill_holes(rgba, depth, mask, target_eye: int = TARGET_RIGHT, fill_mode: int = FILL_NEAREST_BG, stream=None):
-    """Fill holes (mask != 0) of a warped frame in place."""
+def fill_holes(rgba, depth, mask, target_eye: int = TARGET_RIGHT, fill_mode: int = FILL_NEAREST_BG, model=None,
+               stream=None):
+    """Fill holes (mask != 0) of a warped frame in place (FILL_LEARNED needs
+    a Model)."""
     H, W = depth.shape
     _need(rgba, torch.uint8, (H, W, 4), "rgba")
     _need(depth, torch.float32, (H, W), "depth")
     _need(mask, torch.uint8, (H, W), "mask")
     _check(load().yoro_fill_holes(_ptr(rgba), _ptr(depth), _ptr(mask), W, H, int(target_eye), int(fill_mode),
-                                  _stream(stream)))
+                                  _model(model), _stream(stream)))
     return rgba, depth, mask
 
 
@@ -247,9 +269,10 @@ class StereoBatch:
         _check(load().yoro_stereo_batch_launch_lowres(_ptr(self.workspace), int(max_width or self.max_width),
                                                       int(scale), int(bool(linear)), _stream(stream)))
 
-    def run(self, stream=None):
+    def run(self, stream=None, model=None):
+        """prepare + launch, then the learned fill of FILL_LEARNED jobs (model)."""
         _check(load().yoro_stereo_batch(self.jobs, self.n, _ptr(self.workspace), self.workspace.numel(),
-                                        _stream(stream)))
+                                        _model(model), _stream(stream)))
 
     def errors(self) -> int:
         """Rows the last launch skipped (reads the device counter; synchronises)."""

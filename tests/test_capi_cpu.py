@@ -88,7 +88,30 @@ def test_host_validation_rejects_without_launching():
     assert L.yoro_reproject(fake, fake2, 8, 8, 0.06, 900.0, 0, 1, inside, None, None, None) == yoro.ERR_INVALID_ARG
     assert b"overlap" in L.yoro_last_error()
     # fill_holes
-    assert L.yoro_fill_holes(None, fake2, fake3, 8, 8, 0, 1, None) == yoro.ERR_INVALID_ARG
+    assert L.yoro_fill_holes(None, fake2, fake3, 8, 8, 0, 1, None, None) == yoro.ERR_INVALID_ARG
+    # the learned fill: only with a model, sizes multiples of 8, workspace large enough
+    from paper_2506_15183_amd import unet
+
+    assert L.yoro_reproject(fake, fake2, 8, 8, 0.06, 900.0, 0, yoro.FILL_LEARNED, fake3, None, None,
+                            None) == yoro.ERR_UNSUPPORTED
+    assert b"model" in L.yoro_last_error()
+    mk = ctypes.c_void_p(0x50000000)
+    assert L.yoro_fill_holes(fake, fake2, mk, 8, 8, 0, yoro.FILL_LEARNED, None, None) == yoro.ERR_INVALID_ARG
+    need = unet.nnlib().yoro_model_workspace_bytes(1, 8, 8)
+    assert need > 0
+    model = yoro.Model(0x58000000, 0x5C000000, need - 1)
+    assert L.yoro_fill_holes(fake, fake2, mk, 8, 8, 0, yoro.FILL_LEARNED, ctypes.byref(model),
+                             None) == yoro.ERR_WORKSPACE_TOO_SMALL
+    model.workspace_bytes = need
+    assert L.yoro_fill_holes(fake, fake2, mk, 12, 8, 0, yoro.FILL_LEARNED, ctypes.byref(model),
+                             None) == yoro.ERR_UNSUPPORTED
+    bad = yoro.Model(0x58000008, 0x5C000000, need)
+    assert L.yoro_fill_holes(fake, fake2, mk, 8, 8, 0, yoro.FILL_LEARNED, ctypes.byref(bad),
+                             None) == yoro.ERR_INVALID_ARG                             # misaligned weights
+    over = yoro.Model(0x58000000, 0x10000, need)
+    assert L.yoro_fill_holes(fake, fake2, mk, 8, 8, 0, yoro.FILL_LEARNED, ctypes.byref(over),
+                             None) == yoro.ERR_INVALID_ARG                             # workspace over the frame
+    assert b"overlap" in L.yoro_last_error()
     # batch
     assert L.yoro_stereo_batch_workspace_bytes(0) == 0
     assert L.yoro_stereo_batch_workspace_bytes(64) == 64 + 64 * 72
@@ -102,6 +125,20 @@ def test_host_validation_rejects_without_launching():
     assert b"overlap" in L.yoro_last_error()
     assert L.yoro_stereo_batch_prepare(jobs, 2, ws, 8, None) == yoro.ERR_WORKSPACE_TOO_SMALL
     assert L.yoro_stereo_batch_launch(ws, 0, None) == yoro.ERR_INVALID_ARG
+    # learned jobs: not through prepare; through yoro_stereo_batch only with a
+    # model, dst_depth and dst_mask
+    one = (yoro.Job * 1)()
+    one[0].src_rgba, one[0].src_depth, one[0].dst_rgba = 0x10000, 0x20000000, 0x40000000
+    one[0].width, one[0].height, one[0].baseline_m, one[0].focal_px = 8, 8, 0.06, 900.0
+    one[0].target_eye, one[0].fill_mode = 0, yoro.FILL_LEARNED
+    assert L.yoro_stereo_batch_prepare(one, 1, ws, 4096, None) == yoro.ERR_UNSUPPORTED
+    assert L.yoro_stereo_batch(one, 1, ws, 4096, ctypes.byref(model), None) == yoro.ERR_INVALID_ARG
+    assert b"dst_depth" in L.yoro_last_error()
+    one[0].dst_depth, one[0].dst_mask = 0x44000000, 0x48000000
+    assert L.yoro_stereo_batch(one, 1, ws, 4096, None, None) == yoro.ERR_INVALID_ARG
+    model.workspace_bytes = need - 1
+    assert L.yoro_stereo_batch(one, 1, ws, 4096, ctypes.byref(model), None) == yoro.ERR_WORKSPACE_TOO_SMALL
+    model.workspace_bytes = need
     # the downsampled-buffer calls: scale and linear are checked too
     for scale in (0, 3, 32, -1):
         assert L.yoro_reproject_lowres(fake, fake2, 8, 8, 0.06, 900.0, 0, 1, scale, 1, fake3, None, None,

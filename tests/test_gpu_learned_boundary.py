@@ -1,0 +1,90 @@
+"""The learned fill through the boundary calls (YORO_FILL_LEARNED with a
+yoro_model): yoro_fill_holes equals the plain fill followed by
+yoro_model_fill bit for bit, and yoro_stereo_batch runs plain and learned
+jobs side by side, each equal to its stand-alone calls."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle import reproject as orc
+from paper_2506_15183_amd.scenes.configs import config1_frame, config3_frames
+
+pytestmark = pytest.mark.gpu
+
+
+def _t():
+    import torch
+
+    from paper_2506_15183_amd import train, unet, yoro
+
+    return torch, yoro, unet, train
+
+
+def _net(unet, train):
+    return unet.UNet("cuda", params=train.load_weights())
+
+
+def _model(torch, yoro, unet, net, h, w):
+    ws = torch.empty(int(unet.nnlib().yoro_model_workspace_bytes(1, h, w)), dtype=torch.uint8, device="cuda")
+    return yoro.make_model(net.wf, ws), ws
+
+
+def test_fill_holes_learned_equals_plain_then_model_fill(cuda):
+    torch, yoro, unet, train = _t()
+    net = _net(unet, train)
+    spec = config1_frame(0)
+    rgba, depth = spec.render_source()
+    for eye in (orc.TARGET_RIGHT, orc.TARGET_LEFT):
+        warped = orc.reproject(rgba, depth, spec.baseline_m, spec.focal_px, eye, orc.FILL_NONE)
+        a, d, m = [torch.from_numpy(np.ascontiguousarray(x).copy()).cuda() for x in warped]
+        model, ws = _model(torch, yoro, unet, net, spec.height, spec.width)
+        yoro.fill_holes(a, d, m, eye, yoro.FILL_LEARNED, model=model)
+        # The reference: the plain fill, then the network on the plain-filled frame.
+        a2, d2, m2 = [torch.from_numpy(np.ascontiguousarray(x).copy()).cuda() for x in warped]
+        yoro.fill_holes(a2, d2, m2, eye, yoro.FILL_NEAREST_BG)
+        want = net.fill_native(a2[None], d2[None], m2[None])[0]
+        torch.cuda.synchronize()
+        assert np.array_equal(a.cpu().numpy(), want.cpu().numpy())
+        assert np.array_equal(d.cpu().numpy().view(np.uint32), d2.cpu().numpy().view(np.uint32))
+        assert np.array_equal(m.cpu().numpy(), m2.cpu().numpy())
+        plain = orc.fill_holes(*warped, eye, orc.FILL_NEAREST_BG)
+        hits = plain[2] == 0
+        got = a.cpu().numpy()
+        assert np.array_equal(got[hits], plain[0][hits])            # hits untouched
+        assert (got[~hits] != plain[0][~hits]).any()                 # holes refined
+
+
+def test_stereo_batch_mixes_plain_and_learned_jobs(cuda):
+    torch, yoro, unet, train = _t()
+    net = _net(unet, train)
+    specs = config3_frames(n_per_size=1)
+    frames = [s.render_source() for s in specs]
+    src = [(torch.from_numpy(r).cuda(), torch.from_numpy(d).cuda()) for r, d in frames]
+    outs = [(torch.empty((s.height, s.width, 4), dtype=torch.uint8, device="cuda"),
+             torch.empty((s.height, s.width), dtype=torch.float32, device="cuda"),
+             torch.empty((s.height, s.width), dtype=torch.uint8, device="cuda")) for s in specs]
+    modes = [yoro.FILL_LEARNED if i % 2 else yoro.FILL_NEAREST_BG for i in range(len(specs))]
+    jobs = [yoro.make_job(a, b, *o, s.baseline_m, s.focal_px, s.target_eye, md)
+            for s, (a, b), o, md in zip(specs, src, outs, modes)]
+    big = max((s for s, md in zip(specs, modes) if md == yoro.FILL_LEARNED), key=lambda s: s.pixels)
+    model, ws = _model(torch, yoro, unet, net, big.height, big.width)
+    batch = yoro.StereoBatch(jobs)
+    batch.run(model=model)
+    torch.cuda.synchronize()
+    assert batch.errors() == 0
+    for s, (r, d), o, md in zip(specs, frames, outs, modes):
+        plain = orc.reproject(r, d, s.baseline_m, s.focal_px, s.target_eye, orc.FILL_NEAREST_BG, nthreads=0)
+        got = [t.cpu().numpy() for t in o]
+        assert np.array_equal(got[1].view(np.uint32), plain[1].view(np.uint32))
+        assert np.array_equal(got[2], plain[2])
+        if md == yoro.FILL_NEAREST_BG:
+            assert np.array_equal(got[0], plain[0]), f"plain job {s.width}x{s.height}"
+        else:
+            pa, pd, pm = [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in plain]
+            want = net.fill_native(pa[None], pd[None], pm[None])[0].cpu().numpy()
+            assert np.array_equal(got[0], want), f"learned job {s.width}x{s.height}"
+    # A learned job without a model is refused before anything is queued.
+    with pytest.raises(yoro.YoroError) as ei:
+        batch.run()
+    assert ei.value.status == yoro.ERR_INVALID_ARG
