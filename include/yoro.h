@@ -217,6 +217,24 @@ int32_t yoro_stereo_batch(const yoro_job* jobs_host, int32_t n_jobs, void* dev_w
  * last launch because max_width was too small); reset by prepare. */
 const uint32_t* yoro_stereo_batch_errors(const void* dev_workspace);
 
+/*
+ * yoro_stereo_batch_static -- yoro_stereo_batch for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, hosts that forbid hipMalloc): the same prepare + launch of the
+ * same kernels, with the job table in a fixed device array inside the
+ * library (64 + 72 * YORO_STATIC_MAX_JOBS bytes per GPU, held until the
+ * process ends) instead of a caller workspace.  It allocates and frees no
+ * device memory.  Plain jobs only: YORO_FILL_LEARNED and
+ * YORO_FILL_PATCHER are YORO_ERR_UNSUPPORTED; more than
+ * YORO_STATIC_MAX_JOBS jobs is YORO_ERR_INVALID_ARG.  Every call on one GPU
+ * shares that GPU's array, which keeps the last call's table (each call
+ * rewrites the header and every record it uses, error counter included):
+ * calls that overlap on one GPU (on different streams, or not yet finished
+ * when another is queued on another stream) race, so order them on one
+ * stream.  Outputs and other errors as yoro_stereo_batch.
+ */
+#define YORO_STATIC_MAX_JOBS 1024
+int32_t yoro_stereo_batch_static(const yoro_job* jobs_host, int32_t n_jobs, void* hip_stream);
 
 /*
  * yoro_reproject_lowres -- yoro_reproject through a downsampled intermediate

@@ -287,6 +287,34 @@ int32_t launch_batch(const void* dev_workspace, int32_t max_width, void* hip_str
   }
 }
 
+// The job table of yoro_stereo_batch_static: a header and YORO_STATIC_MAX_JOBS
+// records in a device array of the library's own.  In host code `scratch`
+// names a host-side stand-in, never the device memory: every host use goes
+// through the address hipGetSymbolAddress returns for the current device.
+constexpr size_t kStaticTableBytes = sizeof(yoro::BatchHeader) + (size_t)YORO_STATIC_MAX_JOBS * sizeof(yoro::DevJob);
+static __device__ __align__(256) unsigned char scratch[kStaticTableBytes];
+
+std::mutex g_static_mu;
+std::vector<void*> g_static_ptr;  // per device: the device address of scratch
+
+// The device address of this device's table (looked up once per device).
+int32_t static_table(void** out, const char* who) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(YORO_ERR_DEVICE, "%s: hipGetDevice failed: %s", who, hipGetErrorString(e));
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if ((int)g_static_ptr.size() <= dev) g_static_ptr.resize(dev + 1, nullptr);
+  if (!g_static_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(YORO_ERR_DEVICE, "%s: no device address for the job table: %s", who, hipGetErrorString(e));
+    g_static_ptr[dev] = p;
+  }
+  *out = g_static_ptr[dev];
+  return YORO_OK;
+}
+
 }  // namespace
 
 namespace yoro {
@@ -591,6 +619,29 @@ int32_t yoro_stereo_batch(const yoro_job* jobs, int32_t n_jobs, void* dev_worksp
                            model->workspace, model->workspace_bytes, hip_stream);
     }
     return st;
+  } catch (...) {
+    return fail(YORO_ERR_DEVICE, "%s: internal error", who);
+  }
+}
+
+int32_t yoro_stereo_batch_static(const yoro_job* jobs, int32_t n_jobs, void* hip_stream) {
+  const char* who = "yoro_stereo_batch_static";
+  try {
+    if (!jobs || n_jobs <= 0 || n_jobs > YORO_STATIC_MAX_JOBS)
+      return fail(YORO_ERR_INVALID_ARG, "%s: need 1..%d jobs (the fixed table's size), got %d", who,
+                  YORO_STATIC_MAX_JOBS, n_jobs);
+    for (int32_t i = 0; i < n_jobs; ++i)
+      if (jobs[i].fill_mode == YORO_FILL_LEARNED)
+        return fail(YORO_ERR_UNSUPPORTED, "%s: job %d: the learned fill needs a model workspace; use "
+                    "yoro_stereo_batch", who, i);
+    void* table = nullptr;
+    int32_t st = static_table(&table, who);
+    if (st != YORO_OK) return st;
+    st = prepare_batch(jobs, n_jobs, table, kStaticTableBytes, hip_stream, false);
+    if (st != YORO_OK) return st;
+    int32_t max_w = 0;
+    for (int32_t i = 0; i < n_jobs; ++i) max_w = std::max(max_w, jobs[i].width);
+    return launch_batch(table, max_w, hip_stream, who);
   } catch (...) {
     return fail(YORO_ERR_DEVICE, "%s: internal error", who);
   }

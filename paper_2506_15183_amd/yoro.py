@@ -19,6 +19,7 @@ TARGET_RIGHT, TARGET_LEFT = 0, 1
 FILL_NONE, FILL_NEAREST_BG, FILL_LEARNED, FILL_PATCHER = 0, 1, 2, 3
 OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_WORKSPACE_TOO_SMALL, ERR_DEVICE = 0, 1, 2, 3, 4
 MAX_WIDTH, MAX_HEIGHT = 8192, 16384
+STATIC_MAX_JOBS = 1024  # YORO_STATIC_MAX_JOBS
 
 # Every symbol include/yoro.h declares (the learned-fill layers of
 # include/yoro_nn.h are bound in unet.py).
@@ -34,6 +35,7 @@ EXPORTS = (
     "yoro_stereo_batch_launch_lowres",
     "yoro_stereo_batch",
     "yoro_stereo_batch_errors",
+    "yoro_stereo_batch_static",
     "yoro_hole_sse",
     "yoro_last_error",
     "yoro_version",
@@ -117,6 +119,8 @@ def load():
     L.yoro_stereo_batch_launch.restype = i32
     L.yoro_stereo_batch.argtypes = [ctypes.POINTER(Job), i32, vp, ctypes.c_size_t, ctypes.POINTER(Model), vp]
     L.yoro_stereo_batch.restype = i32
+    L.yoro_stereo_batch_static.argtypes = [ctypes.POINTER(Job), i32, vp]
+    L.yoro_stereo_batch_static.restype = i32
     L.yoro_stereo_batch_errors.argtypes = [vp]
     L.yoro_stereo_batch_errors.restype = vp
     L.yoro_hole_sse.argtypes = [vp, vp, vp, i32, i32, vp, vp]
@@ -277,6 +281,13 @@ class StereoBatch:
     def errors(self) -> int:
         """Rows the last launch skipped (reads the device counter; synchronises)."""
         return int(self.workspace[12:16].view(torch.int32).item())
+
+
+def stereo_batch_static(jobs, stream=None):
+    """yoro_stereo_batch_static: the batch with the library's fixed job table
+    (no device allocation; plain jobs only)."""
+    arr = (Job * len(jobs))(*jobs)
+    _check(load().yoro_stereo_batch_static(arr, len(jobs), _stream(stream)))
 
 
 def hole_sse(rgba, ref_rgba, mask=None, out=None, stream=None):
