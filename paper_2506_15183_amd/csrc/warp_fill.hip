@@ -2,12 +2,10 @@
 //
 // One workgroup (256 threads, 4 wave64s) owns one image row at a time
 // (Observation O1, Section 5: the shift is horizontal and one-signed, so
-// rows are independent).  In the single-frame kernel the next row's depth
-// and colour loads are in flight while the current row is processed; the
-// batch kernel relies on more resident rows instead.
+// rows are independent) and strides over the rows of the frame, or of every
+// job of a batch, as a persistent grid.
 //
-// Per row, all in LDS:
-//   A  clear the row's 64-bit target keys;
+// Per row, all in LDS (the row's 64-bit target keys start EMPTY):
 //   B  scatter with the depth test (Section 6, reprojection equation and
 //      Algorithms 1-2; the lowest depth is kept): per source pixel
 //      d = roundf((B*f)/z) in FP32, target column x -+ d, and an LDS
@@ -15,23 +13,29 @@
 //      one row have equal disparity and so never meet on one target: the
 //      minimum is decided by the depth alone, and the low word simply
 //      carries the winner's colour (Algorithm 3's gather of the source
-//      colour, done by the scatter itself);
-//   C  every column is stored (a hole provisionally as RGBA 0, depth +inf);
-//      per wave64 a ballot of "target reached" gives one 64-bit hit mask per
-//      64 columns, and the holes are appended to a compact per-row list (one
-//      LDS atomic per wave);
+//      colour, done by the scatter itself).  The loads of the workgroup's
+//      next row are issued right after the scatter, into the same registers,
+//      so they are in flight during C-F;
+//   C  per wave64 a ballot of "target reached" gives one 64-bit hit mask per
+//      64 columns, and each wave lists its holes;
 //   E  each listed hole walks the hit masks from its own word to its
 //      nearest hit on either side and takes the farther one (Section 5 O2;
 //      Section 7 Patcher figure: on equal depth, the side opposite the
-//      shift), overwriting its provisional value.
+//      shift): the hole's key becomes that hit's key;
+//   F  every column is stored from its key (an empty key: RGBA 0, depth
+//      +inf), four consecutive columns per lane with one 16-byte
+//      non-temporal store, and the keys are cleared for the next row.
+// C and E touch only LDS, so each row issues a fixed number of global
+// stores, all in F, after the next row's loads: the wait for those loads
+// at the next scatter does not have to wait for this row's stores.
 //
 // The code avoids divergent branches where it can: on CDNA the scalar unit
 // issues at the same per-SIMD rate as the vector ALU, so exec-mask juggling
 // costs as much as arithmetic.
 //
-// Wave priorities step down through a row: loads 3, scatter 2, resolve 1,
-// fill 0.  A workgroup that starts a row gets its memory requests out
-// first; the later phases, which wait only on LDS, fill the issue gaps.
+// Wave priorities step through a row: next-row loads 3, scatter 2, C and E
+// 1 (the hole walk 0), stores 2.  A workgroup's memory requests get out
+// ahead of the phases that wait only on LDS.
 //
 // HBM traffic per target pixel: 4 B depth + 4 B RGBA read, 4 B RGBA written
 // (+4 B depth, +1 B mask when asked for).
@@ -40,6 +44,8 @@
 namespace yoro {
 namespace {
 
+typedef uint32_t u32x4v __attribute__((ext_vector_type(4)));
+
 // One row's inputs held in registers: thread t owns columns t + i*kThreads.
 template <int PPT>
 struct RowIn {
@@ -47,101 +53,219 @@ struct RowIn {
   uint32_t c[PPT];
 };
 
-// Columns past the row's end keep depth 0, which splats nothing.
+// Lanes past the row's end load nothing and keep stale registers: the
+// scatter tests x < W in the one ragged chunk.  (Zeroing the registers
+// first would make the next row's loads wait for every outstanding store.)
 template <int PPT>
 __device__ __forceinline__ void load_row(const DevJob& J, int y, RowIn<PPT>& in) {
   const int W = J.width;
   const size_t row = (size_t)y * (size_t)W;
   YORO_GLOBAL const float* zp = gmem(J.src_depth) + row;
   YORO_GLOBAL const uint32_t* cp = gmem(J.src_rgba) + row;
-#pragma unroll
-  for (int i = 0; i < PPT; ++i) {
-    in.z[i] = 0.0f;
-    in.c[i] = 0u;
-  }
   for_cols<PPT>(W, [&](int i, int x) {
     in.z[i] = __builtin_nontemporal_load(&zp[x]);
     in.c[i] = __builtin_nontemporal_load(&cp[x]);
   });
 }
 
-// Phases A-E for row y of job J, whose inputs are in registers.  EXTRA:
-// the job also asks for the depth and/or mask outputs.
-template <int PPT, bool EXTRA>
-__device__ __forceinline__ void warp_fill_row(const DevJob& J, int y, const RowIn<PPT>& in, unsigned char* smem,
-                                              int wl) {
-  RowLds s(smem, wl);
+// B: scatter with the depth test into keys that are EMPTY.  Lanes with
+// nothing to splat (no geometry, a shift of a full row or more, a target off
+// the row, a column past the row's end) hit their own sink slot instead of
+// branching.
+template <int PPT>
+__device__ __forceinline__ void scatter_row(const DevJob& J, const RowIn<PPT>& in, const RowLds& s, int wl) {
   const int W = J.width;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const float bf = J.baseline_m * J.focal_px;
   const uint32_t Wbits = __float_as_uint((float)W);
-  const bool target_right = J.target_eye == 0;
   // x_t = x - d (target right) or x + d (target left), as x + ((d ^ m) - m).
-  const int m = target_right ? -1 : 0;
-  const bool fill = J.fill_mode != 0;
-  const size_t row = (size_t)y * (size_t)W;
-  YORO_GLOBAL uint32_t* orow = gmem(J.dst_rgba) + row;
-  YORO_GLOBAL float* zrow = (EXTRA && J.dst_depth) ? gmem(J.dst_depth) + row : nullptr;
-  YORO_GLOBAL uint8_t* mrow = (EXTRA && J.dst_mask) ? gmem(J.dst_mask) + row : nullptr;
-
-  // A: clear keys, two per 16-byte store (wl >= W is even).
-  for (int e = tid; e < (W + 1) >> 1; e += kThreads)
-    reinterpret_cast<ulonglong2*>(s.key)[e] = make_ulonglong2(kEmpty, kEmpty);
-  __syncthreads();
-
-  __builtin_amdgcn_s_setprio(2);
-  // B: scatter with the depth test.  Lanes with nothing to splat (no
-  // geometry, a shift of a full row or more, a target off the row, a column
-  // past the row's end) hit their own sink slot instead of branching.
+  const int m = J.target_eye == 0 ? -1 : 0;
+  const int nfull = W / kThreads;
 #pragma unroll
   for (int i = 0; i < PPT; ++i) {
-    if (i * kThreads < W) {
+    if (i <= nfull && i * kThreads < W) {
       const int x = tid + i * kThreads;
       const float z = in.z[i];
       const float q = bf / z;
       const int d = round_half_away(q);
       const int xt = x + ((d ^ m) - m);
       // z > 0 and q < W together are q in [+0, W): as bf > 0, any other z
-      // (<= 0, NaN, or the 0 a column past the row's end holds) gives a
-      // negative, -0, infinite or NaN q, whose bits compare above W's.
-      const bool ok = (__float_as_uint(q) < Wbits) & ((unsigned)xt < (unsigned)W);
+      // (<= 0, NaN) gives a negative, -0, infinite or NaN q, whose bits
+      // compare above W's.
+      bool ok = (__float_as_uint(q) < Wbits) & ((unsigned)xt < (unsigned)W);
+      if (i == nfull) ok &= x < W;
       atomicMin(&s.key[ok ? xt : wl + lane], ((uint64_t)__float_as_uint(z) << 32) | in.c[i]);
     }
   }
-  __syncthreads();
-
-  __builtin_amdgcn_s_setprio(1);
-  resolve_fill_row<PPT>(s, W, target_right, fill, [&](int x, uint32_t c, uint32_t zb, uint8_t mk) {
-    orow[x] = c;
-    if (zrow) zrow[x] = __uint_as_float(zb);
-    if (mrow) mrow[x] = mk;
-  });
-  __syncthreads();  // the next row reuses the LDS
 }
 
+// C and E, in LDS only.  C: per wave64 a ballot of "target reached" (a hit's
+// high word holds the bits of a depth in (0, +inf], never the all-ones of
+// EMPTY) gives one hit mask per 64 columns; each wave appends its holes to
+// its own segment of the hole list.  E (with fill): each listed hole walks
+// the hit masks to its nearest hits and its key becomes the chosen hit's
+// key.  E reads only hits' keys and writes only holes' keys.
 template <int PPT>
-__global__ __launch_bounds__(kThreads) void warp_single_kernel(DevJob J, int wl) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  RowIn<PPT> in;
-  int y = blockIdx.x;
-  if (y < J.height) load_row<PPT>(J, y, in);
-  for (; y < J.height; y += gridDim.x) {
-    const RowIn<PPT> cur = in;
-    const int yn = y + gridDim.x;
-    __builtin_amdgcn_s_setprio(3);
-    if (yn < J.height) load_row<PPT>(J, yn, in);
-    __builtin_amdgcn_s_setprio(0);
-    warp_fill_row<PPT, true>(J, y, cur, smem, wl);
+__device__ __forceinline__ void mark_and_fill_row(const RowLds& s, int W, bool target_right, bool fill) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int nw = (W + 63) >> 6;
+  uint16_t* holes = s.holes + wave * s.seg;  // this wave's segment
+  uint32_t run = 0;    // holes listed by this wave so far (wave-uniform)
+  uint64_t mword = 0;  // lane i: hit mask of chunk i's 64 columns of this wave
+#pragma unroll
+  for (int i = 0; i < PPT; ++i) {
+    if (i * kThreads < W) {
+      const int x = tid + i * kThreads;
+      const uint64_t k = s.key[min(x, W - 1)];
+      const bool inrow = x < W;
+      const bool hit = inrow & ((uint32_t)(k >> 32) != 0xFFFFFFFFu);
+      const uint64_t hm = __ballot(hit);
+      if (fill) {
+        const uint64_t om = __ballot(inrow) & ~hm;
+        if ((om >> lane) & 1ull) {
+          const uint32_t below =
+              __builtin_amdgcn_mbcnt_hi((uint32_t)(om >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)om, 0u));
+          holes[run + below] = (uint16_t)x;
+        }
+        run += (uint32_t)__popcll(om);
+      }
+      // Park this chunk's mask in lane i for one store below.
+      mword = (lane == i) ? hm : mword;
+    }
+  }
+  // One LDS store per lane that parked a mask: word (i*4 + wave) holds
+  // chunk i's columns of this wave.
+  const int nchunks = (W + kThreads - 1) / kThreads;
+  const int word = lane * (kThreads / 64) + wave;
+  if (lane < nchunks && word < nw) s.mask[word] = mword;
+  __syncthreads();
+  if (!fill) return;
+  __builtin_amdgcn_s_setprio(0);
+  for (uint32_t h0 = 0; h0 < run; h0 += 64) {
+    const uint32_t h = h0 + lane;
+    int x = h < run ? (int)holes[h] : 0;
+    const bool act = (h < run) & (x < W);  // every listed column is < W; guard anyway
+    x = act ? x : 0;
+    int L, R;
+    nearest_hits_walk(s.mask, nw, W, x, L, R);
+    const uint32_t zl = (uint32_t)(s.key[max(L, 0)] >> 32);
+    const uint32_t zr = (uint32_t)(s.key[min(R, W - 1)] >> 32);
+    const int p = pick_side(L, R, W, zl, zr, target_right);
+    if (act && p >= 0) s.key[x] = s.key[p];
   }
 }
 
-// The batch kernel loads each row when it starts it (no register prefetch of
-// the next row) and asks the compiler for 7 waves per SIMD, the workgroups
-// per CU the LDS of the widest rows allows: latency is hidden by the other
-// resident rows, which measured faster than prefetching at 6 waves per SIMD.
+// F: store every column from its key and leave the keys EMPTY.  A hit or a
+// filled hole carries its key's colour and depth; a key still EMPTY is a
+// hole left unfilled: RGBA 0, depth +inf, mask 1 (2 when the fill found no
+// hit in the row).  Without depth or mask outputs: four consecutive columns
+// per lane, one 16-byte non-temporal store when the row is 16-byte aligned.
+template <int PPT, bool EXTRA>
+__device__ __forceinline__ void store_row(const DevJob& J, int y, const RowLds& s) {
+  const int W = J.width;
+  const size_t row = (size_t)y * (size_t)W;
+  YORO_GLOBAL uint32_t* orow = gmem(J.dst_rgba) + row;
+  if (!EXTRA) {
+    constexpr int NF = (PPT + 3) / 4;  // chunks of 4 * kThreads columns
+    const bool vec = (reinterpret_cast<uintptr_t>(orow) & 15u) == 0;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const int x0 = f * 4 * kThreads + 4 * (int)threadIdx.x;
+      if (f * 4 * kThreads < W && x0 < W) {
+        // x0 + 3 < W rounded up to 4 <= wl: inside the key row.
+        const ulonglong2 k01 = *reinterpret_cast<const ulonglong2*>(&s.key[x0]);
+        const ulonglong2 k23 = *reinterpret_cast<const ulonglong2*>(&s.key[x0 + 2]);
+        *reinterpret_cast<ulonglong2*>(&s.key[x0]) = make_ulonglong2(kEmpty, kEmpty);
+        *reinterpret_cast<ulonglong2*>(&s.key[x0 + 2]) = make_ulonglong2(kEmpty, kEmpty);
+        auto col = [](uint64_t k) { return (uint32_t)(k >> 32) == 0xFFFFFFFFu ? 0u : (uint32_t)k; };
+        const u32x4v c = u32x4v{col(k01.x), col(k01.y), col(k23.x), col(k23.y)};
+        if (vec && x0 + 3 < W) {
+          __builtin_nontemporal_store(c, reinterpret_cast<YORO_GLOBAL u32x4v*>(orow + x0));
+        } else {
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (x0 + j < W) orow[x0 + j] = c[j];
+        }
+      }
+    }
+    return;
+  }
+  YORO_GLOBAL float* zrow = J.dst_depth ? gmem(J.dst_depth) + row : nullptr;
+  YORO_GLOBAL uint8_t* mrow = J.dst_mask ? gmem(J.dst_mask) + row : nullptr;
+  const uint8_t unfilled = J.fill_mode != 0 ? 2 : 1;
+  for_cols<PPT>(W, [&](int, int x) {
+    const uint64_t k = s.key[x];
+    s.key[x] = kEmpty;
+    const bool empty = (uint32_t)(k >> 32) == 0xFFFFFFFFu;
+    orow[x] = empty ? 0u : (uint32_t)k;
+    if (zrow) zrow[x] = __uint_as_float(empty ? kInfBits : (uint32_t)(k >> 32));
+    if (mrow) mrow[x] = ((s.mask[x >> 6] >> (x & 63)) & 1ull) ? 0 : (empty ? unfilled : 1);
+  });
+}
+
+// C, E and F of row y of job J, whose scatter is done (the caller's barrier
+// separates them from it).
 template <int PPT>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) void warp_batch_kernel(
+__device__ __forceinline__ void finish_row(const DevJob& J, int y, const RowLds& s) {
+  __builtin_amdgcn_s_setprio(1);
+  mark_and_fill_row<PPT>(s, J.width, J.target_eye == 0, J.fill_mode != 0);
+  __syncthreads();
+  __builtin_amdgcn_s_setprio(2);
+  if (J.dst_depth || J.dst_mask)
+    store_row<PPT, true>(J, y, s);
+  else
+    store_row<PPT, false>(J, y, s);
+}
+
+__device__ __forceinline__ void clear_keys(const RowLds& s, int wl) {
+  for (int e = threadIdx.x; e < wl / 2; e += kThreads)
+    reinterpret_cast<ulonglong2*>(s.key)[e] = make_ulonglong2(kEmpty, kEmpty);
+}
+
+// Waves per SIMD the kernels ask the compiler for: 6 (80 VGPRs: the
+// registers of the prefetched row stay live through C-F, and 6 measured
+// faster than 7 and 5), or fewer when the LDS of the widest row of this
+// instantiation (one workgroup = one wave per SIMD) allows fewer, so wide
+// rows get the registers that occupancy leaves free.
+constexpr int warp_waves(int ppt) {
+  const int w = kThreads * ppt;
+  const int lds = (w + 64) * 8 + (w / 64) * 8 + 16 + w * 2;  // warp_lds_bytes of that width
+  const int fit = 160 * 1024 / lds;
+  return fit < 1 ? 1 : (fit < 6 ? fit : 6);
+}
+
+template <int PPT>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(warp_waves(PPT)))) void warp_single_kernel(
+    DevJob J, int wl) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  RowLds s(smem, wl);
+  clear_keys(s, wl);
+  RowIn<PPT> cur;
+  int y = blockIdx.x;
+  if (y < J.height) load_row<PPT>(J, y, cur);
+  __syncthreads();
+  for (; y < J.height; y += gridDim.x) {
+    // An opaque copy of the width per row keeps the compiler from hoisting
+    // every per-chunk predicate out of the loop (they spill otherwise).
+    DevJob Jr = J;
+    asm volatile("" : "+s"(Jr.width));
+    __builtin_amdgcn_s_setprio(2);
+    scatter_row<PPT>(Jr, cur, s, wl);
+    const int yn = y + gridDim.x;
+    __builtin_amdgcn_s_setprio(3);
+    if (yn < Jr.height) load_row<PPT>(Jr, yn, cur);
+    __syncthreads();
+    finish_row<PPT>(Jr, y, s);
+    __builtin_amdgcn_s_setprio(0);
+    __syncthreads();  // the next row reuses the LDS
+  }
+}
+
+template <int PPT>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(warp_waves(PPT)))) void warp_batch_kernel(
     BatchHeader* hdr, const DevJob* __restrict__ jobs, int wl) {
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t n = hdr->n_jobs, total = hdr->total_rows;
@@ -150,22 +274,43 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
     while (j + 1 < n && jobs[j + 1].row_start <= r) ++j;
     return j;
   };
-  uint32_t j = 0;
-  for (uint32_t r = blockIdx.x; r < total; r += gridDim.x) {
-    j = job_of(r, j);
+  RowLds s(smem, wl);
+  clear_keys(s, wl);
+  uint32_t r = blockIdx.x;
+  if (r >= total) return;  // uniform per workgroup, before any barrier
+  uint32_t j = job_of(r, 0);
+  RowIn<PPT> cur;
+  {
     const DevJob J = jobs[j];
-    RowIn<PPT> cur;
-    __builtin_amdgcn_s_setprio(3);
     if (J.width <= wl) load_row<PPT>(J, (int)(r - J.row_start), cur);
-    __builtin_amdgcn_s_setprio(0);
-    if (J.width <= wl) {
-      if (J.dst_depth || J.dst_mask)
-        warp_fill_row<PPT, true>(J, (int)(r - J.row_start), cur, smem, wl);
-      else
-        warp_fill_row<PPT, false>(J, (int)(r - J.row_start), cur, smem, wl);
-    } else if (threadIdx.x == 0) {
-      atomicAdd(&hdr->errors, 1u);  // rows wider than the LDS layout are skipped
+  }
+  __syncthreads();
+  while (r < total) {
+    const uint32_t rn = r + gridDim.x;
+    const uint32_t jn = rn < total ? job_of(rn, j) : j;
+    {
+      const DevJob J = jobs[j];
+      if (J.width <= wl) {
+        __builtin_amdgcn_s_setprio(2);
+        scatter_row<PPT>(J, cur, s, wl);
+      } else if (threadIdx.x == 0) {
+        atomicAdd(&hdr->errors, 1u);  // rows wider than the LDS layout are skipped
+      }
     }
+    if (rn < total) {
+      const DevJob Jn = jobs[jn];
+      __builtin_amdgcn_s_setprio(3);
+      if (Jn.width <= wl) load_row<PPT>(Jn, (int)(rn - Jn.row_start), cur);
+    }
+    __syncthreads();
+    {
+      const DevJob J = jobs[j];
+      if (J.width <= wl) finish_row<PPT>(J, (int)(r - J.row_start), s);
+    }
+    __builtin_amdgcn_s_setprio(0);
+    __syncthreads();  // the next row reuses the LDS
+    r = rn;
+    j = jn;
   }
 }
 
