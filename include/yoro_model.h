@@ -42,6 +42,17 @@ int32_t yoro_model_pack(const float* master, void* weights, void* hip_stream);
 /* Workspace for n images of h x w (h, w multiples of 8, n*h*w < 2^31). */
 size_t yoro_model_workspace_bytes(int32_t n, int32_t h, int32_t w);
 
+/* Where a forward pass over n images of h x w leaves its stored activations
+ * in the workspace (read them after the call, e.g. to check each layer):
+ * offsets[18] in bytes from the workspace's start, of NHWC bf16 buffers in
+ * this order, with their channels per pixel (level l has (h >> l) x (w >> l)
+ * pixels per image): e0a 32; c0 64 (d0a, then e0b); d0b 32; d0c 32; p1 32;
+ * e1a 64; c1 128 (d1a, e1b); d1b 64; d1c 64; p2 64; e2a 128; c2 256 (d2a,
+ * e2b); d2b 128; d2c 128; p3 128; e3a 256; e3b 256; and the FP32 residual,
+ * 3 per pixel (yoro_model_residual writes the caller's res instead). */
+#define YORO_MODEL_ACTIVATIONS 18
+int32_t yoro_model_workspace_layout(int32_t n, int32_t h, int32_t w, int64_t* offsets);
+
 /* Residual (FP32 [n*h*w][3]) of the network on n plain-filled images
  * (rgba u8 [n][h][w][4], depth f32 [n][h][w], mask u8 [n][h][w]). */
 int32_t yoro_model_residual(const void* weights, const uint8_t* rgba, const float* depth, const uint8_t* mask,

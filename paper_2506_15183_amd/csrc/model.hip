@@ -170,6 +170,19 @@ size_t yoro_model_workspace_bytes(int32_t n, int32_t h, int32_t w) {
   return carve(nullptr, n, h, w, nullptr);
 }
 
+int32_t yoro_model_workspace_layout(int32_t n, int32_t h, int32_t w, int64_t* offsets) {
+  if (!offsets || !shape_ok(n, h, w))
+    return model_fail(YORO_ERR_INVALID_ARG, "yoro_model_workspace_layout: bad shape or null offsets");
+  char* const base = reinterpret_cast<char*>(256);  // any aligned non-null base: offsets are relative to it
+  Acts a;
+  carve(base, n, h, w, &a);
+  const void* order[YORO_MODEL_ACTIVATIONS] = {a.e0a, a.c0,  a.d0b, a.d0c, a.p1,  a.e1a, a.c1,  a.d1b, a.d1c,
+                                               a.p2,  a.e2a, a.c2,  a.d2b, a.d2c, a.p3,  a.e3a, a.e3b, a.res};
+  for (int i = 0; i < YORO_MODEL_ACTIVATIONS; ++i)
+    offsets[i] = (int64_t)(reinterpret_cast<const char*>(order[i]) - base);
+  return YORO_OK;
+}
+
 int32_t yoro_model_residual(const void* weights, const uint8_t* rgba, const float* depth, const uint8_t* mask,
                             int32_t n, int32_t h, int32_t w, float* res, void* workspace, size_t workspace_bytes,
                             void* hip_stream) {

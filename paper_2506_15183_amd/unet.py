@@ -82,6 +82,8 @@ def nnlib():
         L.yoro_nn_conv3x3_wgrad_workspace.restype = sz
         L.yoro_model_weights_bytes.argtypes = []
         L.yoro_model_weights_bytes.restype = sz
+        L.yoro_model_workspace_layout.argtypes = [i32, i32, i32, vp]
+        L.yoro_model_workspace_layout.restype = i32
         L.yoro_model_workspace_bytes.argtypes = [i32, i32, i32]
         L.yoro_model_workspace_bytes.restype = sz
         L.yoro_model_tiles_workspace_bytes.argtypes = [i32, i32, i32, i32]

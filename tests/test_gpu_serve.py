@@ -87,6 +87,43 @@ def test_plain_serving_processes_every_frame_and_matches_alone(cuda):
             assert torch.equal(g, w), (hi, o, k)
 
 
+def test_burst_arrivals_batch_together_and_match_alone(cuda):
+    """Eight headsets of three resolutions whose frames arrive in bursts at
+    the same instants: the loop batches frames of different sizes into one
+    launch (some batches hold three or more frames), and every frame's
+    result equals the same frame warped alone, bit for bit."""
+    torch, serve, unet, yoro, HeadsetSpec, FrameSpec = _mods()
+    hs = _headsets(HeadsetSpec, 8, rates=(50.0,))
+    bursts = 4  # YORO_SERVE_MAX_OUTPUTS: each arrival keeps its own output set
+    cfg = serve.Config(budget_bytes=10**10, n_sources=3, n_outputs=bursts, max_batch=8, max_in_flight=1)
+    srv = serve.Server(hs, cfg, _frames(FrameSpec))
+    trace = np.zeros(bursts * len(hs), serve.ARRIVAL_DTYPE)
+    for b in range(bursts):
+        for i in range(len(hs)):
+            a = trace[b * len(hs) + i]
+            a["t_ns"] = 10_000_000 + b * 20_000_000  # every headset at the same instant
+            a["headset"] = i
+            a["source"] = (b + i) % cfg.n_sources
+    res = srv.run(trace, serve.PLAIN)
+    assert (res["path"] == serve.PATH_PLAIN).all()
+    assert (res["batch_frames"] >= 3).sum() >= 3, res["batch_frames"]
+    # A batch mixes resolutions: some launch holds frames of two sizes or more.
+    mixed = False
+    for t in np.unique(res["launch_ns"]):
+        sizes = {(hs[int(h)].width, hs[int(h)].height) for h in trace["headset"][res["launch_ns"] == t]}
+        mixed |= len(sizes) >= 2
+    assert mixed
+    # Each arrival has its own output set (n_outputs = bursts): check every frame.
+    count = [0] * len(hs)
+    for k in range(len(trace)):
+        hi = int(trace["headset"][k])
+        o = count[hi] % cfg.n_outputs
+        count[hi] += 1
+        want = _plain_alone(yoro, srv, hs[hi], int(trace["source"][k]))
+        for g, w in zip(srv.outs[hi][o], want):
+            assert torch.equal(g, w), (hi, o, k, int(res["batch_frames"][k]))
+
+
 def test_admission_rejects_what_does_not_fit(cuda):
     torch, serve, unet, yoro, HeadsetSpec, FrameSpec = _mods()
     hs = _headsets(HeadsetSpec, 3)
