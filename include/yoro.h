@@ -192,12 +192,17 @@ int32_t yoro_stereo_batch_prepare(const yoro_job* jobs_host, int32_t n_jobs, voi
 
 /*
  * yoro_stereo_batch_launch -- run the jobs that the last prepare on this
- * workspace uploaded, as one persistent kernel.  max_width must be >= every
+ * workspace uploaded, as one kernel whose grid covers the rows of all jobs
+ * once (a few consecutive rows per workgroup).  max_width must be >= every
  * job's width (it sizes the per-row scratch in LDS); rows of a wider job are
  * skipped and counted in the workspace's error counter (see
- * yoro_stereo_batch_errors).  Capture-safe: no allocation, copy or sync.
+ * yoro_stereo_batch_errors).  total_rows: the sum of the prepared jobs'
+ * heights (1 .. 2^32 - 1), which sizes the grid; rows past a smaller value
+ * are skipped and counted the same way.  Capture-safe: no allocation, copy
+ * or sync.
  */
-int32_t yoro_stereo_batch_launch(const void* dev_workspace, int32_t max_width, void* hip_stream);
+int32_t yoro_stereo_batch_launch(const void* dev_workspace, int32_t max_width, int64_t total_rows,
+                                 void* hip_stream);
 
 /*
  * yoro_stereo_batch -- prepare + launch, then the learned fill of the jobs
@@ -273,12 +278,13 @@ int32_t yoro_reproject_lowres(const uint8_t* src_rgba, const float* src_depth, i
  * this workspace uploaded, each as yoro_reproject_lowres with the given
  * scale and linear flag, as one persistent kernel.  A workgroup takes
  * scale rows of one block row at a time; scale 1 runs
- * yoro_stereo_batch_launch's kernel.  max_width and the error counter
- * as in yoro_stereo_batch_launch.  Capture-safe: no allocation, copy or
- * sync.
+ * yoro_stereo_batch_launch's kernel.  max_width, total_rows and the error
+ * counter as in yoro_stereo_batch_launch (the persistent kernel of scales
+ * 2-16 checks total_rows but needs it for no grid).  Capture-safe: no
+ * allocation, copy or sync.
  */
-int32_t yoro_stereo_batch_launch_lowres(const void* dev_workspace, int32_t max_width, int32_t scale,
-                                        int32_t linear, void* hip_stream);
+int32_t yoro_stereo_batch_launch_lowres(const void* dev_workspace, int32_t max_width, int64_t total_rows,
+                                        int32_t scale, int32_t linear, void* hip_stream);
 
 /*
  * yoro_reproject_pose -- warp one frame to an eye at a general pose (Section

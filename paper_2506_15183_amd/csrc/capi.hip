@@ -267,18 +267,18 @@ int32_t prepare_batch(const yoro_job* jobs, int32_t n_jobs, void* dev_workspace,
   }
 }
 
-int32_t launch_batch(const void* dev_workspace, int32_t max_width, void* hip_stream, const char* who) {
+int32_t launch_batch(const void* dev_workspace, int32_t max_width, int64_t total_rows, void* hip_stream,
+                     const char* who) {
   try {
     if (!dev_workspace) return fail(YORO_ERR_INVALID_ARG, "%s: null workspace", who);
     if (max_width <= 0 || max_width > YORO_MAX_WIDTH)
       return fail(YORO_ERR_INVALID_ARG, "%s: max_width %d out of range", who, max_width);
+    if (total_rows <= 0 || total_rows > 0xFFFFFFFFll)
+      return fail(YORO_ERR_INVALID_ARG, "%s: total_rows %lld out of range", who, (long long)total_rows);
     const auto* hdr = reinterpret_cast<const yoro::BatchHeader*>(dev_workspace);
     const auto* dj = reinterpret_cast<const yoro::DevJob*>(hdr + 1);
-    // Persistent grid: as many workgroups as fit on the chip at once.
-    DeviceFacts f;
-    const int cus = device_facts(&f) ? f.cus : 256;
-    const int grid = cus * yoro::warp_blocks_per_cu(max_width, true);
-    hipError_t e = yoro::launch_warp_batch(hdr, dj, max_width, grid, (hipStream_t)hip_stream);
+    // One workgroup per kBatchRows rows, the grid covering the rows once.
+    hipError_t e = yoro::launch_warp_batch(hdr, dj, max_width, (uint32_t)total_rows, (hipStream_t)hip_stream);
     if (e != hipSuccess)
       return fail(YORO_ERR_DEVICE, "%s: launch failed: %s", who, hipGetErrorString(e));
     return ok();
@@ -535,12 +535,12 @@ int32_t yoro_stereo_batch_prepare(const yoro_job* jobs, int32_t n_jobs, void* de
   return prepare_batch(jobs, n_jobs, dev_workspace, workspace_bytes, hip_stream, false);
 }
 
-int32_t yoro_stereo_batch_launch(const void* dev_workspace, int32_t max_width, void* hip_stream) {
-  return launch_batch(dev_workspace, max_width, hip_stream, "yoro_stereo_batch_launch");
+int32_t yoro_stereo_batch_launch(const void* dev_workspace, int32_t max_width, int64_t total_rows, void* hip_stream) {
+  return launch_batch(dev_workspace, max_width, total_rows, hip_stream, "yoro_stereo_batch_launch");
 }
 
-int32_t yoro_stereo_batch_launch_lowres(const void* dev_workspace, int32_t max_width, int32_t scale, int32_t linear,
-                                        void* hip_stream) {
+int32_t yoro_stereo_batch_launch_lowres(const void* dev_workspace, int32_t max_width, int64_t total_rows,
+                                        int32_t scale, int32_t linear, void* hip_stream) {
   try {
     if (!dev_workspace) return fail(YORO_ERR_INVALID_ARG, "yoro_stereo_batch_launch_lowres: null workspace");
     if (max_width <= 0 || max_width > YORO_MAX_WIDTH)
@@ -550,17 +550,15 @@ int32_t yoro_stereo_batch_launch_lowres(const void* dev_workspace, int32_t max_w
       return fail(YORO_ERR_INVALID_ARG, "yoro_stereo_batch_launch_lowres: scale %d is not 1, 2, 4, 8 or 16", scale);
     if (linear != 0 && linear != 1)
       return fail(YORO_ERR_INVALID_ARG, "yoro_stereo_batch_launch_lowres: linear must be 0 or 1, got %d", linear);
+    if (total_rows <= 0 || total_rows > 0xFFFFFFFFll)
+      return fail(YORO_ERR_INVALID_ARG, "yoro_stereo_batch_launch_lowres: total_rows %lld out of range",
+                  (long long)total_rows);
     const auto* hdr = reinterpret_cast<const yoro::BatchHeader*>(dev_workspace);
     const auto* dj = reinterpret_cast<const yoro::DevJob*>(hdr + 1);
     DeviceFacts f;
     const int cus = device_facts(&f) ? f.cus : 256;
-    if (lg == 0) {  // scale 1 is the direct path
-      const int grid = cus * yoro::warp_blocks_per_cu(max_width, true);
-      hipError_t e = yoro::launch_warp_batch(hdr, dj, max_width, grid, (hipStream_t)hip_stream);
-      if (e != hipSuccess)
-        return fail(YORO_ERR_DEVICE, "yoro_stereo_batch_launch_lowres: launch failed: %s", hipGetErrorString(e));
-      return ok();
-    }
+    if (lg == 0)  // scale 1 is the direct path
+      return launch_batch(dev_workspace, max_width, total_rows, hip_stream, "yoro_stereo_batch_launch_lowres");
     const int grid = cus * yoro::lowres_blocks_per_cu(max_width, lg, true);
     hipError_t e = yoro::launch_lowres(nullptr, hdr, dj, max_width, lg, lg, linear, grid, (hipStream_t)hip_stream);
     if (e != hipSuccess)
@@ -580,12 +578,14 @@ int32_t yoro_stereo_batch(const yoro_job* jobs, int32_t n_jobs, void* dev_worksp
     int32_t st = prepare_batch(jobs, n_jobs, dev_workspace, workspace_bytes, hip_stream, true, false);
     if (st != YORO_OK) return st;
     int32_t max_w = 0, lw = 0, lh = 0;
+    int64_t rows = 0;
     bool any_learned = false;
     std::vector<Range> frames;
     frames.push_back({(uintptr_t)dev_workspace, (uintptr_t)dev_workspace + workspace_bytes, true});
     for (int32_t i = 0; i < n_jobs; ++i) {
       const yoro_job& j = jobs[i];
       max_w = std::max(max_w, j.width);
+      rows += j.height;
       const uintptr_t n = (uintptr_t)j.width * (uintptr_t)j.height;
       frames.push_back({(uintptr_t)j.src_rgba, (uintptr_t)j.src_rgba + 4 * n, false});
       frames.push_back({(uintptr_t)j.src_depth, (uintptr_t)j.src_depth + 4 * n, false});
@@ -610,7 +610,7 @@ int32_t yoro_stereo_batch(const yoro_job* jobs, int32_t n_jobs, void* dev_worksp
           return fail(YORO_ERR_WORKSPACE_TOO_SMALL, "%s: job %d: model workspace too small", who, i);
     }
     st = prepare_batch(jobs, n_jobs, dev_workspace, workspace_bytes, hip_stream, true);
-    if (st == YORO_OK) st = launch_batch(dev_workspace, max_w, hip_stream, who);
+    if (st == YORO_OK) st = launch_batch(dev_workspace, max_w, rows, hip_stream, who);
     if (st != YORO_OK || !any_learned) return st;
     for (int32_t i = 0; i < n_jobs && st == YORO_OK; ++i) {
       const yoro_job& j = jobs[i];
@@ -640,8 +640,9 @@ int32_t yoro_stereo_batch_static(const yoro_job* jobs, int32_t n_jobs, void* hip
     st = prepare_batch(jobs, n_jobs, table, kStaticTableBytes, hip_stream, false);
     if (st != YORO_OK) return st;
     int32_t max_w = 0;
-    for (int32_t i = 0; i < n_jobs; ++i) max_w = std::max(max_w, jobs[i].width);
-    return launch_batch(table, max_w, hip_stream, who);
+    int64_t rows = 0;
+    for (int32_t i = 0; i < n_jobs; ++i) max_w = std::max(max_w, jobs[i].width), rows += jobs[i].height;
+    return launch_batch(table, max_w, rows, hip_stream, who);
   } catch (...) {
     return fail(YORO_ERR_DEVICE, "%s: internal error", who);
   }

@@ -34,7 +34,7 @@
 // costs as much as arithmetic.
 //
 // Wave priorities step through a row: next-row loads 3, scatter 2, C and E
-// 1 (the hole walk 0), stores 2.  A workgroup's memory requests get out
+// 1 (the hole walk 0), stores 3.  A workgroup's memory requests get out
 // ahead of the phases that wait only on LDS.
 //
 // HBM traffic per target pixel: 4 B depth + 4 B RGBA read, 4 B RGBA written
@@ -213,7 +213,7 @@ __device__ __forceinline__ void finish_row(const DevJob& J, int y, const RowLds&
   __builtin_amdgcn_s_setprio(1);
   mark_and_fill_row<PPT>(s, J.width, J.target_eye == 0, J.fill_mode != 0);
   __syncthreads();
-  __builtin_amdgcn_s_setprio(2);
+  __builtin_amdgcn_s_setprio(3);
   if (J.dst_depth || J.dst_mask)
     store_row<PPT, true>(J, y, s);
   else
@@ -225,21 +225,22 @@ __device__ __forceinline__ void clear_keys(const RowLds& s, int wl) {
     reinterpret_cast<ulonglong2*>(s.key)[e] = make_ulonglong2(kEmpty, kEmpty);
 }
 
-// Waves per SIMD the kernels ask the compiler for: 6 (80 VGPRs: the
-// registers of the prefetched row stay live through C-F, and 6 measured
-// faster than 7 and 5), or fewer when the LDS of the widest row of this
-// instantiation (one workgroup = one wave per SIMD) allows fewer, so wide
-// rows get the registers that occupancy leaves free.
-constexpr int warp_waves(int ppt) {
+// Waves per SIMD the kernels ask the compiler for, i.e. their VGPR budget.
+// The single-frame kernel (persistent, the registers of the prefetched row
+// live through C-F): 6, which measured faster than 7 and 5.  The batch
+// kernel: 7 (72 VGPRs, no spills), faster than 6.  Both fewer when the LDS
+// of the widest row of an instantiation (one workgroup = one wave per SIMD)
+// allows fewer, so wide rows get the registers that occupancy leaves free.
+constexpr int warp_waves(int ppt, int cap) {
   const int w = kThreads * ppt;
   const int lds = (w + 64) * 8 + (w / 64) * 8 + 16 + w * 2;  // warp_lds_bytes of that width
   const int fit = 160 * 1024 / lds;
-  return fit < 1 ? 1 : (fit < 6 ? fit : 6);
+  return ppt <= 9 ? cap : (fit < 1 ? 1 : (fit < cap ? fit : cap));
 }
 
 template <int PPT>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(warp_waves(PPT)))) void warp_single_kernel(
-    DevJob J, int wl) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(warp_waves(PPT, 6)))) void
+warp_single_kernel(DevJob J, int wl) {
   extern __shared__ __align__(16) unsigned char smem[];
   RowLds s(smem, wl);
   clear_keys(s, wl);
@@ -264,30 +265,42 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(warp_w
   }
 }
 
+// The batch kernel covers the batch's flat row space once: workgroup b takes
+// the kBatchRows consecutive rows from b * kBatchRows, the next row's loads
+// in flight while the current one finishes.  Workgroups start in launch
+// order, so the rows in flight stay in one window of memory (a persistent
+// grid-stride loop measured 7 % slower: its workgroups drift apart).
 template <int PPT>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(warp_waves(PPT)))) void warp_batch_kernel(
-    BatchHeader* hdr, const DevJob* __restrict__ jobs, int wl) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(warp_waves(PPT, 7)))) void
+warp_batch_kernel(BatchHeader* hdr, const DevJob* __restrict__ jobs, int wl) {
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t n = hdr->n_jobs, total = hdr->total_rows;
-  // Rows only grow, so the job index only moves forward.
-  auto job_of = [&](uint32_t r, uint32_t j) {
-    while (j + 1 < n && jobs[j + 1].row_start <= r) ++j;
-    return j;
-  };
+  const uint64_t first = (uint64_t)blockIdx.x * kBatchRows;
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
+    const uint64_t covered = (uint64_t)gridDim.x * kBatchRows;
+    if (total > covered) atomicAdd(&hdr->errors, (uint32_t)(total - covered));  // rows the grid does not reach
+  }
+  if (first >= total) return;  // uniform per workgroup, before any barrier
+  uint32_t r = (uint32_t)first;
+  const uint32_t rend = total - r < (uint32_t)kBatchRows ? total : r + kBatchRows;
+  // The job of row r: the last whose row_start <= r (binary search).
+  uint32_t lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (jobs[mid].row_start <= r) lo = mid; else hi = mid;
+  }
+  uint32_t j = lo;
   RowLds s(smem, wl);
   clear_keys(s, wl);
-  uint32_t r = blockIdx.x;
-  if (r >= total) return;  // uniform per workgroup, before any barrier
-  uint32_t j = job_of(r, 0);
   RowIn<PPT> cur;
   {
     const DevJob J = jobs[j];
     if (J.width <= wl) load_row<PPT>(J, (int)(r - J.row_start), cur);
   }
   __syncthreads();
-  while (r < total) {
-    const uint32_t rn = r + gridDim.x;
-    const uint32_t jn = rn < total ? job_of(rn, j) : j;
+  for (; r < rend; ++r) {
+    const uint32_t rn = r + 1;
+    const uint32_t jn = (rn < rend && j + 1 < n && jobs[j + 1].row_start <= rn) ? j + 1 : j;
     {
       const DevJob J = jobs[j];
       if (J.width <= wl) {
@@ -297,7 +310,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(warp_w
         atomicAdd(&hdr->errors, 1u);  // rows wider than the LDS layout are skipped
       }
     }
-    if (rn < total) {
+    if (rn < rend) {
       const DevJob Jn = jobs[jn];
       __builtin_amdgcn_s_setprio(3);
       if (Jn.width <= wl) load_row<PPT>(Jn, (int)(rn - Jn.row_start), cur);
@@ -309,7 +322,6 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(warp_w
     }
     __builtin_amdgcn_s_setprio(0);
     __syncthreads();  // the next row reuses the LDS
-    r = rn;
     j = jn;
   }
 }
@@ -550,8 +562,10 @@ hipError_t launch_warp_single(const DevJob& job, int ppt, int grid, hipStream_t 
   }
 }
 
-hipError_t launch_warp_batch(const BatchHeader* hdr, const DevJob* jobs, int max_width, int grid,
+hipError_t launch_warp_batch(const BatchHeader* hdr, const DevJob* jobs, int max_width, uint32_t total_rows,
                              hipStream_t stream) {
+  const uint64_t groups = ((uint64_t)total_rows + kBatchRows - 1) / kBatchRows;
+  const int grid = (int)(groups > 0 ? groups : 1);
   const int ppt = ppt_for(max_width);
   const int wl = lds_width(max_width);
   const size_t lds = warp_lds_bytes(wl);

@@ -83,7 +83,10 @@ inline int lowres_texel_slots(int max_width, int lg) {
 
 // Launchers (defined in warp_fill.hip).  They return hipSuccess or the launch error.
 hipError_t launch_warp_single(const DevJob& job, int ppt, int grid, hipStream_t stream);
-hipError_t launch_warp_batch(const BatchHeader* hdr, const DevJob* jobs, int max_width, int grid,
+// The batch kernel's grid covers the flat row space once, kBatchRows
+// consecutive rows per workgroup (total_rows: the prepared batch's rows).
+constexpr int kBatchRows = 3;
+hipError_t launch_warp_batch(const BatchHeader* hdr, const DevJob* jobs, int max_width, uint32_t total_rows,
                              hipStream_t stream);
 hipError_t launch_upload(const UploadChunk& chunk, DevJob* dst, hipStream_t stream);
 hipError_t launch_header(BatchHeader hdr, BatchHeader* dst, hipStream_t stream);

@@ -42,6 +42,10 @@ EXPORTS = (
 )
 
 
+# include/yoro_measure.h
+MEASURE_EXPORTS = ("yoro_measure_stream",)
+
+
 class YoroError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__(f"yoro status {status}: {message}")
@@ -102,7 +106,7 @@ def load():
     L.yoro_reproject.restype = i32
     L.yoro_reproject_lowres.argtypes = [vp, vp, i32, i32, f32, f32, i32, i32, i32, i32, vp, vp, vp, vp]
     L.yoro_reproject_lowres.restype = i32
-    L.yoro_stereo_batch_launch_lowres.argtypes = [vp, i32, i32, i32, vp]
+    L.yoro_stereo_batch_launch_lowres.argtypes = [vp, i32, ctypes.c_int64, i32, i32, vp]
     L.yoro_stereo_batch_launch_lowres.restype = i32
     L.yoro_reproject_pose_workspace_bytes.argtypes = [i32, i32]
     L.yoro_reproject_pose_workspace_bytes.restype = ctypes.c_size_t
@@ -115,7 +119,7 @@ def load():
     L.yoro_stereo_batch_workspace_bytes.restype = ctypes.c_size_t
     L.yoro_stereo_batch_prepare.argtypes = [ctypes.POINTER(Job), i32, vp, ctypes.c_size_t, vp]
     L.yoro_stereo_batch_prepare.restype = i32
-    L.yoro_stereo_batch_launch.argtypes = [vp, i32, vp]
+    L.yoro_stereo_batch_launch.argtypes = [vp, i32, ctypes.c_int64, vp]
     L.yoro_stereo_batch_launch.restype = i32
     L.yoro_stereo_batch.argtypes = [ctypes.POINTER(Job), i32, vp, ctypes.c_size_t, ctypes.POINTER(Model), vp]
     L.yoro_stereo_batch.restype = i32
@@ -125,6 +129,8 @@ def load():
     L.yoro_stereo_batch_errors.restype = vp
     L.yoro_hole_sse.argtypes = [vp, vp, vp, i32, i32, vp, vp]
     L.yoro_hole_sse.restype = i32
+    L.yoro_measure_stream.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
+    L.yoro_measure_stream.restype = i32
     L.yoro_last_error.argtypes = []
     L.yoro_last_error.restype = ctypes.c_char_p
     L.yoro_version.argtypes = []
@@ -259,19 +265,21 @@ class StereoBatch:
             raise ValueError("bad job count")
         self.workspace = torch.empty(int(nbytes), dtype=torch.uint8, device=device or "cuda")
         self.max_width = max(j.width for j in jobs)
+        self.total_rows = sum(j.height for j in jobs)
 
     def prepare(self, stream=None):
         _check(load().yoro_stereo_batch_prepare(self.jobs, self.n, _ptr(self.workspace), self.workspace.numel(),
                                                 _stream(stream)))
 
-    def launch(self, stream=None, max_width=None):
+    def launch(self, stream=None, max_width=None, total_rows=None):
         _check(load().yoro_stereo_batch_launch(_ptr(self.workspace), int(max_width or self.max_width),
-                                               _stream(stream)))
+                                               int(total_rows or self.total_rows), _stream(stream)))
 
     def launch_lowres(self, scale: int, linear: bool = True, stream=None, max_width=None):
         """Run the prepared jobs through a 1/scale intermediate buffer."""
         _check(load().yoro_stereo_batch_launch_lowres(_ptr(self.workspace), int(max_width or self.max_width),
-                                                      int(scale), int(bool(linear)), _stream(stream)))
+                                                      int(self.total_rows), int(scale), int(bool(linear)),
+                                                      _stream(stream)))
 
     def run(self, stream=None, model=None):
         """prepare + launch, then the learned fill of FILL_LEARNED jobs (model)."""
@@ -301,6 +309,16 @@ def hole_sse(rgba, ref_rgba, mask=None, out=None, stream=None):
         out = torch.empty(2, dtype=torch.int64, device=rgba.device)
     _check(load().yoro_hole_sse(_ptr(rgba), _ptr(ref_rgba), _ptr(mask), W, H, _ptr(out), _stream(stream)))
     return out
+
+
+def measure_stream(a, b, c, stream=None):
+    """yoro_measure_stream: c = a ^ b over int32 tensors of one size (the
+    warp's 8 B in / 4 B out per element, nothing computed in between)."""
+    for t in (a, b, c):
+        if t.dtype != torch.int32 or not t.is_contiguous() or not t.is_cuda or t.numel() != a.numel():
+            raise ValueError("measure_stream: want contiguous CUDA int32 tensors of one size")
+    _check(load().yoro_measure_stream(_ptr(a), _ptr(b), _ptr(c), a.numel(), _stream(stream)))
+    return c
 
 
 def version() -> int:

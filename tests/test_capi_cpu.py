@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
     assert set(header_functions()) == set(yoro.EXPORTS)
     assert yoro.version() == 1
-    for header in ("yoro_nn.h", "yoro_model.h", "yoro_serve.h"):
+    for header in ("yoro_nn.h", "yoro_model.h", "yoro_serve.h", "yoro_measure.h"):
         names = header_functions(header)
         assert names, header
         for name in names:
@@ -39,6 +39,13 @@ def test_library_exports_every_declared_symbol():
     from paper_2506_15183_amd import serve
 
     assert set(header_functions("yoro_serve.h")) == set(serve.EXPORTS)
+    assert set(header_functions("yoro_measure.h")) == set(yoro.MEASURE_EXPORTS)
+    # the streaming kernel's host checks: misaligned, overlapping, empty
+    L = yoro.load()
+    a, b, c = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x200000), ctypes.c_void_p(0x300000)
+    assert L.yoro_measure_stream(ctypes.c_void_p(0x100004), b, c, 16, None) == yoro.ERR_INVALID_ARG
+    assert L.yoro_measure_stream(a, b, ctypes.c_void_p(0x100010), 16, None) == yoro.ERR_INVALID_ARG
+    assert L.yoro_measure_stream(a, b, c, 0, None) == yoro.ERR_INVALID_ARG
 
 
 def test_nn_host_validation_rejects_without_launching():
@@ -124,7 +131,9 @@ def test_host_validation_rejects_without_launching():
     assert L.yoro_stereo_batch_prepare(jobs, 2, ws, 4096, None) == yoro.ERR_INVALID_ARG
     assert b"overlap" in L.yoro_last_error()
     assert L.yoro_stereo_batch_prepare(jobs, 2, ws, 8, None) == yoro.ERR_WORKSPACE_TOO_SMALL
-    assert L.yoro_stereo_batch_launch(ws, 0, None) == yoro.ERR_INVALID_ARG
+    assert L.yoro_stereo_batch_launch(ws, 0, 16, None) == yoro.ERR_INVALID_ARG
+    assert L.yoro_stereo_batch_launch(ws, 8, 0, None) == yoro.ERR_INVALID_ARG        # no rows
+    assert L.yoro_stereo_batch_launch(ws, 8, 1 << 32, None) == yoro.ERR_INVALID_ARG  # too many rows
     # learned jobs: not through prepare; through yoro_stereo_batch only with a
     # model, dst_depth and dst_mask
     one = (yoro.Job * 1)()
@@ -143,15 +152,16 @@ def test_host_validation_rejects_without_launching():
     for scale in (0, 3, 32, -1):
         assert L.yoro_reproject_lowres(fake, fake2, 8, 8, 0.06, 900.0, 0, 1, scale, 1, fake3, None, None,
                                        None) == yoro.ERR_INVALID_ARG
-        assert L.yoro_stereo_batch_launch_lowres(ws, 8, scale, 1, None) == yoro.ERR_INVALID_ARG
+        assert L.yoro_stereo_batch_launch_lowres(ws, 8, 16, scale, 1, None) == yoro.ERR_INVALID_ARG
     assert L.yoro_reproject_lowres(fake, fake2, 8, 8, 0.06, 900.0, 0, 1, 4, 2, fake3, None, None,
                                    None) == yoro.ERR_INVALID_ARG
     assert L.yoro_reproject_lowres(None, fake2, 8, 8, 0.06, 900.0, 0, 1, 4, 1, fake3, None, None,
                                    None) == yoro.ERR_INVALID_ARG
     assert L.yoro_reproject_lowres(fake, fake2, 8, 8, 0.06, 900.0, 0, 3, 4, 1, fake3, None, None,
                                    None) == yoro.ERR_INVALID_ARG   # the Patcher needs depth and mask
-    assert L.yoro_stereo_batch_launch_lowres(None, 8, 4, 1, None) == yoro.ERR_INVALID_ARG
-    assert L.yoro_stereo_batch_launch_lowres(ws, 8193, 4, 1, None) == yoro.ERR_INVALID_ARG
+    assert L.yoro_stereo_batch_launch_lowres(None, 8, 16, 4, 1, None) == yoro.ERR_INVALID_ARG
+    assert L.yoro_stereo_batch_launch_lowres(ws, 8193, 16, 4, 1, None) == yoro.ERR_INVALID_ARG
+    assert L.yoro_stereo_batch_launch_lowres(ws, 8, 0, 4, 1, None) == yoro.ERR_INVALID_ARG
     # the general-pose call: a unit quaternion, finite values, a workspace of one u64 per pixel
     assert L.yoro_reproject_pose_workspace_bytes(8, 8) == 512
     assert L.yoro_reproject_pose_workspace_bytes(0, 8) == 0

@@ -312,6 +312,31 @@ def test_batch_too_narrow_launch_counts_skipped_rows(cuda):
     assert_same(tuple(x.cpu().numpy() for x in dev[0][2:]), o)
 
 
+def test_batch_launch_short_of_rows_counts_them(cuda):
+    """A launch told fewer rows than the batch holds covers only as many as
+    its grid reaches; the rest are skipped and counted, and every covered
+    frame is still right."""
+    torch, yoro = _gpu()
+    specs = config3_frames(n_per_size=1)
+    frames, dev = _batch_inputs(specs)
+    jobs = [yoro.make_job(d[0], d[1], d[2], d[3], d[4], s.baseline_m, s.focal_px, s.target_eye, 1)
+            for s, d in zip(specs, dev)]
+    b = yoro.StereoBatch(jobs)
+    T = b.total_rows
+    b.prepare()
+    b.launch(total_rows=T - 10)
+    torch.cuda.synchronize()
+    covered = -(-(T - 10) // 3) * 3  # the grid's rows: three per workgroup
+    assert b.errors() == T - covered
+    rgba, depth = frames[0]
+    o = orc.reproject(rgba, depth, specs[0].baseline_m, specs[0].focal_px, specs[0].target_eye, 1)
+    assert_same(tuple(x.cpu().numpy() for x in dev[0][2:]), o)
+    b.prepare()
+    b.launch()
+    torch.cuda.synchronize()
+    assert b.errors() == 0
+
+
 def test_invalid_arguments_raise(cuda):
     torch, yoro = _gpu()
     rgba = torch.zeros((4, 8, 4), dtype=torch.uint8, device="cuda")
