@@ -40,6 +40,16 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def host_cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def host_threads() -> int:
     n = os.environ.get("OMP_NUM_THREADS")
     if n and n.isdigit():
@@ -117,6 +127,28 @@ def main():
     log(f"batch: {ms_step:.3f} ms/step wall, launch avg {per_launch_ms.mean():.3f} ms "
         f"(p10 {np.percentile(per_launch_ms, 10):.3f}, p90 {np.percentile(per_launch_ms, 90):.3f}), "
         f"{achieved:.0f} GB/s algorithmic")
+
+    # The practical ceiling for this access pattern: a streaming kernel that
+    # reads 8 B and writes 4 B per element over buffers of the batch's size.
+    sa = torch.ones(pixels, dtype=torch.int32, device=dev)
+    sb = torch.full((pixels,), 3, dtype=torch.int32, device=dev)
+    sc = torch.empty_like(sa)
+    for _ in range(3):
+        yoro.measure_stream(sa, sb, sc, stream=stream)
+    torch.cuda.synchronize()
+    sev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(20)]
+    with torch.cuda.stream(stream):
+        for a_, b_ in sev:
+            a_.record(stream)
+            yoro.measure_stream(sa, sb, sc, stream=stream)
+            b_.record(stream)
+    torch.cuda.synchronize()
+    stream_ms = float(np.mean([a_.elapsed_time(b_) for a_, b_ in sev]))
+    stream_gbs = algo_bytes / (stream_ms * 1e-3) / 1e9
+    assert int(sc[::9973].sum().item()) == 2 * sc[::9973].numel()  # 1 ^ 3
+    del sa, sb, sc
+    log(f"streaming kernel (8 B read + 4 B written per element, {pixels} elements): {stream_ms:.3f} ms, "
+        f"{stream_gbs:.0f} GB/s; the warp kernel reaches {achieved / stream_gbs:.3f} of it")
 
     # ------------------------------------------- single 1832x1920 frame
     single = None
@@ -240,6 +272,20 @@ def main():
             reps += 1
         cpu = {"value": round(pixels * reps / t_cpu / 1e6, 1), "unit": "Mpix/s", "cores": threads, "kind": "oracle",
                "sample": f"the full 64-frame batch x {reps} passes ({t_cpu:.1f} s), OpenMP over rows"}
+        # One thread, on the first 8 frames (2 of each size), about 8 s.
+        sub = list(zip(specs, frames))[:8]
+        sub_px = sum(s.pixels for s, _ in sub)
+        t1_cpu, reps1 = 0.0, 0
+        while t1_cpu < 8.0 and reps1 < 100:
+            t1 = time.perf_counter()
+            for s, (r, d) in sub:
+                orc.reproject(r, d, s.baseline_m, s.focal_px, s.target_eye, orc.FILL_NEAREST_BG, nthreads=1)
+            t1_cpu += time.perf_counter() - t1
+            reps1 += 1
+        cpu["single_thread"] = {"value": round(sub_px * reps1 / t1_cpu / 1e6, 1), "unit": "Mpix/s",
+                                "sample": f"the first 8 frames of the batch (2 of each size, {sub_px} px) x {reps1} "
+                                          f"passes ({t1_cpu:.1f} s), one thread"}
+        cpu["host_cpu"] = host_cpu_model()
         # Other sections write the batch's outputs too: rerun the timed
         # launch so that the check compares its own result with the oracle.
         graph.replay()
@@ -356,6 +402,10 @@ def main():
             "traffic": traffic,
             "kernel": "warp_batch_kernel<9>",
             "launch_ms_avg": round(float(per_launch_ms.mean()), 4),
+            "launch_ms_p10": round(float(np.percentile(per_launch_ms, 10)), 4),
+            "launch_ms_p90": round(float(np.percentile(per_launch_ms, 90)), 4),
+            "stream_gb_s": round(stream_gbs, 1),
+            "frac_vs_stream": round(achieved / stream_gbs, 4),
         },
         "cpu_baseline": cpu,
         "parity_vs_oracle": parity,

@@ -2,7 +2,7 @@
 
 Workflow (each step its own process; the GPU steps under rocprofv3):
 
-  1. rocprofv3 --kernel-trace --stats -d OUT/trace -o t -- python bench.py --no-cpu-baseline --no-single-frame --serve-seconds 0 --eval-frames 0
+  1. rocprofv3 --kernel-trace --stats -d OUT/trace -o t -- python bench.py --no-cpu-baseline --no-single-frame --serve-seconds 0 --eval-frames 0 --no-lowres
   2. rocprofv3 --pmc FETCH_SIZE -d OUT/fetch -o f -- python -m paper_2506_15183_amd.profiling counters
   3. rocprofv3 --pmc WRITE_SIZE -d OUT/write -o w -- python -m paper_2506_15183_amd.profiling counters
   4. python -m paper_2506_15183_amd.profiling summarize OUT > profiles/<kernel>_<workload>.md
@@ -61,17 +61,11 @@ def lowres_lds_bytes(max_width: int, k: int) -> int:
 def counters_workload(launches: int = 5) -> None:
     import torch
 
-    from . import yoro
-    from .scenes import config3_frames
+    from . import workloads
 
     dev = torch.device("cuda:0")
-    specs = config3_frames()
-    frames = [s.render_source() for s in specs]
-    src = [(torch.from_numpy(r).to(dev), torch.from_numpy(d).to(dev)) for r, d in frames]
-    dst = [torch.empty((s.height, s.width, 4), dtype=torch.uint8, device=dev) for s in specs]
-    jobs = [yoro.make_job(a, b, o, None, None, s.baseline_m, s.focal_px, s.target_eye, yoro.FILL_NEAREST_BG)
-            for s, (a, b), o in zip(specs, src, dst)]
-    batch = yoro.StereoBatch(jobs, device=dev)
+    # The benchmark's own batch (RGBA output only).
+    batch = workloads.rgba_only_batch(dev).batch
     batch.prepare()
     for _ in range(launches):
         batch.launch()
@@ -237,7 +231,7 @@ def summarize(out_dir: str, pixels: int, algo_bytes_per_px: int = 12) -> str:
         "Commands (from the repository root, on one MI355X; OUT=the output directory):",
         "",
         "```",
-        "rocprofv3 --kernel-trace --stats -d $OUT/trace -o t -- python bench.py --no-cpu-baseline --no-single-frame --serve-seconds 0 --eval-frames 0",
+        "rocprofv3 --kernel-trace --stats -d $OUT/trace -o t -- python bench.py --no-cpu-baseline --no-single-frame --serve-seconds 0 --eval-frames 0 --no-lowres",
         "rocprofv3 --pmc FETCH_SIZE -d $OUT/fetch -o f -- python -m paper_2506_15183_amd.profiling counters",
         "rocprofv3 --pmc WRITE_SIZE -d $OUT/write -o w -- python -m paper_2506_15183_amd.profiling counters",
         "python -m paper_2506_15183_amd.profiling summarize $OUT",
@@ -310,7 +304,7 @@ def summarize_lowres(out_dir: str, pixels: int, max_width: int = 2160) -> str:
         "Commands (from the repository root, on one MI355X; OUT=the output directory):",
         "",
         "```",
-        "rocprofv3 --kernel-trace --stats -d $OUT/trace -o t -- python bench.py --no-cpu-baseline --no-single-frame --serve-seconds 0 --eval-frames 0",
+        "rocprofv3 --kernel-trace --stats -d $OUT/trace -o t -- python bench.py --no-cpu-baseline --no-single-frame --serve-seconds 0 --eval-frames 0 --no-lowres",
         "rocprofv3 --pmc FETCH_SIZE -d $OUT/fetch -o f -- python -m paper_2506_15183_amd.profiling counters",
         "rocprofv3 --pmc WRITE_SIZE -d $OUT/write -o w -- python -m paper_2506_15183_amd.profiling counters",
         "python -m paper_2506_15183_amd.profiling summarize-lowres $OUT",
