@@ -62,6 +62,19 @@
  *   of it in FP32 in exactly this order (it decides 8-bit values).  The
  *   edge itself is always the first sample, so the division is never by 0.
  *
+ *   Near-object hybrid (Section 11.4, Impact of Object Distance: objects
+ *   nearer than a minimum distance are rendered conventionally and the
+ *   method handles the rest), oracle_reproject_hybrid.  Reading: the scene
+ *   is split at depth D along the view axis.  The far field is every source
+ *   pixel with depth z >= D: it is warped and filled exactly as above, the
+ *   pixels with z < D taking no part (as if they had no geometry).  The
+ *   near field is every surface point nearer than D, rendered for the
+ *   target eye by the caller's renderer and handed in as a layer (colour and
+ *   depth; a depth that is not below D, NaN included, means no near surface
+ *   there).  It lies in front of all far-field content, so the target pixel
+ *   takes the near layer's colour and depth wherever its depth is below D
+ *   (mask 3), and the warped and filled far field elsewhere.
+ *
  * Rounding reading: d = roundf(q), halfway cases away from zero, with
  * q = (B*f)/z, one FP32 multiply then one correctly rounded FP32 division.
  * Depths that are NaN, zero or negative carry no geometry and are skipped; a
@@ -81,6 +94,7 @@
 
 enum { OR_TARGET_RIGHT = 0, OR_TARGET_LEFT = 1 };
 enum { OR_FILL_NONE = 0, OR_FILL_NEAREST_BG = 1, OR_FILL_PATCHER = 3, OR_FILL_SIDE_ONLY = 101 };
+enum { OR_MASK_NEAR = 3 }; /* hybrid: the pixel is the near layer's */
 
 #define OR_EMPTY 0xFFFFFFFFFFFFFFFFull
 
@@ -620,6 +634,42 @@ int oracle_reproject_pose(const uint8_t* src_rgba, const float* src_depth, int32
  * RGB differences over pixels with mask != 0, and the number of such pixels.
  * Integer arithmetic, so the sum is exact.
  */
+/*
+ * Near-object hybrid (see the header): the far field (source depth >= near_m)
+ * warped and filled per fill_mode, then the near layer (near_rgba, near_depth:
+ * the target eye's near field, H*W*4 bytes and H*W floats) wherever its depth
+ * is below near_m.  Outputs as oracle_reproject; dst_depth and dst_mask may
+ * be NULL.  Returns 0, or -1 on bad arguments.
+ */
+int oracle_reproject_hybrid(const uint8_t* src_rgba, const float* src_depth, int32_t width, int32_t height,
+                            float baseline_m, float focal_px, int32_t target_eye, int32_t fill_mode, float near_m,
+                            const uint8_t* near_rgba, const float* near_depth, uint8_t* dst_rgba, float* dst_depth,
+                            uint8_t* dst_mask, int32_t nthreads) {
+  if (width <= 0 || height <= 0 || !src_rgba || !src_depth || !near_rgba || !near_depth || !dst_rgba) return -1;
+  const size_t n = (size_t)width * (size_t)height;
+  /* The far field: source pixels nearer than near_m carry no geometry. */
+  float* far_depth = (float*)malloc(sizeof(float) * n);
+  for (size_t i = 0; i < n; ++i) far_depth[i] = src_depth[i] < near_m ? NAN : src_depth[i];
+  float* z = dst_depth ? dst_depth : (float*)malloc(sizeof(float) * n);
+  uint8_t* m = dst_mask ? dst_mask : (uint8_t*)malloc(n);
+  int rc = oracle_reproject(src_rgba, far_depth, width, height, baseline_m, focal_px, target_eye, fill_mode,
+                            dst_rgba, z, m, nthreads);
+  /* The near field lies in front of everything warped: it wins outright. */
+  if (rc == 0) {
+    for (size_t i = 0; i < n; ++i) {
+      if (near_depth[i] < near_m) {
+        memcpy(&dst_rgba[4 * i], &near_rgba[4 * i], 4);
+        z[i] = near_depth[i];
+        m[i] = OR_MASK_NEAR;
+      }
+    }
+  }
+  free(far_depth);
+  if (!dst_depth) free(z);
+  if (!dst_mask) free(m);
+  return rc;
+}
+
 void oracle_hole_sse(const uint8_t* rgba, const uint8_t* ref, const uint8_t* mask, int64_t n_pixels,
                      uint64_t* sse, uint64_t* count) {
   uint64_t acc = 0, cnt = 0;

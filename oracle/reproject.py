@@ -57,6 +57,11 @@ def lib():
                                           ctypes.c_int32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                           ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
                                           ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_float)]
+        L.oracle_reproject_hybrid.restype = ctypes.c_int
+        L.oracle_reproject_hybrid.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                              ctypes.c_float, ctypes.c_float, ctypes.c_int32, ctypes.c_int32,
+                                              ctypes.c_float, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
         L.oracle_fill_holes.restype = ctypes.c_int
         L.oracle_fill_holes.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                         ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
@@ -152,6 +157,34 @@ def project_pose(z: float, x: int, y: int, width: int, height: int, focal_px: fl
                                    float(np.float32(cx)), float(np.float32(cy)), q.ctypes.data, t.ctypes.data,
                                    ctypes.byref(xt), ctypes.byref(yt), ctypes.byref(zt))
     return None if rc != 0 else (int(xt.value), int(yt.value), float(np.float32(zt.value)))
+
+
+MASK_NEAR = 3  # hybrid: the pixel comes from the near layer
+
+
+def reproject_hybrid(src_rgba: np.ndarray, src_depth: np.ndarray, baseline_m: float, focal_px: float,
+                     target_eye: int, fill_mode: int, near_m: float, near_rgba: np.ndarray, near_depth: np.ndarray,
+                     nthreads: int = 0):
+    """Near-object hybrid (Section 11.4): the far field (source depth >=
+    near_m) warped and filled, the target eye's near layer over it where its
+    depth is below near_m.  (dst_rgba, dst_depth, dst_mask)."""
+    src_rgba = np.ascontiguousarray(src_rgba, dtype=np.uint8)
+    src_depth = np.ascontiguousarray(src_depth, dtype=np.float32)
+    near_rgba = np.ascontiguousarray(near_rgba, dtype=np.uint8)
+    near_depth = np.ascontiguousarray(near_depth, dtype=np.float32)
+    H, W = src_depth.shape
+    assert src_rgba.shape == (H, W, 4) and near_rgba.shape == (H, W, 4) and near_depth.shape == (H, W)
+    dst = np.empty_like(src_rgba)
+    dz = np.empty_like(src_depth)
+    mk = np.empty((H, W), dtype=np.uint8)
+    rc = lib().oracle_reproject_hybrid(src_rgba.ctypes.data, src_depth.ctypes.data, W, H,
+                                       float(np.float32(baseline_m)), float(np.float32(focal_px)), target_eye,
+                                       fill_mode, float(np.float32(near_m)), near_rgba.ctypes.data,
+                                       near_depth.ctypes.data, dst.ctypes.data, dz.ctypes.data, mk.ctypes.data,
+                                       nthreads)
+    if rc != 0:
+        raise ValueError("oracle_reproject_hybrid: bad arguments")
+    return dst, dz, mk
 
 
 def fill_holes(rgba: np.ndarray, depth: np.ndarray, mask: np.ndarray, target_eye: int = TARGET_RIGHT,

@@ -114,6 +114,26 @@ def render(scene: Scene, eye_x: float, W: int | None = None, H: int | None = Non
     return rgba, depth
 
 
+def render_near(scene: Scene, eye_x: float, near_m: float, W: int | None = None, H: int | None = None,
+                x_off: int = 0, y_off: int = 0, nthreads: int = 0):
+    """The near field of one eye, as a conventional renderer would draw it for
+    the near-object hybrid: every pixel whose nearest surface lies closer
+    than near_m (its FP32 depth below near_m) gets that surface's colour and
+    depth; every other pixel RGBA 0 and depth +inf."""
+    W = scene.Wv if W is None else W
+    H = scene.Hv if H is None else H
+    rgba = np.empty((H, W, 4), dtype=np.uint8)
+    depth = np.empty((H, W), dtype=np.float32)
+    near = float(np.float32(near_m))
+    lib().ys_render(scene.objects, scene.n, W, H, x_off, y_off, scene.f, 0.5 * scene.Wv,
+                    0.5 * scene.Hv, float(eye_x), scene.seed & 0xFFFFFFFFFFFFFFFF, scene.Hv,
+                    near, rgba.ctypes.data, depth.ctypes.data, nthreads)
+    miss = ~(depth < np.float32(near))
+    rgba[miss] = 0
+    depth[miss] = np.inf
+    return rgba, depth
+
+
 def render_pair(scene: Scene, baseline_m: float, **kw):
     """(left rgba, left depth, right rgba, right depth); right eye at +baseline."""
     l_rgba, l_depth = render(scene, 0.0, **kw)
