@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "yoro.h"
+#include "yoro_hybrid.h"
 #include "yoro_internal.h"
 #include "yoro_model.h"
 
@@ -482,6 +483,90 @@ int32_t yoro_reproject_pose(const uint8_t* src_rgba, const float* src_depth, int
     return ok();
   } catch (...) {
     return fail(YORO_ERR_DEVICE, "yoro_reproject_pose: internal error");
+  }
+}
+
+int32_t yoro_reproject_hybrid(const uint8_t* src_rgba, const float* src_depth, int32_t width, int32_t height,
+                              float baseline_m, float focal_px, int32_t target_eye, int32_t fill_mode, float near_m,
+                              const uint8_t* near_rgba, const float* near_depth, uint8_t* dst_rgba, float* dst_depth,
+                              uint8_t* dst_mask, void* hip_stream) {
+  const char* who = "yoro_reproject_hybrid";
+  try {
+    int32_t st = check_frame(src_rgba, src_depth, width, height, baseline_m, focal_px, target_eye, fill_mode,
+                             dst_rgba, dst_depth, dst_mask, who);
+    if (st == YORO_OK) st = reject_learned(fill_mode, who);
+    if (st != YORO_OK) return st;
+    if (!std::isfinite(near_m) || !(near_m > 0.0f))
+      return fail(YORO_ERR_INVALID_ARG, "%s: near_m %g must be finite and positive", who, (double)near_m);
+    if (!near_rgba || !near_depth || !aligned4(near_rgba) || !aligned4(near_depth))
+      return fail(YORO_ERR_INVALID_ARG, "%s: near_rgba and near_depth are required, 4-byte aligned", who);
+    const uintptr_t n = (uintptr_t)width * (uintptr_t)height;
+    const Range ins[] = {{(uintptr_t)near_rgba, (uintptr_t)near_rgba + 4 * n, false},
+                         {(uintptr_t)near_depth, (uintptr_t)near_depth + 4 * n, false}};
+    const Range outs[] = {{(uintptr_t)dst_rgba, (uintptr_t)dst_rgba + 4 * n, true},
+                          {(uintptr_t)dst_depth, dst_depth ? (uintptr_t)dst_depth + 4 * n : 0, true},
+                          {(uintptr_t)dst_mask, dst_mask ? (uintptr_t)dst_mask + n : 0, true}};
+    for (const Range& a : ins)
+      for (const Range& b : outs)
+        if (b.hi > b.lo && overlaps(a, b)) return fail(YORO_ERR_INVALID_ARG, "%s: an output overlaps the near layer", who);
+    const bool patcher = fill_mode == YORO_FILL_PATCHER;
+    if (patcher && (!dst_depth || !dst_mask))
+      return fail(YORO_ERR_INVALID_ARG, "%s: the Patcher fill needs dst_depth and dst_mask", who);
+    const int ppt = pick_ppt(width);
+    if (ppt < 0) return fail(YORO_ERR_UNSUPPORTED, "%s: width %d too wide", who, width);
+    // The far field: warped (near pixels skipped) and filled; the Patcher
+    // reads neighbouring rows, so it runs after every row is warped; the
+    // near layer goes over the finished far field.
+    yoro_job j{src_rgba, src_depth, dst_rgba, dst_depth, dst_mask, width, height, baseline_m, focal_px,
+               target_eye, patcher ? (int32_t)YORO_FILL_NONE : fill_mode};
+    hipStream_t s = (hipStream_t)hip_stream;
+    hipError_t e = yoro::launch_warp_single(make_job(j, 0), ppt, grid_for(height, yoro::warp_blocks_per_cu(width, false)),
+                                            s, true, near_m);
+    if (e == hipSuccess && patcher)
+      e = yoro::launch_fill(reinterpret_cast<uint32_t*>(dst_rgba), dst_depth, dst_mask, width, height, target_eye,
+                            fill_mode, ppt, grid_for(height, yoro::fill_blocks_per_cu(width, fill_mode)), s);
+    if (e == hipSuccess) {
+      DeviceFacts f;
+      const int cus = device_facts(&f) ? f.cus : 256;
+      const int64_t want = ((int64_t)n + 255) / 256;
+      const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, (int64_t)cus * 8));
+      e = yoro::launch_composite_near(reinterpret_cast<const uint32_t*>(near_rgba), near_depth, near_m, (int64_t)n,
+                                      reinterpret_cast<uint32_t*>(dst_rgba), dst_depth, dst_mask, grid, s);
+    }
+    if (e != hipSuccess) return fail(YORO_ERR_DEVICE, "%s: launch failed: %s", who, hipGetErrorString(e));
+    return ok();
+  } catch (...) {
+    return fail(YORO_ERR_DEVICE, "%s: internal error", who);
+  }
+}
+
+int32_t yoro_render_near(const yoro_object* objects, int32_t n, int32_t width, int32_t height, int32_t x_off,
+                         int32_t y_off, double focal_px, double cx, double cy, double eye_x, float near_m,
+                         uint8_t* rgba, float* depth, void* hip_stream) {
+  const char* who = "yoro_render_near";
+  try {
+    if (!rgba || !depth || (n > 0 && !objects))
+      return fail(YORO_ERR_INVALID_ARG, "%s: rgba, depth and (for n > 0) objects are required", who);
+    if (n < 0 || n > 65536) return fail(YORO_ERR_INVALID_ARG, "%s: n %d out of range", who, n);
+    if (width <= 0 || height <= 0 || width > YORO_MAX_WIDTH || height > YORO_MAX_HEIGHT)
+      return fail(YORO_ERR_INVALID_ARG, "%s: bad size %dx%d", who, width, height);
+    if (!std::isfinite(focal_px) || !(focal_px > 0.0) || !std::isfinite(cx) || !std::isfinite(cy) ||
+        !std::isfinite(eye_x))
+      return fail(YORO_ERR_INVALID_ARG, "%s: camera parameters must be finite (focal > 0)", who);
+    if (std::isnan(near_m) || !(near_m > 0.0f)) return fail(YORO_ERR_INVALID_ARG, "%s: near_m must be > 0", who);
+    if (!aligned4(rgba) || !aligned4(depth) || (objects && (reinterpret_cast<uintptr_t>(objects) & 7u)))
+      return fail(YORO_ERR_INVALID_ARG, "%s: misaligned pointer", who);
+    const uintptr_t np = (uintptr_t)width * (uintptr_t)height;
+    const Range a{(uintptr_t)rgba, (uintptr_t)rgba + 4 * np, true}, b{(uintptr_t)depth, (uintptr_t)depth + 4 * np, true};
+    const Range o{(uintptr_t)objects, (uintptr_t)objects + sizeof(yoro_object) * (uintptr_t)n, false};
+    if (overlaps(a, b) || (n > 0 && (overlaps(a, o) || overlaps(b, o))))
+      return fail(YORO_ERR_INVALID_ARG, "%s: buffers overlap", who);
+    hipError_t e = yoro::launch_render_near(objects, n, width, height, x_off, y_off, focal_px, cx, cy, eye_x, near_m,
+                                            reinterpret_cast<uint32_t*>(rgba), depth, (hipStream_t)hip_stream);
+    if (e != hipSuccess) return fail(YORO_ERR_DEVICE, "%s: launch failed: %s", who, hipGetErrorString(e));
+    return ok();
+  } catch (...) {
+    return fail(YORO_ERR_DEVICE, "%s: internal error", who);
   }
 }
 

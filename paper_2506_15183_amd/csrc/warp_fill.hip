@@ -72,8 +72,11 @@ __device__ __forceinline__ void load_row(const DevJob& J, int y, RowIn<PPT>& in)
 // nothing to splat (no geometry, a shift of a full row or more, a target off
 // the row, a column past the row's end) hit their own sink slot instead of
 // branching.
-template <int PPT>
-__device__ __forceinline__ void scatter_row(const DevJob& J, const RowIn<PPT>& in, const RowLds& s, int wl) {
+// NEAR (the near-object hybrid's far field): source pixels nearer than
+// near_m take no part.
+template <int PPT, bool NEAR = false>
+__device__ __forceinline__ void scatter_row(const DevJob& J, const RowIn<PPT>& in, const RowLds& s, int wl,
+                                            float near_m = 0.0f) {
   const int W = J.width;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -95,6 +98,7 @@ __device__ __forceinline__ void scatter_row(const DevJob& J, const RowIn<PPT>& i
       // compare above W's.
       bool ok = (__float_as_uint(q) < Wbits) & ((unsigned)xt < (unsigned)W);
       if (i == nfull) ok &= x < W;
+      if (NEAR) ok &= z >= near_m;
       atomicMin(&s.key[ok ? xt : wl + lane], ((uint64_t)__float_as_uint(z) << 32) | in.c[i]);
     }
   }
@@ -238,9 +242,9 @@ constexpr int warp_waves(int ppt, int cap) {
   return ppt <= 9 ? cap : (fit < 1 ? 1 : (fit < cap ? fit : cap));
 }
 
-template <int PPT>
+template <int PPT, bool NEAR>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(warp_waves(PPT, 6)))) void
-warp_single_kernel(DevJob J, int wl) {
+warp_single_kernel(DevJob J, int wl, float near_m) {
   extern __shared__ __align__(16) unsigned char smem[];
   RowLds s(smem, wl);
   clear_keys(s, wl);
@@ -254,7 +258,7 @@ warp_single_kernel(DevJob J, int wl) {
     DevJob Jr = J;
     asm volatile("" : "+s"(Jr.width));
     __builtin_amdgcn_s_setprio(2);
-    scatter_row<PPT>(Jr, cur, s, wl);
+    scatter_row<PPT, NEAR>(Jr, cur, s, wl, near_m);
     const int yn = y + gridDim.x;
     __builtin_amdgcn_s_setprio(3);
     if (yn < Jr.height) load_row<PPT>(Jr, yn, cur);
@@ -544,16 +548,22 @@ hipError_t set_lds_limit(const void* fn, size_t bytes) {
 
 }  // namespace
 
-hipError_t launch_warp_single(const DevJob& job, int ppt, int grid, hipStream_t stream) {
+hipError_t launch_warp_single(const DevJob& job, int ppt, int grid, hipStream_t stream, bool near, float near_m) {
   const int wl = lds_width(job.width);
   const size_t lds = warp_lds_bytes(wl);
   switch (ppt) {
-#define X(P)                                                                                     \
-  case P: {                                                                                      \
-    hipError_t e = set_lds_limit((const void*)warp_single_kernel<P>, lds);                       \
-    if (e != hipSuccess) return e;                                                               \
-    hipLaunchKernelGGL(warp_single_kernel<P>, dim3(grid), dim3(kThreads), lds, stream, job, wl); \
-    return hipGetLastError();                                                                    \
+#define X(P)                                                                                                 \
+  case P: {                                                                                                  \
+    const void* k = near ? (const void*)warp_single_kernel<P, true> : (const void*)warp_single_kernel<P, false>; \
+    hipError_t e = set_lds_limit(k, lds);                                                                    \
+    if (e != hipSuccess) return e;                                                                           \
+    if (near)                                                                                                \
+      hipLaunchKernelGGL((warp_single_kernel<P, true>), dim3(grid), dim3(kThreads), lds, stream, job, wl,    \
+                         near_m);                                                                            \
+    else                                                                                                     \
+      hipLaunchKernelGGL((warp_single_kernel<P, false>), dim3(grid), dim3(kThreads), lds, stream, job, wl,   \
+                         0.0f);                                                                              \
+    return hipGetLastError();                                                                                \
   }
     YORO_PPT_CASES(X)
 #undef X
@@ -638,9 +648,9 @@ int warp_blocks_per_cu(int max_width, bool batch) {
   switch (ppt) {
 #define X(P)                                                                                                      \
   case P:                                                                                                         \
-    (void)set_lds_limit(batch ? (const void*)warp_batch_kernel<P> : (const void*)warp_single_kernel<P>, lds);      \
+    (void)set_lds_limit(batch ? (const void*)warp_batch_kernel<P> : (const void*)warp_single_kernel<P, false>, lds); \
     e = batch ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, warp_batch_kernel<P>, kThreads, lds)            \
-              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, warp_single_kernel<P>, kThreads, lds);          \
+              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, warp_single_kernel<P, false>, kThreads, lds);   \
     break;
     YORO_PPT_CASES(X)
 #undef X

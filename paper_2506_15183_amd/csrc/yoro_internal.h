@@ -82,7 +82,9 @@ inline int lowres_texel_slots(int max_width, int lg) {
 }
 
 // Launchers (defined in warp_fill.hip).  They return hipSuccess or the launch error.
-hipError_t launch_warp_single(const DevJob& job, int ppt, int grid, hipStream_t stream);
+// near: the near-object hybrid's far field (source depth < near_m skipped).
+hipError_t launch_warp_single(const DevJob& job, int ppt, int grid, hipStream_t stream, bool near = false,
+                              float near_m = 0.0f);
 // The batch kernel's grid covers the flat row space once, kBatchRows
 // consecutive rows per workgroup (total_rows: the prepared batch's rows).
 constexpr int kBatchRows = 3;
@@ -155,6 +157,17 @@ hipError_t nn_composite_tiles(const float* res, const int* plan, int k, int crop
 // Occupancy-derived workgroups per CU for the row kernels.
 int warp_blocks_per_cu(int max_width, bool batch);
 int fill_blocks_per_cu(int width, int fill_mode);
+
+// The near-object hybrid (hybrid.hip): the near layer of a box-and-sphere
+// scene for one eye, and its composite over the far field.
+}  // namespace yoro
+struct yoro_object;
+namespace yoro {
+hipError_t launch_render_near(const ::yoro_object* objs, int n, int W, int H, int x_off, int y_off, double f,
+                              double cx, double cy, double eye_x, float near_m, uint32_t* rgba, float* depth,
+                              hipStream_t stream);
+hipError_t launch_composite_near(const uint32_t* near_rgba, const float* near_depth, float near_m, int64_t n,
+                                 uint32_t* rgba, float* depth, uint8_t* mask, int grid, hipStream_t stream);
 
 // Reprojection through a general pose (pose.hip): X_t = A X + b per pinhole
 // point, A = R^T and b = -R^T t of the target eye's pose in the source eye's

@@ -44,6 +44,9 @@ EXPORTS = (
 
 # include/yoro_measure.h
 MEASURE_EXPORTS = ("yoro_measure_stream",)
+# include/yoro_hybrid.h
+HYBRID_EXPORTS = ("yoro_reproject_hybrid", "yoro_render_near")
+MASK_NEAR = 3
 
 
 class YoroError(RuntimeError):
@@ -129,6 +132,11 @@ def load():
     L.yoro_stereo_batch_errors.restype = vp
     L.yoro_hole_sse.argtypes = [vp, vp, vp, i32, i32, vp, vp]
     L.yoro_hole_sse.restype = i32
+    L.yoro_reproject_hybrid.argtypes = [vp, vp, i32, i32, f32, f32, i32, i32, f32, vp, vp, vp, vp, vp, vp]
+    L.yoro_reproject_hybrid.restype = i32
+    f64 = ctypes.c_double
+    L.yoro_render_near.argtypes = [vp, i32, i32, i32, i32, i32, f64, f64, f64, f64, f32, vp, vp, vp]
+    L.yoro_render_near.restype = i32
     L.yoro_measure_stream.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
     L.yoro_measure_stream.restype = i32
     L.yoro_last_error.argtypes = []
@@ -237,6 +245,46 @@ def fill_holes(rgba, depth, mask, target_eye: int = TARGET_RIGHT, fill_mode: int
     _check(load().yoro_fill_holes(_ptr(rgba), _ptr(depth), _ptr(mask), W, H, int(target_eye), int(fill_mode),
                                   _model(model), _stream(stream)))
     return rgba, depth, mask
+
+
+def reproject_hybrid(src_rgba, src_depth, baseline_m: float, focal_px: float, target_eye: int, fill_mode: int,
+                     near_m: float, near_rgba, near_depth, out=None, with_depth: bool = True, with_mask: bool = True,
+                     stream=None):
+    """Near-object hybrid (include/yoro_hybrid.h): the far field warped and
+    filled, the target eye's near layer over it.  Returns (rgba, depth or
+    None, mask or None)."""
+    H, W = src_depth.shape
+    _need(src_rgba, torch.uint8, (H, W, 4), "src_rgba")
+    _need(src_depth, torch.float32, (H, W), "src_depth")
+    _need(near_rgba, torch.uint8, (H, W, 4), "near_rgba")
+    _need(near_depth, torch.float32, (H, W), "near_depth")
+    if out is None:
+        dev = src_depth.device
+        out = (torch.empty((H, W, 4), dtype=torch.uint8, device=dev),
+               torch.empty((H, W), dtype=torch.float32, device=dev) if with_depth else None,
+               torch.empty((H, W), dtype=torch.uint8, device=dev) if with_mask else None)
+    rgba, depth, mask = out
+    _check(load().yoro_reproject_hybrid(_ptr(src_rgba), _ptr(src_depth), W, H, float(baseline_m), float(focal_px),
+                                        int(target_eye), int(fill_mode), float(near_m), _ptr(near_rgba),
+                                        _ptr(near_depth), _ptr(rgba), _ptr(depth), _ptr(mask), _stream(stream)))
+    return rgba, depth, mask
+
+
+def render_near(objects, n: int, width: int, height: int, focal_px: float, cx: float, cy: float, eye_x: float,
+                near_m: float, x_off: int = 0, y_off: int = 0, out=None, stream=None):
+    """yoro_render_near: the near layer of one eye.  objects: a CUDA uint8
+    tensor holding n yoro_object records (88 bytes each).  Returns (rgba, depth)."""
+    if objects.dtype != torch.uint8 or not objects.is_cuda or objects.numel() < 88 * n:
+        raise ValueError("render_near: objects must be a CUDA uint8 tensor of n * 88 bytes")
+    dev = objects.device
+    if out is None:
+        out = (torch.empty((height, width, 4), dtype=torch.uint8, device=dev),
+               torch.empty((height, width), dtype=torch.float32, device=dev))
+    rgba, depth = out
+    _check(load().yoro_render_near(_ptr(objects), int(n), int(width), int(height), int(x_off), int(y_off),
+                                   float(focal_px), float(cx), float(cy), float(eye_x), float(near_m), _ptr(rgba),
+                                   _ptr(depth), _stream(stream)))
+    return rgba, depth
 
 
 def make_job(src_rgba, src_depth, dst_rgba, dst_depth, dst_mask, baseline_m, focal_px,

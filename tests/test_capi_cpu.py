@@ -31,7 +31,7 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, name), name
     assert set(header_functions()) == set(yoro.EXPORTS)
     assert yoro.version() == 1
-    for header in ("yoro_nn.h", "yoro_model.h", "yoro_serve.h", "yoro_measure.h"):
+    for header in ("yoro_nn.h", "yoro_model.h", "yoro_serve.h", "yoro_measure.h", "yoro_hybrid.h"):
         names = header_functions(header)
         assert names, header
         for name in names:
@@ -40,6 +40,7 @@ def test_library_exports_every_declared_symbol():
 
     assert set(header_functions("yoro_serve.h")) == set(serve.EXPORTS)
     assert set(header_functions("yoro_measure.h")) == set(yoro.MEASURE_EXPORTS)
+    assert set(header_functions("yoro_hybrid.h")) == set(yoro.HYBRID_EXPORTS)
     # the streaming kernel's host checks: misaligned, overlapping, empty
     L = yoro.load()
     a, b, c = ctypes.c_void_p(0x100000), ctypes.c_void_p(0x200000), ctypes.c_void_p(0x300000)
@@ -94,6 +95,22 @@ def test_host_validation_rejects_without_launching():
     inside = ctypes.c_void_p(0x10000 + 16)
     assert L.yoro_reproject(fake, fake2, 8, 8, 0.06, 900.0, 0, 1, inside, None, None, None) == yoro.ERR_INVALID_ARG
     assert b"overlap" in L.yoro_last_error()
+    # the near-object hybrid: near_m finite and > 0, the near layer present and
+    # clear of the outputs, no learned fill
+    nr, nd = ctypes.c_void_p(0x60000000), ctypes.c_void_p(0x64000000)
+    for nm in (0.0, -1.0, float("nan"), float("inf")):
+        assert L.yoro_reproject_hybrid(fake, fake2, 8, 8, 0.06, 900.0, 0, 1, nm, nr, nd, fake3, None, None,
+                                       None) == yoro.ERR_INVALID_ARG
+    assert L.yoro_reproject_hybrid(fake, fake2, 8, 8, 0.06, 900.0, 0, 1, 1.0, None, nd, fake3, None, None,
+                                   None) == yoro.ERR_INVALID_ARG
+    assert L.yoro_reproject_hybrid(fake, fake2, 8, 8, 0.06, 900.0, 0, 1, 1.0, fake3, nd, fake3, None, None,
+                                   None) == yoro.ERR_INVALID_ARG                        # output over the layer
+    assert L.yoro_reproject_hybrid(fake, fake2, 8, 8, 0.06, 900.0, 0, yoro.FILL_LEARNED, 1.0, nr, nd, fake3, None,
+                                   None, None) == yoro.ERR_UNSUPPORTED
+    assert L.yoro_render_near(None, 3, 8, 8, 0, 0, 900.0, 4.0, 4.0, 0.0, 1.0, fake, fake2, None) == yoro.ERR_INVALID_ARG
+    assert L.yoro_render_near(fake3, -1, 8, 8, 0, 0, 900.0, 4.0, 4.0, 0.0, 1.0, fake, fake2, None) == yoro.ERR_INVALID_ARG
+    assert L.yoro_render_near(fake3, 3, 8, 8, 0, 0, 0.0, 4.0, 4.0, 0.0, 1.0, fake, fake2, None) == yoro.ERR_INVALID_ARG
+    assert L.yoro_render_near(fake3, 3, 8, 8, 0, 0, 900.0, 4.0, 4.0, 0.0, 0.0, fake, fake2, None) == yoro.ERR_INVALID_ARG
     # fill_holes
     assert L.yoro_fill_holes(None, fake2, fake3, 8, 8, 0, 1, None, None) == yoro.ERR_INVALID_ARG
     # the learned fill: only with a model, sizes multiples of 8, workspace large enough
