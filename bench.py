@@ -312,6 +312,7 @@ def main():
 
         t1 = time.time()
         quality = evaluate.evaluate(net, args.eval_frames)
+        quality["hybrid"] = evaluate.evaluate_hybrid(net, min(args.eval_frames, 8))
         log(f"hole PSNR ({time.time() - t1:.1f}s): {quality}")
         learned_roof = {"bound": "mfma", "achieved": quality["learned_tflops"], "peak": evaluate.BF16_PEAK_TFLOPS,
                         "unit": "TFLOP/s", "frac": quality["learned_frac_of_bf16_peak"],

@@ -1,5 +1,6 @@
-"""Hole PSNR of the plain nearest-background fill, the paper's Patcher and
-the learned fill against the ray-cast target eye on held-out full frames,
+"""Hole PSNR of the plain nearest-background fill, the paper's Patcher,
+the learned fill and the near-object hybrid against the ray-cast target eye
+on held-out full frames,
 the learned fill's inference throughput, and the whole-image error of the
 reprojection through a downsampled intermediate buffer at scales 2-16.
 
@@ -165,6 +166,62 @@ def evaluate_sparse(net: unet.UNet, n_frames: int = 8):
             "hole_psnr_learned_db": round(_psnr(*pooled[1]), 3)}
 
 
+def evaluate_hybrid(net: unet.UNet, n_frames: int = 8, nears=(0.5, 1.0)):
+    """The near-object hybrid (Section 11.4) beside the three fills, on the
+    held-out 1832 x 1920 frames (objects from 0.3 m): every method's error
+    against the ray-cast target eye over the plain path's hole pixels and
+    over the whole image.  The hybrid renders the near field (surfaces
+    nearer than near_m) for the target eye with yoro_render_near and warps
+    and fills the rest with the plain fill; its time per frame is the near
+    render plus the hybrid warp."""
+    dev = net.device
+    names = ["plain", "patcher", "learned"] + [f"hybrid_{d:g}m" for d in nears]
+    holes = {k: np.zeros(2, dtype=np.int64) for k in names}
+    whole = {k: np.zeros(2, dtype=np.int64) for k in names}
+    near_frac = {d: [] for d in nears}
+    left_frac = {d: [] for d in nears}
+    times = {d: [] for d in nears}
+    for i, spec in enumerate(config4_test_frames(n_frames)):
+        sc = spec.scene()
+        s_rgba, s_depth = spec.render_source()
+        t_rgba, _ = spec.render_target()
+        src = torch.from_numpy(s_rgba).to(dev)
+        srd = torch.from_numpy(s_depth).to(dev)
+        tgt = torch.from_numpy(t_rgba).to(dev)
+        raw = bytes(memoryview(sc.objects).cast("B"))[: 88 * sc.n]
+        objs = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(dev)
+        rgba, depth, mask = yoro.reproject(src, srd, spec.baseline_m, spec.focal_px, spec.target_eye,
+                                           yoro.FILL_NEAREST_BG)
+        outs = {"plain": rgba,
+                "patcher": yoro.reproject(src, srd, spec.baseline_m, spec.focal_px, spec.target_eye,
+                                          yoro.FILL_PATCHER)[0],
+                "learned": net.fill_native(rgba[None], depth[None], mask[None])[0]}
+        for d in nears:
+            ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            ev[0].record()
+            nr, nd = yoro.render_near(objs, sc.n, spec.width, spec.height, sc.f, 0.5 * sc.Wv, 0.5 * sc.Hv,
+                                      spec.target_eye_x(), d)
+            hr, _, hm = yoro.reproject_hybrid(src, srd, spec.baseline_m, spec.focal_px, spec.target_eye,
+                                              yoro.FILL_NEAREST_BG, d, nr, nd)
+            ev[1].record()
+            torch.cuda.synchronize()
+            times[d].append(ev[0].elapsed_time(ev[1]))
+            outs[f"hybrid_{d:g}m"] = hr
+            near_frac[d].append(float((hm == yoro.MASK_NEAR).float().mean().item()))
+            left_frac[d].append(float(((hm == 1) | (hm == 2)).float().mean().item()))
+        for k, o in outs.items():
+            holes[k] += _sse(o, tgt, mask)
+            whole[k] += _sse(o, tgt, None)
+    res = {"frames": n_frames, "size": "1832x1920", "hole_pixels": int(holes["plain"][1]),
+           "hole_psnr_db": {k: round(_psnr(*v), 3) for k, v in holes.items()},
+           "image_psnr_db": {k: round(_psnr(*v), 3) for k, v in whole.items()}}
+    for d in nears:
+        res[f"hybrid_{d:g}m"] = {"near_fraction": round(float(np.mean(near_frac[d])), 4),
+                                 "far_holes_fraction": round(float(np.mean(left_frac[d])), 4),
+                                 "render_and_warp_ms_per_frame": round(float(np.median(times[d][1:] or times[d])), 4)}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--frames", type=int, default=16)
@@ -172,6 +229,7 @@ def main():
     a = ap.parse_args()
     net = unet.UNet("cuda", params=train.load_weights(a.weights))
     res = evaluate(net, a.frames, log=lambda m: print(m, file=sys.stderr, flush=True))
+    res["hybrid"] = evaluate_hybrid(net, min(a.frames, 8))
     print(json.dumps(res), flush=True)
 
 
