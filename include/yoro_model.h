@@ -77,6 +77,21 @@ int32_t yoro_model_fill_tiles(const void* weights, const uint8_t* rgba, const fl
                               int32_t chunk, uint8_t* out, void* workspace, size_t workspace_bytes,
                               void* hip_stream);
 
+/* Learned fill of one w x h frame in bands of `band` full-width rows: band
+ * b covers rows [b band, b band + band) and runs on the crop of rows
+ * [b band - halo, b band + band + halo), shifted inward at the frame's top
+ * and bottom (band, halo, w, h multiples of 8, halo <= band / 2).  With halo
+ * at or above the network's reach (54 pixels) the result equals
+ * yoro_model_fill bit for bit, at about (band + 2 halo) / band of its work
+ * and with the workspace of one crop.  band_has_holes: host, one byte per
+ * band (NULL: every band); a band without holes is skipped (its pixels are
+ * not written).  out may equal rgba: a band is written only after every
+ * band pass that reads its rows. */
+size_t yoro_model_bands_workspace_bytes(int32_t w, int32_t h, int32_t band, int32_t halo);
+int32_t yoro_model_fill_bands(const void* weights, const uint8_t* rgba, const float* depth, const uint8_t* mask,
+                              int32_t w, int32_t h, int32_t band, int32_t halo, const uint8_t* band_has_holes,
+                              uint8_t* out, void* workspace, size_t workspace_bytes, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

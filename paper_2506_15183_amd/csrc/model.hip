@@ -220,6 +220,23 @@ int32_t yoro_model_fill(const void* weights, const uint8_t* rgba, const float* d
   return launched(e, who);
 }
 
+size_t yoro_model_bands_workspace_bytes(int32_t w, int32_t h, int32_t band, int32_t halo) {
+  if (w <= 0 || h <= 0 || w % 8 || h % 8 || band <= 0 || band % 8 || halo < 0 || halo % 8 || 2 * halo > band)
+    return 0;
+  const int ch = band + 2 * halo < h ? band + 2 * halo : h;
+  if (!shape_ok(1, ch, w)) return 0;
+  // The activations of one band crop (their residual buffer is the first of
+  // three residual buffers) and two more residual buffers.
+  return carve(nullptr, 1, ch, w, nullptr) + 2 * (((size_t)ch * w * 3 * 4 + 255) & ~(size_t)255);
+}
+
+int32_t yoro_model_fill_bands(const void* weights, const uint8_t* rgba, const float* depth, const uint8_t* mask,
+                              int32_t w, int32_t h, int32_t band, int32_t halo, const uint8_t* band_has_holes,
+                              uint8_t* out, void* workspace, size_t workspace_bytes, void* hip_stream) {
+  return yoro::model_fill_bands_paced(weights, rgba, depth, mask, w, h, band, halo, band_has_holes, out, workspace,
+                                      workspace_bytes, hip_stream, std::function<hipError_t()>());
+}
+
 size_t yoro_model_tiles_workspace_bytes(int32_t k, int32_t chunk, int32_t tile, int32_t halo) {
   if (k <= 0 || chunk <= 0 || tile <= 0 || halo < 0 || k > 65535) return 0;
   const int crop = tile + 2 * halo;
@@ -238,6 +255,73 @@ int32_t yoro_model_fill_tiles(const void* weights, const uint8_t* rgba, const fl
 }  // extern "C"
 
 namespace yoro {
+
+// Bands of `band` rows, each run on the crop of rows [y0 - halo, y0 + band +
+// halo) clamped inward to the frame (full width: a contiguous row range of
+// the frame, read in place).  A band's composite writes `out`, which may be
+// `rgba`, so it is queued only once no later band's crop reaches its rows
+// (crops only move down, so that is when the next crop starts below it).
+// With halo <= band / 2 at most two bands wait at a time (the last crop,
+// shifted up at a short last band, can reach two bands back): three
+// residual buffers in turn.
+int32_t model_fill_bands_paced(const void* weights, const uint8_t* rgba, const float* depth, const uint8_t* mask,
+                               int32_t w, int32_t h, int32_t band, int32_t halo, const uint8_t* band_has_holes,
+                               uint8_t* out, void* workspace, size_t workspace_bytes, void* hip_stream,
+                               const std::function<hipError_t()>& between) {
+  const char* who = "yoro_model_fill_bands";
+  if (!weights || !rgba || !depth || !mask || !out || !workspace)
+    return model_fail(YORO_ERR_INVALID_ARG, "%s: null pointer", who);
+  const size_t need = yoro_model_bands_workspace_bytes(w, h, band, halo);
+  if (need == 0)
+    return model_fail(YORO_ERR_INVALID_ARG, "%s: bad frame %d x %d, band %d or halo %d (multiples of 8, halo <= band/2)",
+                      who, w, h, band, halo);
+  if (!al16(weights) || !al4(rgba) || !al4(depth) || !al4(out) || !al16(workspace))
+    return model_fail(YORO_ERR_INVALID_ARG, "%s: misaligned pointer", who);
+  if (workspace_bytes < need) return model_fail(YORO_ERR_WORKSPACE_TOO_SMALL, "%s: workspace too small", who);
+  const int ch = band + 2 * halo < h ? band + 2 * halo : h;
+  Acts a;
+  const size_t used = carve(static_cast<char*>(workspace), 1, ch, w, &a);
+  const size_t rbytes = ((size_t)ch * w * 3 * 4 + 255) & ~(size_t)255;
+  float* res[3] = {a.res, reinterpret_cast<float*>(static_cast<char*>(workspace) + used),
+                   reinterpret_cast<float*>(static_cast<char*>(workspace) + used + rbytes)};
+  hipStream_t s = (hipStream_t)hip_stream;
+  const int nb = (h + band - 1) / band;
+  auto crop_of = [&](int b) {
+    int oy = b * band - halo;
+    return oy < 0 ? 0 : (oy > h - ch ? h - ch : oy);
+  };
+  struct Pending {
+    int b, oy;
+  };
+  Pending q[3];
+  int nq = 0;
+  hipError_t e = hipSuccess;
+  auto composite = [&](const Pending& p) {
+    const int y0 = p.b * band, rows = (y0 + band < h ? band : h - y0);
+    const long long off = (long long)y0 * w;
+    return yoro::nn_composite(res[p.b % 3] + (long long)(y0 - p.oy) * w * 3,
+                              reinterpret_cast<const uint32_t*>(rgba) + off, mask + off, (long long)rows * w,
+                              reinterpret_cast<uint32_t*>(out) + off, s);
+  };
+  for (int b = 0; b < nb && e == hipSuccess; ++b) {
+    if (band_has_holes && !band_has_holes[b]) continue;
+    const int oy = crop_of(b);
+    // Bands whose rows this crop (and every later one) no longer reaches.
+    while (nq > 0 && e == hipSuccess && (q[0].b + 1) * band <= oy) {
+      e = composite(q[0]);
+      q[0] = q[1], q[1] = q[2], --nq;
+    }
+    if (e != hipSuccess) break;
+    const long long off = (long long)oy * w;
+    Acts ab = a;
+    ab.res = res[b % 3];
+    e = forward(static_cast<const uint16_t*>(weights), rgba + 4 * off, depth + off, mask + off, 1, ch, w, ab, s);
+    q[nq++] = Pending{b, oy};
+    if (e == hipSuccess && between) e = between();
+  }
+  for (int i = 0; i < nq && e == hipSuccess; ++i) e = composite(q[i]);
+  return launched(e, who);
+}
 
 int32_t model_fill_tiles_paced(const void* weights, const uint8_t* rgba, const float* depth, const uint8_t* mask,
                                int32_t w, int32_t h, const int32_t* plan, int32_t k, int32_t tile, int32_t halo,

@@ -49,6 +49,7 @@ constexpr int kConvThreads = 256;  // 4 waves
 constexpr int kTileH = 8, kTileW = 32;
 constexpr int kPatchH = kTileH + 2, kPatchW = kTileW + 2;
 constexpr int kPatchStride = 40;
+constexpr int kPatchLoads = (kPatchH * kPatchW * 4 + kConvThreads - 1) / kConvThreads;  // 16-byte loads per thread
 
 constexpr float kLogZmin = -1.2039728043259361f;  // log(0.3)
 constexpr float kLogZmax = 3.912023005428146f;    // log(50)
@@ -68,8 +69,15 @@ __device__ __forceinline__ u32x4 input_channels(uint32_t c, float z, uint8_t m) 
   return u32x4{(uint32_t)v[0] | ((uint32_t)v[1] << 16), (uint32_t)v[2] | ((uint32_t)v[3] << 16), (uint32_t)v[4], 0u};
 }
 
-template <int CT>
-__global__ __launch_bounds__(kConvThreads) void conv3x3_tiled_kernel(const uint16_t* __restrict__ x, int ldx, int N,
+// Waves per SIMD (the VGPR budget) for a CT-wide output tile: what the LDS
+// of one workgroup (patch + CT channels of weights) lets fit, and no more
+// than the registers of the prefetched patch leave room for without spills.
+constexpr int conv_waves(int ct) { return ct <= 32 ? 3 : 2; }
+
+// RAW: the first layer, whose input is the frame itself (raw_rgba, ...).
+template <int CT, bool RAW>
+__global__ __launch_bounds__(kConvThreads) __attribute__((amdgpu_waves_per_eu(conv_waves(CT)))) void
+conv3x3_tiled_kernel(const uint16_t* __restrict__ x, int ldx, int N,
                                                                      int H, int W, int Cin,
                                                                      const uint16_t* __restrict__ wgt, int Cout,
                                                                      void* __restrict__ y, int ldy, int y_fp32,
@@ -96,8 +104,7 @@ __global__ __launch_bounds__(kConvThreads) void conv3x3_tiled_kernel(const uint1
     }
   };
   // With one input chunk the weights stay in LDS for every tile this
-  // workgroup takes (the launch is then persistent); otherwise each chunk of
-  // each tile stages its own.
+  // workgroup takes; otherwise each chunk of each tile stages its own.
   const bool one_chunk = Cin == 32;
   if (one_chunk) stage_weights(0);
   // Tiles v = blockIdx.x, + gridDim.x, ... in an XCD-aware order: workgroup
@@ -105,46 +112,84 @@ __global__ __launch_bounds__(kConvThreads) void conv3x3_tiled_kernel(const uint1
   // count), and each XCD takes one contiguous range of tiles, so tiles that
   // share halo rows share an L2.
   const int q8 = ntiles >> 3, r8 = ntiles & 7;
-  for (int v = blockIdx.x; v < ntiles; v += gridDim.x) {
-  const int xc = v & 7;
-  int b = xc * q8 + min(xc, r8) + (v >> 3);
-  const int tx = b % tiles_x;
-  b /= tiles_x;
-  const int ty = b % tiles_y;
-  const int n = b / tiles_y;
-  const int x0 = tx * kTileW, y0 = ty * kTileH;
-  const long long img = (long long)n * H * W;
+  auto origin = [&](int v, int& x0, int& y0, int& n) {
+    const int xc = v & 7;
+    int b = xc * q8 + min(xc, r8) + (v >> 3);
+    const int tx = b % tiles_x;
+    b /= tiles_x;
+    const int ty = b % tiles_y;
+    n = b / tiles_y;
+    x0 = tx * kTileW;
+    y0 = ty * kTileH;
+  };
+  // The workgroup's items are (tile, 32-channel input chunk) in order.  The
+  // next item's patch is loaded into registers before this item's MFMAs and
+  // stores go out, and written to LDS at the next item's start, so the loads
+  // are in flight while this item computes.  Every lane loads (coordinates
+  // clamped into the frame, no branches, so no load has to land before the
+  // next is issued); which lanes lie outside the frame is kept as a bit mask
+  // and their values are zeroed when written to LDS.  The first layer's
+  // frame values are held raw (colour, depth bits, mask) and packed then.
+  u32x4 pre[kPatchLoads];
+  uint32_t inside_bits = 0;
+  auto load_patch = [&](int v, int ci0) {
+    int x0, y0, n;
+    origin(v, x0, y0, n);
+    const long long img = (long long)n * H * W;
+    inside_bits = 0;
+#pragma unroll
+    for (int k = 0; k < kPatchLoads; ++k) {
+      const int e = threadIdx.x + k * kConvThreads;
+      const int pix = e >> 2, part = e & 3;
+      const int py = pix / kPatchW, px = pix - py * kPatchW;
+      const int gy = y0 + py - 1, gx = x0 + px - 1;
+      const bool inside = e < kPatchH * kPatchW * 4 && gy >= 0 && gy < H && gx >= 0 && gx < W;
+      inside_bits |= (uint32_t)inside << k;
+      const int cy = min(max(gy, 0), H - 1), cx = min(max(gx, 0), W - 1);
+      if (RAW) {
+        const long long q = img + (long long)cy * W + cx;
+        pre[k] = u32x4{raw_rgba[q], __float_as_uint(raw_depth[q]), (uint32_t)raw_mask[q], 0u};
+      } else {
+        // ups: x is the half-resolution image and the input is its nearest
+        // x2 upsampling, read in place.
+        const long long src = ups ? (img >> 2) + (long long)(cy >> 1) * (W >> 1) + (cx >> 1)
+                                  : img + (long long)cy * W + cx;
+        pre[k] = *reinterpret_cast<const u32x4*>(x + src * ldx + ci0 + part * 8);
+      }
+    }
+  };
+  auto store_patch = [&]() {
+#pragma unroll
+    for (int k = 0; k < kPatchLoads; ++k) {
+      const int e = threadIdx.x + k * kConvThreads;
+      if (e >= kPatchH * kPatchW * 4) continue;
+      const bool inside = (inside_bits >> k) & 1u;
+      u32x4 v = pre[k];
+      // The first layer: its packed input (Cin 32) built channel by channel
+      // as the input-packing kernel does, in the first 8 channels.
+      if (RAW) v = (e & 3) == 0 ? input_channels(v[0], __uint_as_float(v[1]), (uint8_t)v[2]) : u32x4{0u, 0u, 0u, 0u};
+      if (!inside) v = u32x4{0u, 0u, 0u, 0u};
+      *reinterpret_cast<u32x4*>(patch + (e >> 2) * kPatchStride + (e & 3) * 8) = v;
+    }
+  };
   floatx4 acc[4][NB];
 #pragma unroll
   for (int m = 0; m < 4; ++m)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[m][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
-
-  for (int ci0 = 0; ci0 < Cin; ci0 += 32) {
-    __syncthreads();  // the previous chunk's (or tile's) readers are done with the patch
-    for (int e = threadIdx.x; e < kPatchH * kPatchW * 4; e += kConvThreads) {
-      const int pix = e >> 2, part = e & 3;
-      const int py = pix / kPatchW, px = pix - py * kPatchW;
-      const int gy = y0 + py - 1, gx = x0 + px - 1;
-      u32x4 v = {0u, 0u, 0u, 0u};
-      if (raw_rgba) {
-        // The first layer reads the frame itself: its packed input (Cin 32)
-        // is built here, channel by channel as the input-packing kernel does.
-        if (part == 0 && gy >= 0 && gy < H && gx >= 0 && gx < W) {
-          const long long q = img + (long long)gy * W + gx;
-          v = input_channels(raw_rgba[q], raw_depth[q], raw_mask[q]);
-        }
-      } else if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
-        // ups: x is the half-resolution image and the input is its nearest
-        // x2 upsampling, read in place.
-        const long long src = ups ? (img >> 2) + (long long)(gy >> 1) * (W >> 1) + (gx >> 1)
-                                  : img + (long long)gy * W + gx;
-        v = *reinterpret_cast<const u32x4*>(x + src * ldx + ci0 + part * 8);
-      }
-      *reinterpret_cast<u32x4*>(patch + pix * kPatchStride + part * 8) = v;
-    }
+  int v = blockIdx.x, ci0 = 0;
+  if (v < ntiles) load_patch(v, 0);
+  while (v < ntiles) {
+    __syncthreads();  // the previous item's readers are done with the patch (and the weights)
+    store_patch();
     if (!one_chunk) stage_weights(ci0);
+    int vn = v, cn = ci0 + 32;
+    if (cn == Cin) {
+      vn = v + gridDim.x;
+      cn = 0;
+    }
     __syncthreads();
+    if (vn < ntiles) load_patch(vn, cn);
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
       u32x4 bcur[NB];
@@ -163,7 +208,14 @@ __global__ __launch_bounds__(kConvThreads) void conv3x3_tiled_kernel(const uint1
                                                                0);
       }
     }
-  }
+    if (cn != 0) {  // more input chunks of this tile to come
+      v = vn;
+      ci0 = cn;
+      continue;
+    }
+  int x0, y0, n;
+  origin(v, x0, y0, n);
+  const long long img = (long long)n * H * W;
   // Epilogue: lane holds channel co0 + 16nb + lane%16 of pixels 4*(lane/16)+r
   // of M tile m, i.e. row 2*wave + m/2, column 16*(m%2) + 4*(lane/16) + r.
 #pragma unroll
@@ -217,7 +269,13 @@ __global__ __launch_bounds__(kConvThreads) void conv3x3_tiled_kernel(const uint1
       }
     }
   }
-  }  // tiles
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[m][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+  v = vn;
+  ci0 = cn;
+  }  // items
 }
 
 // ---------------------------------------------------------- weight grad --
@@ -736,11 +794,11 @@ int device_cus() {
   return c;
 }
 
-template <int CT>
+template <int CT, bool RAW>
 int conv_blocks_per_cu() {
   static const int nb = [] {
     int v = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, conv3x3_tiled_kernel<CT>, kConvThreads, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, conv3x3_tiled_kernel<CT, RAW>, kConvThreads, 0) != hipSuccess)
       v = 0;
     return v > 0 ? v : 1;
   }();
@@ -757,26 +815,30 @@ hipError_t conv3x3_launch(const uint16_t* x, int ldx, int N, int H, int W, int C
   const int nt = (int)tiles;
   // One workgroup per tile, or, with one input chunk (weights staged once per
   // workgroup), a persistent grid of the workgroups that fit, a multiple of 8.
-  auto grid_x = [&](int per_cu) -> unsigned {
-    if (Cin != 32) return (unsigned)nt;
-    const long long g = ((long long)device_cus() * per_cu) & ~7LL;
+  // A persistent grid: the workgroups that fit at once (over the ny blocks of
+  // output channels), a multiple of 8, each looping over tiles; its next
+  // item's patch loads overlap the current item's MFMAs across tiles too.
+  auto grid_x = [&](int per_cu, int ny) -> unsigned {
+    const long long g = ((long long)device_cus() * per_cu / ny) & ~7LL;
     return (unsigned)(g >= 8 && g < nt ? g : nt);
   };
-  if (cout_store <= 16) {  // e.g. the 3-channel head: only the first 16 outputs are computed
-    hipLaunchKernelGGL(conv3x3_tiled_kernel<16>, dim3(grid_x(conv_blocks_per_cu<16>()), 1),
+  if (raw_rgba) {  // the first layer (Cin 32, Cout a multiple of 32)
+    if (Cin != 32 || Cout % 32 != 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((conv3x3_tiled_kernel<32, true>), dim3(grid_x(conv_blocks_per_cu<32, true>(), Cout / 32), Cout / 32),
                        dim3(kConvThreads), 0, s, x, ldx, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi,
-                       msrc, ldm, ups, nt, pool, ldp, raw_rgba, raw_depth,
-                       raw_mask);
+                       msrc, ldm, ups, nt, pool, ldp, raw_rgba, raw_depth, raw_mask);
+  } else if (cout_store <= 16) {  // e.g. the 3-channel head: only the first 16 outputs are computed
+    hipLaunchKernelGGL((conv3x3_tiled_kernel<16, false>), dim3(grid_x(conv_blocks_per_cu<16, false>(), 1), 1),
+                       dim3(kConvThreads), 0, s, x, ldx, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi,
+                       msrc, ldm, ups, nt, pool, ldp, raw_rgba, raw_depth, raw_mask);
   } else if (Cout % 64 == 0) {
-    hipLaunchKernelGGL(conv3x3_tiled_kernel<64>, dim3(grid_x(conv_blocks_per_cu<64>()), Cout / 64),
+    hipLaunchKernelGGL((conv3x3_tiled_kernel<64, false>), dim3(grid_x(conv_blocks_per_cu<64, false>(), Cout / 64), Cout / 64),
                        dim3(kConvThreads), 0, s, x, ldx, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi,
-                       msrc, ldm, ups, nt, pool, ldp, raw_rgba, raw_depth,
-                       raw_mask);
+                       msrc, ldm, ups, nt, pool, ldp, raw_rgba, raw_depth, raw_mask);
   } else {
-    hipLaunchKernelGGL(conv3x3_tiled_kernel<32>, dim3(grid_x(conv_blocks_per_cu<32>()), Cout / 32),
+    hipLaunchKernelGGL((conv3x3_tiled_kernel<32, false>), dim3(grid_x(conv_blocks_per_cu<32, false>(), Cout / 32), Cout / 32),
                        dim3(kConvThreads), 0, s, x, ldx, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi,
-                       msrc, ldm, ups, nt, pool, ldp, raw_rgba, raw_depth,
-                       raw_mask);
+                       msrc, ldm, ups, nt, pool, ldp, raw_rgba, raw_depth, raw_mask);
   }
   return hipGetLastError();
 }

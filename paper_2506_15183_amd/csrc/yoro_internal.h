@@ -119,6 +119,12 @@ int32_t model_fill_tiles_paced(const void* weights, const uint8_t* rgba, const f
                                int32_t chunk, uint8_t* out, void* workspace, size_t workspace_bytes,
                                void* hip_stream, const std::function<hipError_t()>& between);
 
+// yoro_model_fill_bands with a host call between bands, as above.
+int32_t model_fill_bands_paced(const void* weights, const uint8_t* rgba, const float* depth, const uint8_t* mask,
+                               int32_t w, int32_t h, int32_t band, int32_t halo, const uint8_t* band_has_holes,
+                               uint8_t* out, void* workspace, size_t workspace_bytes, void* hip_stream,
+                               const std::function<hipError_t()>& between);
+
 hipError_t nn_conv3x3_input(const uint32_t* rgba, const float* depth, const uint8_t* mask, int N, int H, int W,
                             const uint16_t* wgt, int Cout, uint16_t* y, int ldy, int relu, hipStream_t s);
 // The convolution (bf16 output, optional ReLU) followed by a 2x2 average

@@ -73,6 +73,7 @@ def nnlib():
             "yoro_model_residual": [vp, vp, vp, vp, i32, i32, i32, vp, vp, sz, vp],
             "yoro_model_fill": [vp, vp, vp, vp, i32, i32, i32, vp, vp, sz, vp],
             "yoro_model_fill_tiles": [vp, vp, vp, vp, i32, i32, vp, i32, i32, i32, i32, vp, vp, sz, vp],
+            "yoro_model_fill_bands": [vp, vp, vp, vp, i32, i32, i32, i32, vp, vp, vp, sz, vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -86,6 +87,8 @@ def nnlib():
         L.yoro_model_workspace_layout.restype = i32
         L.yoro_model_workspace_bytes.argtypes = [i32, i32, i32]
         L.yoro_model_workspace_bytes.restype = sz
+        L.yoro_model_bands_workspace_bytes.argtypes = [i32, i32, i32, i32]
+        L.yoro_model_bands_workspace_bytes.restype = sz
         L.yoro_model_tiles_workspace_bytes.argtypes = [i32, i32, i32, i32]
         L.yoro_model_tiles_workspace_bytes.restype = sz
         _nn = L
@@ -416,6 +419,24 @@ class UNet:
         _ok(L.yoro_model_fill_tiles(_p(self.wf), _p(rgba), _p(depth), _p(mask), w, h, _p(plan_d), k, tile, halo, chunk,
                                     _p(out), _p(ws), nbytes, yoro._stream(stream)))
         return out, k
+
+    def fill_bands(self, rgba, depth, mask, out=None, band: int = 256, halo: int = HALO, band_has_holes=None,
+                   stream=None):
+        """Learned fill of one frame in full-width bands (yoro_model_fill_bands);
+        equal to fill_native bit for bit with halo >= boundary_reach()."""
+        h, w = depth.shape
+        L = nnlib()
+        if out is None:
+            out = rgba.clone()
+        nbytes = L.yoro_model_bands_workspace_bytes(w, h, band, halo)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        flags = None
+        if band_has_holes is not None:
+            flags = np.ascontiguousarray(band_has_holes, dtype=np.uint8)
+        _ok(L.yoro_model_fill_bands(_p(self.wf), _p(rgba), _p(depth), _p(mask), w, h, band, halo,
+                                    None if flags is None else flags.ctypes.data, _p(out), _p(ws), nbytes,
+                                    yoro._stream(stream)))
+        return out
 
     def fill_native(self, rgba, depth, mask, out=None, stream=None):
         """fill() through the library's own forward sequence (yoro_model_fill)."""

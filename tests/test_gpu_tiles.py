@@ -193,3 +193,40 @@ def test_native_forward_equals_the_python_sequence(cuda):
     # A short workspace is refused before anything runs.
     assert L.yoro_model_fill(G._p(net.wf), G._p(a), G._p(d), G._p(m), n, h, w, G._p(a), G._p(ws), nbytes - 1,
                              None) == 3
+
+
+@pytest.mark.parametrize("band,halo", [(256, 64), (128, 64), (512, 64)])
+def test_fill_bands_equals_whole_frame_fill(cuda, band, halo):
+    """Full-width bands (yoro_model_fill_bands), in place and out of place,
+    with and without skipped bands, equal the whole-frame learned fill bit for
+    bit at the serving sizes (short last bands included)."""
+    torch, G = _t()
+    rng = np.random.default_rng(band + halo)
+    net = G.UNet("cuda", params=_strong_head(G, 5))
+    for (w, h) in ((1440, 1600), (1832, 1920), (2160, 2160), (256, 200)):
+        rgba, depth, mask = _frame(rng, h, w)
+        a, d, m = _dev(torch, rgba, depth, mask)
+        want = net.fill_native(a[None], d[None], m[None])[0]
+        got = net.fill_bands(a, d, m, band=band, halo=halo)
+        torch.cuda.synchronize()
+        assert torch.equal(got, want), (w, h)
+        inplace = a.clone()
+        net.fill_bands(inplace, d, m, out=inplace, band=band, halo=halo)
+        torch.cuda.synchronize()
+        assert torch.equal(inplace, want), (w, h, "in place")
+    # Holes in two bands only: the other bands may be skipped.
+    w, h = 1832, 1920
+    rgba, depth, mask = _frame(rng, h, w)
+    keep = np.zeros((h, w), bool)
+    keep[300:340] = True
+    keep[1500:1510] = True
+    mask[~keep] = 0
+    a, d, m = _dev(torch, rgba, depth, mask)
+    nb = -(-h // band)
+    flags = [int(mask[b * band:(b + 1) * band].any()) for b in range(nb)]
+    assert 0 < sum(flags) < nb
+    want = net.fill_native(a[None], d[None], m[None])[0]
+    got = a.clone()
+    net.fill_bands(got, d, m, out=got, band=band, halo=halo, band_has_holes=flags)
+    torch.cuda.synchronize()
+    assert torch.equal(got, want)
