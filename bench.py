@@ -354,7 +354,8 @@ def main():
         runs = serve.run_interleaved(srv, trace, (serve.PLAIN, serve.LEARNED), rounds=2)
         serving["sparse_scenes"] = {
             "workload": f"as above with scenes of U{{20..60}} objects at depth >= 2 m, {sparse_s:g} s per policy "
-                        f"as two alternating rounds, refinement at most every {cfg_s.learned_min_interval_ms:g} ms",
+                        f"as two alternating rounds, refinement at most every {cfg_s.learned_min_interval_ms:g} ms, "
+                        f"in full-width bands of {cfg_s.band} rows",
             "plain": serve.summarize(*runs[serve.PLAIN], hs, sparse_s),
             "learned_policy": serve.summarize(*runs[serve.LEARNED], hs, sparse_s),
         }

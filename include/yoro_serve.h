@@ -13,9 +13,10 @@
  * device (on a stream of its own that the call creates and destroys, so
  * neither the plain stream nor a refinement delays it) and reads the counts
  * back; a frame whose hole fraction is at most
- * learned_max_hole_fraction is refined by yoro_model_fill_tiles on the
- * learned stream (in place, on the frame's output), the others keep the
- * plain fill.  A frame whose headset's previous counted frame was above the
+ * learned_max_hole_fraction is refined on the learned stream (in place, on
+ * the frame's output) by yoro_model_fill_tiles over its hole tiles, or, with
+ * band > 0, by yoro_model_fill_bands over the full-width bands that hold
+ * holes; the others keep the plain fill.  A frame whose headset's previous counted frame was above the
  * threshold is released as soon as its warp is done (fallback predicted, no
  * wait for its own count), and while a headset falls back its holes are
  * counted on every 8th frame only (holes = -1 in the results of the others).
@@ -33,9 +34,9 @@
  *
  * Streams: the plain work runs on hip_stream, the refinement on
  * options->learned_stream (both of default priority).  A worker thread of
- * the call enqueues each refinement one chunk of crops at a time and waits
- * for a chunk before it enqueues the next, so a warp that shares a hardware
- * queue with the refinement waits for one chunk at most.  The call returns
+ * the call enqueues each refinement one layer of the network at a time and
+ * keeps at most two layers queued, so a warp that shares a hardware queue
+ * with the refinement waits for two layers' kernels at most.  The call returns
  * when every admitted frame is final; it synchronises both streams at the
  * end.
  */
@@ -89,7 +90,9 @@ typedef struct yoro_serve_options {
   int32_t policy;                    /* yoro_serve_policy */
   float learned_max_hole_fraction;   /* refine only at or below this */
   const void* model_weights;         /* yoro_model.h weights (learned policy) */
-  void* learned_workspace;           /* yoro_model_tiles_workspace_bytes(max tiles, chunk, tile, halo) */
+  void* learned_workspace;           /* tiles: yoro_model_tiles_workspace_bytes(max tiles, chunk, tile,
+                                        halo); bands: the largest yoro_model_bands_workspace_bytes(w, h,
+                                        band, halo) of the admitted headsets */
   size_t learned_workspace_bytes;
   int32_t tile, halo, chunk;         /* hole-tile inference (yoro_model.h) */
   void* learned_stream;              /* hipStream_t for the refinement */
@@ -98,6 +101,9 @@ typedef struct yoro_serve_options {
                                         refinement is done; 1 releases every frame at its warp (plain
                                         fill, done_ns) and refines it afterwards in place, a hole tile
                                         at a time (refined_ns) */
+  int32_t band;                      /* learned policy: 0 refines hole tiles; > 0 refines the bands of
+                                        `band` full-width rows that hold holes (a multiple of tile,
+                                        2 halo <= band; headsets' sizes multiples of 8) */
 } yoro_serve_options;
 
 typedef struct yoro_serve_result {   /* one per arrival */

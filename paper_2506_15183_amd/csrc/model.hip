@@ -76,11 +76,13 @@ size_t carve(char* base, long long n, int h, int w, Acts* a) {
 
 // The forward pass; every step is a layer kernel of nn.hip.
 hipError_t forward(const uint16_t* wts, const uint8_t* rgba, const float* depth, const uint8_t* mask, int n, int h,
-                   int w, const Acts& a, hipStream_t s) {
+                   int w, const Acts& a, hipStream_t s, const std::function<hipError_t()>* pace = nullptr) {
   using namespace yoro;
   hipError_t e = hipSuccess;
+  // Every layer is one launch; the pacing call follows each.
   auto ok = [&](hipError_t r) {
     if (e == hipSuccess) e = r;
+    if (e == hipSuccess && pace && *pace) e = (*pace)();
   };
   auto conv = [&](int i, const uint16_t* x, int ldx, int lev, uint16_t* y, int ldy) {
     const Layer L = kLayers[i];
@@ -267,7 +269,7 @@ namespace yoro {
 int32_t model_fill_bands_paced(const void* weights, const uint8_t* rgba, const float* depth, const uint8_t* mask,
                                int32_t w, int32_t h, int32_t band, int32_t halo, const uint8_t* band_has_holes,
                                uint8_t* out, void* workspace, size_t workspace_bytes, void* hip_stream,
-                               const std::function<hipError_t()>& between) {
+                               const std::function<hipError_t()>& pace) {
   const char* who = "yoro_model_fill_bands";
   if (!weights || !rgba || !depth || !mask || !out || !workspace)
     return model_fail(YORO_ERR_INVALID_ARG, "%s: null pointer", who);
@@ -315,9 +317,9 @@ int32_t model_fill_bands_paced(const void* weights, const uint8_t* rgba, const f
     const long long off = (long long)oy * w;
     Acts ab = a;
     ab.res = res[b % 3];
-    e = forward(static_cast<const uint16_t*>(weights), rgba + 4 * off, depth + off, mask + off, 1, ch, w, ab, s);
+    e = forward(static_cast<const uint16_t*>(weights), rgba + 4 * off, depth + off, mask + off, 1, ch, w, ab, s,
+                &pace);
     q[nq++] = Pending{b, oy};
-    if (e == hipSuccess && between) e = between();
   }
   for (int i = 0; i < nq && e == hipSuccess; ++i) e = composite(q[i]);
   return launched(e, who);
@@ -326,7 +328,7 @@ int32_t model_fill_bands_paced(const void* weights, const uint8_t* rgba, const f
 int32_t model_fill_tiles_paced(const void* weights, const uint8_t* rgba, const float* depth, const uint8_t* mask,
                                int32_t w, int32_t h, const int32_t* plan, int32_t k, int32_t tile, int32_t halo,
                                int32_t chunk, uint8_t* out, void* workspace, size_t workspace_bytes,
-                               void* hip_stream, const std::function<hipError_t()>& between) {
+                               void* hip_stream, const std::function<hipError_t()>& pace) {
   const char* who = "yoro_model_fill_tiles";
   if (!weights || !rgba || !depth || !mask || !plan || !out || !workspace)
     return model_fail(YORO_ERR_INVALID_ARG, "%s: null pointer", who);
@@ -354,11 +356,10 @@ int32_t model_fill_tiles_paced(const void* weights, const uint8_t* rgba, const f
   for (int c0 = 0; c0 < k && e == hipSuccess; c0 += cmax) {
     const int kc = k - c0 < cmax ? k - c0 : cmax;
     e = forward(static_cast<const uint16_t*>(weights), reinterpret_cast<const uint8_t*>(crgba + c0 * cpx),
-                cdepth + c0 * cpx, cmask + c0 * cpx, kc, crop, crop, a, s);
+                cdepth + c0 * cpx, cmask + c0 * cpx, kc, crop, crop, a, s, &pace);
     if (e == hipSuccess)
       e = yoro::nn_composite_tiles(a.res, plan + 4 * c0, kc, crop, tile, w, h, reinterpret_cast<const uint32_t*>(rgba),
                                    mask, reinterpret_cast<uint32_t*>(out), s);
-    if (e == hipSuccess && between && c0 + cmax < k) e = between();
   }
   return launched(e, who);
 }

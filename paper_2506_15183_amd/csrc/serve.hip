@@ -71,7 +71,8 @@ bool options_ok(const yoro_serve_options* o) {
   if (learned(o) && (o->tile <= 0 || o->tile % 8 || o->halo < 0 || o->halo % 8 || o->chunk < 1 ||
                      !o->model_weights || !o->learned_workspace || !o->learned_stream ||
                      !(o->learned_max_hole_fraction >= 0.0f) || o->learned_min_interval_ns < 0 ||
-                     (o->progressive != 0 && o->progressive != 1)))
+                     (o->progressive != 0 && o->progressive != 1) || o->band < 0 ||
+                     (o->band > 0 && (o->band % o->tile || 2 * o->halo > o->band))))
     return false;
   return true;
 }
@@ -91,6 +92,36 @@ struct Batch {
 constexpr int kRecount = 8;
 
 }  // namespace
+
+// Two-deep pacing of a refinement on its stream: after each layer is
+// enqueued, record an event and wait for the one recorded after the layer
+// before.  At most two layers of the refinement are queued at a time, and
+// the device does not wait for the host between layers.  (An event still
+// pending when the pacer is destroyed is released once it completes.)
+class Pacer {
+ public:
+  explicit Pacer(hipStream_t s) : s_(s) {
+    for (hipEvent_t& e : ev_)
+      if (err_ == hipSuccess) err_ = hipEventCreateWithFlags(&e, hipEventDisableTiming);
+  }
+  ~Pacer() {
+    for (hipEvent_t e : ev_)
+      if (e) (void)hipEventDestroy(e);
+  }
+  hipError_t error() const { return err_; }
+  hipError_t operator()() {
+    hipError_t r = hipEventRecord(ev_[n_ & 1], s_);
+    if (r == hipSuccess && n_ > 0) r = hipEventSynchronize(ev_[(n_ - 1) & 1]);
+    ++n_;
+    return r;
+  }
+
+ private:
+  hipStream_t s_;
+  hipEvent_t ev_[2] = {nullptr, nullptr};
+  hipError_t err_ = hipSuccess;
+  int n_ = 0;
+};
 
 // Enqueues refinements from a thread of its own: a tile fill is hundreds of
 // kernel launches (about a millisecond of host time), during which the
@@ -200,7 +231,7 @@ int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, c
       if (!H.dst_rgba[o] || (L_on && (!H.dst_mask[o] || !H.dst_depth[o])))
         return serve_fail(YORO_ERR_INVALID_ARG, "%s: headset %d: missing output %d", who, i, o);
     if (L_on) {
-      const int crop = O.tile + 2 * O.halo;
+      const int crop = O.band > 0 ? 0 : O.tile + 2 * O.halo;
       if (H.width % 8 || H.height % 8 || H.width < crop || H.height < crop)
         return serve_fail(YORO_ERR_INVALID_ARG, "%s: headset %d: %d x %d does not take %d-pixel crops", who, i,
                           H.width, H.height, crop);
@@ -218,7 +249,18 @@ int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, c
   if (workspace_bytes < yoro_serve_workspace_bytes(&O, max_w, max_h) ||
       host_bytes < yoro_serve_host_bytes(&O, max_w, max_h))
     return serve_fail(YORO_ERR_WORKSPACE_TOO_SMALL, "%s: workspace or host staging too small", who);
-  if (L_on && O.learned_workspace_bytes < yoro_model_tiles_workspace_bytes(Lay.tiles, O.chunk, O.tile, O.halo))
+  size_t l_need = 0;
+  if (L_on && O.band > 0) {
+    for (int i = 0; i < n_headsets; ++i) {
+      if (!headsets[i].admitted) continue;
+      const size_t b = yoro_model_bands_workspace_bytes(headsets[i].width, headsets[i].height, O.band, O.halo);
+      if (b == 0) return serve_fail(YORO_ERR_INVALID_ARG, "%s: headset %d: too large for bands", who, i);
+      l_need = b > l_need ? b : l_need;
+    }
+  } else if (L_on) {
+    l_need = yoro_model_tiles_workspace_bytes(Lay.tiles, O.chunk, O.tile, O.halo);
+  }
+  if (L_on && O.learned_workspace_bytes < l_need)
     return serve_fail(YORO_ERR_WORKSPACE_TOO_SMALL, "%s: learned workspace too small", who);
 
   hipStream_t s = (hipStream_t)hip_stream;
@@ -287,6 +329,39 @@ int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, c
     if (l_active || last_in[arrivals[k].headset * YORO_SERVE_MAX_OUTPUTS + out_of[k]] != k) return YORO_PATH_BUSY;
     const int64_t t_start = now_ns();
     if (l_started >= 0 && t_start - l_started < O.learned_min_interval_ns) return YORO_PATH_BUSY;
+    const int o = out_of[k];
+    if (O.band > 0) {
+      // Bands of `band` rows cover whole rows of tiles.
+      const int ntx = (H.width + O.tile - 1) / O.tile, per = O.band / O.tile;
+      std::vector<uint8_t> flags((H.height + O.band - 1) / O.band, 0);
+      for (int t = 0; t < nt; ++t)
+        if (counts[t]) flags[(t / ntx) / per] = 1;
+      refiner->submit([&O, &H, o, flags, ls, lev](std::string* err) -> int32_t {
+        Pacer pace(ls);
+        hipError_t e = pace.error();
+        if (e != hipSuccess) {
+          *err = std::string("pacing event: ") + hipGetErrorString(e);
+          return YORO_ERR_DEVICE;
+        }
+        const int32_t st = yoro::model_fill_bands_paced(
+            O.model_weights, H.dst_rgba[o], H.dst_depth[o], H.dst_mask[o], H.width, H.height, O.band, O.halo,
+            flags.data(), H.dst_rgba[o], O.learned_workspace, O.learned_workspace_bytes, ls,
+            [&pace]() { return pace(); });
+        if (st != YORO_OK) {
+          *err = std::string("band fill: ") + yoro_last_error();
+          return st;
+        }
+        e = hipEventRecord(lev, ls);
+        if (e != hipSuccess) {
+          *err = std::string("event record: ") + hipGetErrorString(e);
+          return YORO_ERR_DEVICE;
+        }
+        return YORO_OK;
+      });
+      l_active = true, l_frame = k, l_headset = arrivals[k].headset, l_out = o;
+      l_started = t_start;
+      return YORO_PATH_LEARNED;
+    }
     const int crop = O.tile + 2 * O.halo, ntx = (H.width + O.tile - 1) / O.tile;
     int kc = 0;
     for (int t = 0; t < nt; ++t) {
@@ -298,7 +373,6 @@ int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, c
       plan_host[4 * kc] = ox, plan_host[4 * kc + 1] = oy, plan_host[4 * kc + 2] = tx, plan_host[4 * kc + 3] = ty;
       ++kc;
     }
-    const int o = out_of[k];
     // The plan buffer is not touched again before this refinement completes.
     refiner->submit([&O, &H, o, kc, plan_dev, plan_host, ls, lev](std::string* err) -> int32_t {
       hipError_t e = hipMemcpyAsync(plan_dev, plan_host, (size_t)kc * 16, hipMemcpyHostToDevice, ls);
@@ -306,22 +380,19 @@ int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, c
         *err = std::string("plan upload: ") + hipGetErrorString(e);
         return YORO_ERR_DEVICE;
       }
-      // One chunk of crops in flight at a time: streams can share a hardware
-      // queue, and a warp batch queued behind the refinement then waits for
-      // the chunk ahead of it, not for the whole refinement.
-      hipEvent_t pev = nullptr;
-      e = hipEventCreateWithFlags(&pev, hipEventDisableTiming);
+      // Two layers in flight at a time: streams can share a hardware queue,
+      // and a warp batch queued behind the refinement then waits for those
+      // layers, not for the whole refinement.
+      Pacer pace(ls);
+      e = pace.error();
       if (e != hipSuccess) {
         *err = std::string("pacing event: ") + hipGetErrorString(e);
         return YORO_ERR_DEVICE;
       }
       const int32_t st = yoro::model_fill_tiles_paced(
           O.model_weights, H.dst_rgba[o], H.dst_depth[o], H.dst_mask[o], H.width, H.height, plan_dev, kc, O.tile,
-          O.halo, O.chunk, H.dst_rgba[o], O.learned_workspace, O.learned_workspace_bytes, ls, [pev, ls]() {
-            hipError_t r = hipEventRecord(pev, ls);
-            return r == hipSuccess ? hipEventSynchronize(pev) : r;
-          });
-      (void)hipEventDestroy(pev);
+          O.halo, O.chunk, H.dst_rgba[o], O.learned_workspace, O.learned_workspace_bytes, ls,
+          [&pace]() { return pace(); });
       if (st != YORO_OK) {
         *err = std::string("tile fill: ") + yoro_last_error();
         return st;

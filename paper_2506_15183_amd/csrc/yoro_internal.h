@@ -106,25 +106,26 @@ constexpr int kLossBlocks = 512;   // blocks (and partial sums) of the L1 loss
 size_t nn_wgrad_chunks(long long P);
 hipError_t nn_conv3x3(const uint16_t* x, int ldx, int N, int H, int W, int Cin, const uint16_t* wgt, int Cout, void* y,
                       int ldy, int y_fp32, int cout_store, int epi, const uint16_t* msrc, int ldm, hipStream_t s);
-// The first convolution (Cin 32, bf16 output, optional ReLU) reading the
-// frame's RGBA, depth and mask and packing them as nn_input does, in one
-// pass; equal to nn_input then nn_conv3x3.
-// yoro_model_fill_tiles with a host call between chunks of crops (after each
-// chunk's composite is enqueued, before the next chunk's forward pass): the
-// caller may wait there, so that work queued behind the fill on the same
-// hardware queue waits for one chunk at most.  Same arguments, results and
-// errors as yoro_model_fill_tiles otherwise; an empty between is that call.
+// yoro_model_fill_tiles with a host call after each layer of the network is
+// enqueued (each chunk of crops runs the 18 layers in turn): the caller may
+// wait there, e.g. for the layer before, so that work queued behind the fill
+// on the same hardware queue waits for a layer or two at most.  Same
+// arguments, results and errors as yoro_model_fill_tiles otherwise; an empty
+// pace is that call.
 int32_t model_fill_tiles_paced(const void* weights, const uint8_t* rgba, const float* depth, const uint8_t* mask,
                                int32_t w, int32_t h, const int32_t* plan, int32_t k, int32_t tile, int32_t halo,
                                int32_t chunk, uint8_t* out, void* workspace, size_t workspace_bytes,
-                               void* hip_stream, const std::function<hipError_t()>& between);
+                               void* hip_stream, const std::function<hipError_t()>& pace);
 
-// yoro_model_fill_bands with a host call between bands, as above.
+// yoro_model_fill_bands with the same host call after each layer.
 int32_t model_fill_bands_paced(const void* weights, const uint8_t* rgba, const float* depth, const uint8_t* mask,
                                int32_t w, int32_t h, int32_t band, int32_t halo, const uint8_t* band_has_holes,
                                uint8_t* out, void* workspace, size_t workspace_bytes, void* hip_stream,
-                               const std::function<hipError_t()>& between);
+                               const std::function<hipError_t()>& pace);
 
+// The first convolution (Cin 32, bf16 output, optional ReLU) reading the
+// frame's RGBA, depth and mask and packing them as nn_input does, in one
+// pass; equal to nn_input then nn_conv3x3.
 hipError_t nn_conv3x3_input(const uint32_t* rgba, const float* depth, const uint8_t* mask, int N, int H, int W,
                             const uint16_t* wgt, int Cout, uint16_t* y, int ldy, int relu, hipStream_t s);
 // The convolution (bf16 output, optional ReLU) followed by a 2x2 average

@@ -65,6 +65,7 @@ class Options(ctypes.Structure):
         ("learned_stream", ctypes.c_void_p),
         ("learned_min_interval_ns", ctypes.c_int64),
         ("progressive", ctypes.c_int32),
+        ("band", ctypes.c_int32),
     ]
 
 
@@ -151,6 +152,12 @@ class Config:
     # Learned policy: release every frame at its warp and refine it in place
     # afterwards (latency = first delivery; refined_ns marks the upgrade).
     progressive: bool = False
+    # Learned policy: 0 refines 128-pixel hole tiles (each in a crop with
+    # `halo` pixels of context), > 0 the full-width bands of this many rows
+    # that hold holes (a multiple of `tile`).  512-row bands refine a sparse
+    # 1832x1920 frame in about 5 ms against about 8 ms for its hole tiles
+    # (whose crops overlap), and reserve less memory than the tile plan.
+    band: int = 512
 
 
 class Server:
@@ -175,8 +182,13 @@ class Server:
         if model is not None:
             from . import unet
 
-            tiles = -(-max_w // cfg.tile) * -(-max_h // cfg.tile)
-            self.learned_bytes = unet.nnlib().yoro_model_tiles_workspace_bytes(tiles, cfg.chunk, cfg.tile, cfg.halo)
+            N = unet.nnlib()
+            if cfg.band > 0:
+                self.learned_bytes = max(N.yoro_model_bands_workspace_bytes(h.width, h.height, cfg.band, cfg.halo)
+                                         for h in self.h)
+            else:
+                tiles = -(-max_w // cfg.tile) * -(-max_h // cfg.tile)
+                self.learned_bytes = N.yoro_model_tiles_workspace_bytes(tiles, cfg.chunk, cfg.tile, cfg.halo)
         reserved = self.ws_bytes + self.learned_bytes + (model.wf.numel() * 2 if model is not None else 0)
         need = [headset_bytes(h, cfg.n_sources, cfg.n_outputs) for h in self.h]
         self.admitted = admit(need, cfg.budget_bytes, reserved)
@@ -227,7 +239,7 @@ class Server:
         o.learned_max_hole_fraction = c.learned_max_hole_fraction
         o.learned_min_interval_ns = int(c.learned_min_interval_ms * 1e6)
         o.progressive = int(bool(c.progressive))
-        o.tile, o.halo, o.chunk = c.tile, c.halo, c.chunk
+        o.tile, o.halo, o.chunk, o.band = c.tile, c.halo, c.chunk, c.band
         if policy == LEARNED:
             o.model_weights = self.model.wf.data_ptr()
             # (sizing happens before the workspace exists: any non-null address)

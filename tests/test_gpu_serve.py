@@ -147,12 +147,21 @@ def _strong_net(unet, seed):
     return unet.UNet("cuda", params=p)
 
 
-def test_learned_policy_refines_and_falls_back(cuda):
+def _learned_want(net, cfg, rgba, depth, mask):
+    """The stand-alone learned fill the loop's refinement must equal: hole
+    tiles, or full-width bands."""
+    if cfg.band > 0:
+        return net.fill_bands(rgba, depth, mask, band=cfg.band, halo=cfg.halo)
+    return net.fill_tiles(rgba, depth, mask, chunk=cfg.chunk)[0]
+
+
+@pytest.mark.parametrize("band", [0, 256])
+def test_learned_policy_refines_and_falls_back(cuda, band):
     torch, serve, unet, yoro, HeadsetSpec, FrameSpec = _mods()
     hs = _headsets(HeadsetSpec, 4, rates=(60.0, 50.0, 40.0))
     net = _strong_net(unet, 8)
     cfg = serve.Config(budget_bytes=10**10, n_sources=2, n_outputs=2, max_batch=4, max_in_flight=2, chunk=4,
-                       learned_max_hole_fraction=1.0)
+                       learned_max_hole_fraction=1.0, band=band)
     srv = serve.Server(hs, cfg, _frames(FrameSpec), model=net)
     trace = serve.make_trace(hs, 0.4, cfg.n_sources, seed=3)
     res = srv.run(trace, serve.LEARNED)
@@ -169,7 +178,7 @@ def test_learned_policy_refines_and_falls_back(cuda):
         if res["holes"][k] >= 0:
             assert int(res["holes"][k]) == int((mask != 0).sum())
         if paths[k] == serve.PATH_LEARNED:
-            want, _ = net.fill_tiles(rgba, depth, mask, chunk=cfg.chunk)
+            want = _learned_want(net, cfg, rgba, depth, mask)
             checked += 1
         else:
             want = rgba
@@ -202,7 +211,8 @@ def test_refinement_interval_budget(cuda):
     assert (res["done_ns"] >= res["launch_ns"]).all()
 
 
-def test_progressive_refinement_releases_at_the_warp(cuda):
+@pytest.mark.parametrize("band", [0, 256])
+def test_progressive_refinement_releases_at_the_warp(cuda, band):
     """Progressive mode: every frame is released with the plain fill when its
     warp completes (done_ns); a refined frame is upgraded in place later
     (refined_ns), and the output it leaves equals the stand-alone tiled
@@ -211,7 +221,7 @@ def test_progressive_refinement_releases_at_the_warp(cuda):
     hs = _headsets(HeadsetSpec, 4, rates=(60.0, 50.0, 40.0))
     net = _strong_net(unet, 8)
     cfg = serve.Config(budget_bytes=10**10, n_sources=2, n_outputs=2, max_batch=4, max_in_flight=2, chunk=4,
-                       learned_max_hole_fraction=1.0, progressive=True)
+                       learned_max_hole_fraction=1.0, progressive=True, band=band)
     srv = serve.Server(hs, cfg, _frames(FrameSpec), model=net)
     trace = serve.make_trace(hs, 0.4, cfg.n_sources, seed=3)
     res = srv.run(trace, serve.LEARNED)
@@ -224,7 +234,7 @@ def test_progressive_refinement_releases_at_the_warp(cuda):
     checked = 0
     for (hi, o), k in _last_per_output(trace, res, cfg.n_outputs, len(hs)).items():
         rgba, depth, mask = _plain_alone(yoro, srv, hs[hi], int(trace["source"][k]))
-        want = net.fill_tiles(rgba, depth, mask, chunk=cfg.chunk)[0] if refined[k] else rgba
+        want = _learned_want(net, cfg, rgba, depth, mask) if refined[k] else rgba
         checked += int(refined[k])
         assert torch.equal(srv.outs[hi][o][0], want), (hi, o, k, int(paths[k]))
     assert checked >= 1

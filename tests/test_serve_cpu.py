@@ -75,6 +75,13 @@ def test_workspace_sizes_and_option_checks():
     assert L.yoro_serve_workspace_bytes(ctypes.byref(o), 2160, 2160) == 0
     o.progressive = 1
     assert L.yoro_serve_workspace_bytes(ctypes.byref(o), 2160, 2160) == learned
+    # Bands: a multiple of the tile, at least twice the halo.
+    for band, ok in ((256, True), (384, True), (200, False), (128, True), (-128, False)):
+        o.band = band
+        assert (L.yoro_serve_workspace_bytes(ctypes.byref(o), 2160, 2160) == learned) == ok, band
+    o.halo = 72
+    assert L.yoro_serve_workspace_bytes(ctypes.byref(o), 2160, 2160) == 0  # 2 halo > 128
+    o.halo, o.band = 64, 0
     o.max_batch = 0
     assert L.yoro_serve_workspace_bytes(ctypes.byref(o), 2160, 2160) == 0
 
