@@ -365,6 +365,13 @@ def main():
         prog = serve.run_interleaved(srv, trace, (serve.LEARNED,), rounds=2)
         srv.cfg.progressive = False
         serving["sparse_scenes"]["learned_progressive"] = serve.summarize(*prog[serve.LEARNED], hs, sparse_s)
+        # Held mode with no interval budget: a refinement starts whenever none
+        # runs, so every eligible frame that finds the refiner free is refined
+        # and counted at its refined completion.
+        srv.cfg.learned_min_interval_ms = 0.0
+        free = serve.run_interleaved(srv, trace, (serve.LEARNED,), rounds=2)
+        srv.cfg.learned_min_interval_ms = cfg_s.learned_min_interval_ms
+        serving["sparse_scenes"]["learned_no_budget"] = serve.summarize(*free[serve.LEARNED], hs, sparse_s)
         del srv
         # What a refinement buys on such frames: hole PSNR against the
         # ray-cast other eye, plain and learned fill.

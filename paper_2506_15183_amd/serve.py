@@ -298,12 +298,14 @@ def summarize(trace, res, headsets, seconds: float):
     if refined.any():
         out["refined_fraction"] = round(float(refined.mean()), 5)
         out["learned_frames_p50_ms"] = round(float(np.percentile(lat[refined], 50)), 4)
+        out["learned_frames_p99_ms"] = round(float(np.percentile(lat[refined], 99)), 4)
         out["learned_frames_max_ms"] = round(float(lat[refined].max()), 4)
         out["p99_plain_path_frames_ms"] = round(float(np.percentile(lat[~refined], 99)), 4)
         up = res["refined_ns"][done][refined]
         if (up >= 0).any():  # progressive: time from arrival to the refined upgrade
             t_up = (up[up >= 0] - trace["t_ns"][done][refined][up >= 0]) / 1e6
             out["refined_upgrade_p50_ms"] = round(float(np.percentile(t_up, 50)), 4)
+            out["refined_upgrade_p99_ms"] = round(float(np.percentile(t_up, 99)), 4)
             out["refined_upgrade_max_ms"] = round(float(t_up.max()), 4)
     holes = res["holes"][done]
     if (holes >= 0).any():
