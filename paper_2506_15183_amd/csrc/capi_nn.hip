@@ -64,7 +64,8 @@ int32_t yoro_nn_conv3x3(const void* x, int32_t ldx, int32_t n, int32_t h, int32_
 
 size_t yoro_nn_conv3x3_wgrad_workspace(int32_t n, int32_t h, int32_t w, int32_t cin, int32_t cout) {
   if (!shape_ok(n, h, w) || cin <= 0 || cout <= 0) return 0;
-  return yoro::nn_wgrad_chunks((long long)n * h * w) * 9 * (size_t)cin * (size_t)cout * sizeof(float);
+  if (cin % 32 || cout % 32) return 0;
+  return yoro::nn_wgrad_chunks(n, h, w, cin, cout) * 9 * (size_t)cin * (size_t)cout * sizeof(float);
 }
 
 int32_t yoro_nn_conv3x3_wgrad(const void* x, int32_t ldx, const void* dy, int32_t lddy, int32_t n, int32_t h,

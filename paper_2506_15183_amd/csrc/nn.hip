@@ -279,106 +279,194 @@ conv3x3_tiled_kernel(const uint16_t* __restrict__ x, int ldx, int N,
 }
 
 // ---------------------------------------------------------- weight grad --
-// dW[t][co][ci] = sum_p dy[p][co] * x[p + off(t)][ci].  GEMM with M = co,
-// N = ci, K = pixels.  A workgroup owns one tap, a TCO x TCI block and one
-// chunk of pixels; dy and x tiles of 32 pixels are staged in LDS transposed
-// (channel-major) so each lane reads its 8 consecutive pixels in one load.
-// Partial sums go to ws[chunk][t][co][ci]; a second kernel adds the chunks in
-// order, so the result does not depend on scheduling.
-constexpr int kWgPix = 32;
-constexpr int kWgPad = 8;  // LDS row pad (bf16 elements)
+// dW[t][co][ci] = sum_p dy[p][co] * x[p + off(t)][ci]: per tap a GEMM with
+// M = co, N = ci, K = pixels.  A workgroup owns a TCO x 32 block of (co, ci)
+// and all nine taps, and walks the tiles of kWgRows x kWgCols pixels of its
+// chunk.  Per tile, dy (TCO channels) and the x patch with its one-pixel
+// halo (32 channels) are staged in LDS channel-major; the patch is stored
+// three times, shifted by 0, 1 and 2 columns, so that each tap's operand is
+// an aligned 16-byte read.  Each tile row is one K step of 32 pixels for all
+// nine taps, which share the step's dy fragments.  Wave w owns ci rows
+// 16 (w & 1) .. +15 and TCO / 32 of the 16-row co tiles: 9 TCO / 32
+// accumulators.  Partial sums go to ws[chunk][t][co][ci]; a second kernel
+// adds the chunks in order, so the result does not depend on scheduling.
+constexpr int kWgRows = 4;                                        // tile rows = K steps per tile
+constexpr int kWgCols = 32;                                       // pixels per K step
+constexpr int kWgTci = 32;                                        // input channels per workgroup
+constexpr int kWgRowStride = 40;                                  // bf16 per staged row: 32 + 8 pad
+constexpr int kWgDyStride = kWgRows * kWgRowStride + 8;           // bf16 per dy channel
+constexpr int kWgXStride = (kWgRows + 2) * kWgRowStride + 8;      // bf16 per x channel and shift
+// The channel strides (84 and 124 dwords) put the 16 channels that one
+// fragment read touches on distinct 4-dword bank groups.
 
-template <int TCO, int TCI>
+template <int TCO>
 __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(const uint16_t* __restrict__ x, int ldx,
-                                                            const uint16_t* __restrict__ dy, int lddy, int N, int H,
-                                                            int W, int Cin, int Cout, int chunk_pix,
+                                                            const uint16_t* __restrict__ dy, int lddy, int H, int W,
+                                                            int Cin, int Cout, long long tiles, int nchunks,
                                                             float* __restrict__ ws) {
-  __shared__ __align__(16) uint16_t sa[TCO][kWgPix + kWgPad];
-  __shared__ __align__(16) uint16_t sb[TCI][kWgPix + kWgPad];
-  const int nco = Cout / TCO, nci = Cin / TCI;
-  int bid = blockIdx.x;
-  const int t = bid / (nco * nci);
-  bid -= t * nco * nci;
-  const int co0 = (bid / nci) * TCO, ci0 = (bid % nci) * TCI;
+  __shared__ __align__(16) uint16_t sdy[TCO * kWgDyStride];
+  __shared__ __align__(16) uint16_t sx[3 * kWgTci * kWgXStride];
+  constexpr int CPW = TCO / 32;  // co tiles per wave
+  const int nci = Cin / kWgTci;
+  const int co0 = (blockIdx.x / nci) * TCO, ci0 = (blockIdx.x % nci) * kWgTci;
   const int chunk = blockIdx.y;
-  const long long P = (long long)N * H * W;
-  const long long pbeg = (long long)chunk * chunk_pix;
-  const long long pend = pbeg + chunk_pix < P ? pbeg + chunk_pix : P;
-  const int dyo = t / 3 - 1, dxo = t % 3 - 1;
+  const long long t0 = tiles * chunk / nchunks, t1 = tiles * (chunk + 1) / nchunks;
+  const int tiles_x = (W + kWgCols - 1) / kWgCols, tiles_y = (H + kWgRows - 1) / kWgRows;
+  const long long per_img = (long long)tiles_x * tiles_y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  constexpr int WM = TCO / 32, WN = TCI / 32;  // waves used: WM x WN (each 32 x 32)
-  const int wm = wave / WN, wn = wave % WN;
-  const bool active = wave < WM * WN;
-  floatx4 acc[2][2];
+  const int kg = (lane >> 4) * 8;
+  const int cit = wave & 1, cog = wave >> 1;
+  floatx4 acc[CPW][9];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < CPW; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < 9; ++t) acc[i][t] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  for (long long pk = pbeg; pk < pend; pk += kWgPix) {
-    // Stage dy[32 px][TCO] -> sa[co][px] and x(shifted)[32 px][TCI] -> sb[ci][px].
-    for (int e = threadIdx.x; e < kWgPix * (TCO / 8); e += 256) {
-      const int px = e / (TCO / 8), c8 = (e % (TCO / 8)) * 8;
-      const long long p = pk + px;
-      u32x4 v = {0u, 0u, 0u, 0u};
-      if (p < pend) v = *reinterpret_cast<const u32x4*>(dy + p * lddy + co0 + c8);
+  // Staging: thread e of a tile loads dy items e, e + 256, ... and x items
+  // likewise (item = 8 channels of one pixel).  The next tile's items are
+  // loaded into registers while the current tile's MFMAs run; addresses are
+  // clamped into the tensors and items outside the image are zeroed when
+  // they are written to LDS (branch-free loads keep them all in flight).
+  constexpr int kDyItems = kWgRows * kWgCols * (TCO / 8);
+  constexpr int kXPix = (kWgRows + 2) * (kWgCols + 2);
+  constexpr int kXItems = kXPix * (kWgTci / 8);
+  constexpr int kDyPer = (kDyItems + 255) / 256, kXPer = (kXItems + 255) / 256;
+  u32x4 vdy[kDyPer], vx[kXPer];
+  unsigned okdy = 0, okx = 0;
+  auto load_tile = [&](long long tile) {
+    const long long n = tile / per_img;
+    const int rem = (int)(tile - n * per_img);
+    const int y0 = (rem / tiles_x) * kWgRows, x0 = (rem % tiles_x) * kWgCols;
+    okdy = 0, okx = 0;
+#pragma unroll
+    for (int k = 0; k < kDyPer; ++k) {
+      const int e = threadIdx.x + 256 * k;
+      const int px = e % (kWgRows * kWgCols), c8 = (e / (kWgRows * kWgCols)) * 8;
+      const int yy = y0 + px / kWgCols, xx = x0 + px % kWgCols;
+      const bool ok = e < kDyItems && yy < H && xx < W;
+      const long long pix = ok ? (n * H + yy) * W + xx : 0;
+      vdy[k] = *reinterpret_cast<const u32x4*>(dy + pix * lddy + co0 + (ok ? c8 : 0));
+      okdy |= (ok ? 1u : 0u) << k;
+    }
+#pragma unroll
+    for (int k = 0; k < kXPer; ++k) {
+      const int e = threadIdx.x + 256 * k;
+      const int px = e % kXPix, c8 = (e / kXPix) * 8;
+      const int yy = y0 - 1 + px / (kWgCols + 2), xx = x0 - 1 + px % (kWgCols + 2);
+      const bool ok = e < kXItems && yy >= 0 && yy < H && xx >= 0 && xx < W;
+      const long long pix = ok ? (n * H + yy) * W + xx : 0;
+      vx[k] = *reinterpret_cast<const u32x4*>(x + pix * ldx + ci0 + (ok ? c8 : 0));
+      okx |= (ok ? 1u : 0u) << k;
+    }
+  };
+  // dy[y0 + r][x0 + c][co0 + ch] -> sdy[ch][r][c]; x[y0 - 1 + rr][x0 - 1 + pc]
+  // [ci0 + ch] -> sx[s][ch][rr][pc - s] for the shifts s = 0, 1, 2 whose
+  // column pc - s lies in [0, 32).  Pixels run fastest across lanes, so a
+  // wave's 16-bit stores fill rows.
+  auto store_tile = [&]() {
+#pragma unroll
+    for (int k = 0; k < kDyPer; ++k) {
+      const int e = threadIdx.x + 256 * k;
+      if (e >= kDyItems) continue;
+      const int px = e % (kWgRows * kWgCols), c8 = (e / (kWgRows * kWgCols)) * 8;
+      const bool ok = (okdy >> k) & 1u;
+      uint16_t* d = sdy + c8 * kWgDyStride + (px / kWgCols) * kWgRowStride + px % kWgCols;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        sa[c8 + 2 * j][px] = (uint16_t)(v[j] & 0xFFFFu);
-        sa[c8 + 2 * j + 1][px] = (uint16_t)(v[j] >> 16);
+        const uint32_t w = ok ? vdy[k][j] : 0u;
+        d[(2 * j) * kWgDyStride] = (uint16_t)(w & 0xFFFFu);
+        d[(2 * j + 1) * kWgDyStride] = (uint16_t)(w >> 16);
       }
     }
-    for (int e = threadIdx.x; e < kWgPix * (TCI / 8); e += 256) {
-      const int px = e / (TCI / 8), c8 = (e % (TCI / 8)) * 8;
-      const long long p = pk + px;
-      u32x4 v = {0u, 0u, 0u, 0u};
-      if (p < pend) {
-        const int n = (int)(p / ((long long)H * W));
-        const int rem = (int)(p - (long long)n * H * W);
-        const int yy = rem / W + dyo, xx = rem % W + dxo;
-        if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-          v = *reinterpret_cast<const u32x4*>(x + ((long long)n * H * W + (long long)yy * W + xx) * ldx + ci0 + c8);
-      }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        sb[c8 + 2 * j][px] = (uint16_t)(v[j] & 0xFFFFu);
-        sb[c8 + 2 * j + 1][px] = (uint16_t)(v[j] >> 16);
+    for (int k = 0; k < kXPer; ++k) {
+      const int e = threadIdx.x + 256 * k;
+      if (e >= kXItems) continue;
+      const int px = e % kXPix, c8 = (e / kXPix) * 8;
+      const int rr = px / (kWgCols + 2), pc = px % (kWgCols + 2);
+      const bool ok = (okx >> k) & 1u;
+#pragma unroll
+      for (int sh = 0; sh < 3; ++sh) {
+        const int c = pc - sh;
+        if (c < 0 || c >= kWgCols) continue;
+        uint16_t* d = sx + (sh * kWgTci + c8) * kWgXStride + rr * kWgRowStride + c;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const uint32_t w = ok ? vx[k][j] : 0u;
+          d[(2 * j) * kWgXStride] = (uint16_t)(w & 0xFFFFu);
+          d[(2 * j + 1) * kWgXStride] = (uint16_t)(w >> 16);
+        }
       }
     }
+  };
+
+  if (t0 < t1) load_tile(t0);
+  for (long long tile = t0; tile < t1; ++tile) {
+    __syncthreads();  // the previous tile's fragments have been read
+    store_tile();
     __syncthreads();
-    if (active) {
-      const int kg = (lane >> 4) * 8;
-      u32x4 a[2], b[2];
+    if (tile + 1 < t1) load_tile(tile + 1);
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const u32x4*>(&sa[wm * 32 + i * 16 + (lane & 15)][kg]);
+    for (int r = 0; r < kWgRows; ++r) {
+      u32x4 a[CPW];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const u32x4*>(&sb[wn * 32 + j * 16 + (lane & 15)][kg]);
+      for (int i = 0; i < CPW; ++i)
+        a[i] = *reinterpret_cast<const u32x4*>(&sdy[((cog * CPW + i) * 16 + (lane & 15)) * kWgDyStride +
+                                                    r * kWgRowStride + kg]);
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int t = 0; t < 9; ++t) {
+        const int ty = t / 3, tx = t % 3;
+        const u32x4 b = *reinterpret_cast<const u32x4*>(
+            &sx[(tx * kWgTci + cit * 16 + (lane & 15)) * kWgXStride + (r + ty) * kWgRowStride + kg]);
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a[i]), as_bf16x8(b[j]), acc[i][j], 0, 0, 0);
+        for (int i = 0; i < CPW; ++i)
+          acc[i][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a[i]), as_bf16x8(b), acc[i][t], 0, 0, 0);
+      }
     }
-    __syncthreads();
   }
-  if (!active) return;
-  float* out = ws + ((long long)chunk * 9 + t) * Cout * Cin;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int t = 0; t < 9; ++t) {
+    float* out = ws + ((long long)chunk * 9 + t) * Cout * Cin;
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int i = 0; i < CPW; ++i)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int co = co0 + wm * 32 + i * 16 + (lane >> 4) * 4 + r;
-        const int ci = ci0 + wn * 32 + j * 16 + (lane & 15);
-        out[(long long)co * Cin + ci] = acc[i][j][r];
+        const int co = co0 + (cog * CPW + i) * 16 + (lane >> 4) * 4 + r;
+        const int ci = ci0 + cit * 16 + (lane & 15);
+        out[(long long)co * Cin + ci] = acc[i][t][r];
       }
+  }
+}
+
+// The chunk partial sums ws[c][i] (c < nchunks, i < n) added in a fixed
+// order in two steps, so the result does not depend on scheduling: first
+// each group of kSumGroup consecutive chunks into the group's first slot (in
+// place), then the groups' sums in order.  The first step's loads are
+// independent, so they are in flight together.
+constexpr int kSumGroup = 16;
+
+__global__ void sum_chunk_groups_kernel(float* __restrict__ ws, int nchunks, long long n) {
+  const int ngroups = (nchunks + kSumGroup - 1) / kSumGroup;
+  for (long long j = (long long)blockIdx.x * blockDim.x + threadIdx.x; j < n * ngroups;
+       j += (long long)gridDim.x * blockDim.x) {
+    const int g = (int)(j / n);
+    const long long i = j - (long long)g * n;
+    const int c0 = g * kSumGroup, cn = nchunks - c0 < kSumGroup ? nchunks - c0 : kSumGroup;
+    float v[kSumGroup];
+#pragma unroll
+    for (int c = 0; c < kSumGroup; ++c) v[c] = c < cn ? ws[(long long)(c0 + c) * n + i] : 0.0f;
+    float s = v[0];
+#pragma unroll
+    for (int c = 1; c < kSumGroup; ++c)
+      if (c < cn) s += v[c];
+    ws[(long long)c0 * n + i] = s;
+  }
 }
 
 __global__ void sum_chunks_kernel(const float* __restrict__ ws, int nchunks, long long n, float* __restrict__ out) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
     float s = 0.0f;
-    for (int c = 0; c < nchunks; ++c) s += ws[(long long)c * n + i];  // fixed order: deterministic
+    for (int c = 0; c < nchunks; c += kSumGroup) s += ws[(long long)c * n + i];  // fixed order: deterministic
     out[i] = s;
   }
 }
@@ -869,41 +957,46 @@ hipError_t nn_conv3x3_up(const uint16_t* x, int ldx, int N, int H, int W, int Ci
   return conv3x3_launch(x, ldx, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi, msrc, ldm, 1, s);
 }
 
-// Pixels per split-K chunk: at least kWgradChunk, and large enough that at
-// most kWgradMaxChunks partial sums are written and added up.
-long long wgrad_chunk_pix(long long P) {
-  long long c = (P + kWgradMaxChunks - 1) / kWgradMaxChunks;
-  c = (c + 31) / 32 * 32;
-  return c > kWgradChunk ? c : kWgradChunk;
+int wgrad_tco(int Cout) { return Cout % 64 == 0 ? 64 : 32; }
+
+long long wgrad_tiles(long long N, int H, int W) {
+  return N * ((H + kWgRows - 1) / kWgRows) * ((W + kWgCols - 1) / kWgCols);
 }
 
-size_t nn_wgrad_chunks(long long P) {
-  const long long c = wgrad_chunk_pix(P);
-  return (size_t)((P + c - 1) / c);
+// Split-K chunks: enough that the grid holds about kWgradGroups workgroups,
+// at most one per tile and at most kWgradMaxChunks.
+size_t nn_wgrad_chunks(long long N, int H, int W, int Cin, int Cout) {
+  const long long tiles = wgrad_tiles(N, H, W);
+  const long long blocks = (long long)(Cout / wgrad_tco(Cout)) * (Cin / kWgTci);
+  if (tiles <= 0 || blocks <= 0) return 0;
+  long long c = (kWgradGroups + blocks - 1) / blocks;
+  if (c > tiles) c = tiles;
+  if (c > kWgradMaxChunks) c = kWgradMaxChunks;
+  return (size_t)(c > 0 ? c : 1);
 }
 
 hipError_t nn_conv3x3_wgrad(const uint16_t* x, int ldx, const uint16_t* dy, int lddy, int N, int H, int W, int Cin,
                             int Cout, float* dw, float* ws, hipStream_t s) {
-  const long long P = (long long)N * H * W;
-  const int nchunks = (int)nn_wgrad_chunks(P);
-  const int chunk_pix = (int)wgrad_chunk_pix(P);
-  const int tco = Cout % 64 == 0 ? 64 : 32, tci = Cin % 64 == 0 ? 64 : 32;
-  const dim3 grid(9 * (Cout / tco) * (Cin / tci), nchunks);
-  if (tco == 64 && tci == 64)
-    hipLaunchKernelGGL((conv3x3_wgrad_kernel<64, 64>), grid, dim3(256), 0, s, x, ldx, dy, lddy, N, H, W, Cin, Cout,
-                       chunk_pix, ws);
-  else if (tco == 64)
-    hipLaunchKernelGGL((conv3x3_wgrad_kernel<64, 32>), grid, dim3(256), 0, s, x, ldx, dy, lddy, N, H, W, Cin, Cout,
-                       chunk_pix, ws);
-  else if (tci == 64)
-    hipLaunchKernelGGL((conv3x3_wgrad_kernel<32, 64>), grid, dim3(256), 0, s, x, ldx, dy, lddy, N, H, W, Cin, Cout,
-                       chunk_pix, ws);
+  if (Cin % kWgTci || Cout % 32) return hipErrorInvalidValue;
+  const long long tiles = wgrad_tiles(N, H, W);
+  const int nchunks = (int)nn_wgrad_chunks(N, H, W, Cin, Cout);
+  const int tco = wgrad_tco(Cout);
+  const dim3 grid((Cout / tco) * (Cin / kWgTci), nchunks);
+  if (tco == 64)
+    hipLaunchKernelGGL((conv3x3_wgrad_kernel<64>), grid, dim3(256), 0, s, x, ldx, dy, lddy, H, W, Cin, Cout, tiles,
+                       nchunks, ws);
   else
-    hipLaunchKernelGGL((conv3x3_wgrad_kernel<32, 32>), grid, dim3(256), 0, s, x, ldx, dy, lddy, N, H, W, Cin, Cout,
-                       chunk_pix, ws);
+    hipLaunchKernelGGL((conv3x3_wgrad_kernel<32>), grid, dim3(256), 0, s, x, ldx, dy, lddy, H, W, Cin, Cout, tiles,
+                       nchunks, ws);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const long long n = 9LL * Cout * Cin;
+  if (nchunks > 1) {
+    const long long groups = (nchunks + kSumGroup - 1) / kSumGroup;
+    hipLaunchKernelGGL(sum_chunk_groups_kernel, dim3(grid_1d(n * groups, 256)), dim3(256), 0, s, ws, nchunks, n);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(sum_chunks_kernel, dim3(grid_1d(n, 256)), dim3(256), 0, s, ws, nchunks, n, dw);
   return hipGetLastError();
 }

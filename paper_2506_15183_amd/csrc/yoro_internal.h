@@ -100,10 +100,10 @@ hipError_t launch_hole_sse(const uint32_t* rgba, const uint32_t* ref, const uint
 void set_last_error(const char* msg);
 
 // Learned-fill kernels (defined in nn.hip).  bf16 tensors are raw uint16_t.
-constexpr int kWgradChunk = 2048;      // minimum pixels per split-K chunk of the weight gradient
-constexpr int kWgradMaxChunks = 128;  // at most this many chunk partial sums
-constexpr int kLossBlocks = 512;   // blocks (and partial sums) of the L1 loss
-size_t nn_wgrad_chunks(long long P);
+constexpr int kWgradGroups = 512;     // workgroups the weight gradient's split-K grid aims for
+constexpr int kWgradMaxChunks = 512;  // at most this many chunk partial sums
+constexpr int kLossBlocks = 512;      // blocks (and partial sums) of the L1 loss
+size_t nn_wgrad_chunks(long long N, int H, int W, int Cin, int Cout);
 hipError_t nn_conv3x3(const uint16_t* x, int ldx, int N, int H, int W, int Cin, const uint16_t* wgt, int Cout, void* y,
                       int ldy, int y_fp32, int cout_store, int epi, const uint16_t* msrc, int ldm, hipStream_t s);
 // yoro_model_fill_tiles with a host call after each layer of the network is

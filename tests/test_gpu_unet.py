@@ -101,7 +101,9 @@ def test_weight_gradient(cuda):
     torch, G = _t()
     L = G.nnlib()
     rng = np.random.default_rng(2)
-    for (n, h, w, cin, cout) in [(1, 8, 8, 32, 32), (2, 16, 24, 64, 32), (1, 40, 40, 32, 64), (3, 4, 4, 128, 256)]:
+    # Tiles of 4 x 32 pixels: ragged rows and columns, several split-K chunks.
+    for (n, h, w, cin, cout) in [(1, 8, 8, 32, 32), (2, 16, 24, 64, 32), (1, 40, 40, 32, 64), (3, 4, 4, 128, 256),
+                                 (2, 36, 72, 32, 64), (1, 30, 50, 64, 32), (4, 64, 96, 32, 32)]:
         x = U.bf16(rng.normal(size=(n, h, w, cin)))
         dy = U.bf16(rng.normal(size=(n, h, w, cout)))
         ws = torch.empty(L.yoro_nn_conv3x3_wgrad_workspace(n, h, w, cin, cout) // 4 + 4, dtype=torch.float32,
@@ -117,6 +119,18 @@ def test_weight_gradient(cuda):
         G._ok(L.yoro_nn_conv3x3_wgrad(G._p(xd), cin, G._p(dyd), cout, n, h, w, cin, cout, G._p(dw2), G._p(ws),
                                       ws.numel() * 4, None))
         assert torch.equal(dw, dw2)
+    # Channel slices of wider buffers (strides above the channel counts).
+    n, h, w, cin, cout = 2, 20, 44, 32, 64
+    xa = U.bf16(rng.normal(size=(n, h, w, 96)))
+    dya = U.bf16(rng.normal(size=(n, h, w, 128)))
+    xd, dyd = bf(xa.reshape(-1, 96)), bf(dya.reshape(-1, 128))
+    ws = torch.empty(L.yoro_nn_conv3x3_wgrad_workspace(n, h, w, cin, cout) // 4 + 4, dtype=torch.float32,
+                     device="cuda")
+    dw = torch.empty(9 * cout * cin, dtype=torch.float32, device="cuda")
+    G._ok(L.yoro_nn_conv3x3_wgrad(G._p(xd, 32), 96, G._p(dyd, 64), 128, n, h, w, cin, cout, G._p(dw),
+                                  G._p(ws), ws.numel() * 4, None))
+    want = U.conv3x3_grad_weight(xa[..., 32:64], dya[..., 64:128])
+    assert rel_l2(dw.cpu().numpy().reshape(want.shape), want) < 1e-5
 
 
 def test_pool_upsample_and_grads(cuda):
