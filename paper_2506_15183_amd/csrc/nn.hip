@@ -88,6 +88,10 @@ conv3x3_tiled_kernel(const uint16_t* __restrict__ x, int ldx, int N,
                                                                      const float* __restrict__ raw_depth,
                                                                      const uint8_t* __restrict__ raw_mask) {
   constexpr int NB = CT / 16;
+  // 8-byte output stores: bf16 output, channel groups of 4 whole, and 8-byte
+  // aligned rows (the launcher checks the base pointers).
+  const bool wide = !y_fp32 && (cout_store & 3) == 0 && (ldy & 3) == 0 && (epi != 2 || (ldm & 3) == 0) &&
+                    ((reinterpret_cast<uintptr_t>(y) | reinterpret_cast<uintptr_t>(msrc)) & 7u) == 0;
   __shared__ __align__(16) uint16_t patch[kPatchH * kPatchW * kPatchStride];
   // The chunk's weights for all nine taps: [tap][output channel][32 + 8 pad].
   __shared__ __align__(16) uint16_t wlds[9 * CT * kPatchStride];
@@ -218,6 +222,60 @@ conv3x3_tiled_kernel(const uint16_t* __restrict__ x, int ldx, int N,
   const long long img = (long long)n * H * W;
   // Epilogue: lane holds channel co0 + 16nb + lane%16 of pixels 4*(lane/16)+r
   // of M tile m, i.e. row 2*wave + m/2, column 16*(m%2) + 4*(lane/16) + r.
+  if (wide) {
+    // bf16 outputs: the four lanes 4q..4q+3 of a 16-lane group hold four
+    // channels of the same four pixels; a 4 x 4 transpose between them (two
+    // DPP exchanges) gives lane j = lane%4 pixel 4*(lane/16) + j's four
+    // channels 4q..4q+3, stored as one 8-byte write instead of four 2-byte
+    // ones.  The values are those of the per-element path below.
+    const int j = lane & 3, q = (lane >> 2) & 3, g = lane >> 4;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int gy = y0 + 2 * wave + (m >> 1), gx = x0 + (m & 1) * 16 + g * 4 + j;
+      const bool in = gy < H && gx < W;
+      const long long p = img + (long long)(in ? gy : 0) * W + (in ? gx : 0);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        uint32_t h[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) h[r] = to_bf16(epi == 1 ? fmaxf(acc[m][nb][r], 0.0f) : acc[m][nb][r]);
+        const uint32_t A = h[0] | (h[1] << 16), B = h[2] | (h[3] << 16);
+        // Lanes j and j ^ 2 swap pixel pairs: each keeps the pair holding
+        // its own pixel, for its channel (own) and channel j ^ 2 (recv).
+        const uint32_t own = (j & 2) ? B : A;
+        const uint32_t recv = (uint32_t)__builtin_amdgcn_mov_dpp((int)((j & 2) ? A : B), 0x4E, 0xF, 0xF, true);
+        // Lanes j and j ^ 1 swap the halves for each other's pixel.
+        const int sh_mine = (j & 1) * 16, sh_other = 16 - sh_mine;
+        const uint32_t S = ((own >> sh_other) & 0xFFFFu) | (((recv >> sh_other) & 0xFFFFu) << 16);
+        const uint32_t R = (uint32_t)__builtin_amdgcn_mov_dpp((int)S, 0xB1, 0xF, 0xF, true);
+        // Channels j, j ^ 1, j ^ 2, j ^ 3 of pixel j; channel c is entry c ^ j.
+        uint32_t w01 = ((own >> sh_mine) & 0xFFFFu) | ((R & 0xFFFFu) << 16);  // entries 0, 1
+        uint32_t w23 = ((recv >> sh_mine) & 0xFFFFu) | (R & 0xFFFF0000u);     // entries 2, 3
+        if (j & 2) {
+          const uint32_t t = w01;
+          w01 = w23;
+          w23 = t;
+        }
+        if (j & 1) {
+          w01 = (w01 >> 16) | (w01 << 16);
+          w23 = (w23 >> 16) | (w23 << 16);
+        }
+        const int co = co0 + nb * 16 + 4 * q;
+        if (!in || co >= cout_store) continue;
+        if (epi == 2) {  // ReLU derivative: zero where the forward activation was not positive
+          const uint2 mk = *reinterpret_cast<const uint2*>(msrc + p * ldm + co);
+          const uint32_t mw[2] = {mk.x, mk.y};
+          uint32_t* ww[2] = {&w01, &w23};
+#pragma unroll
+          for (int u = 0; u < 2; ++u) {
+            if (!(from_bf16((uint16_t)(mw[u] & 0xFFFFu)) > 0.0f)) *ww[u] &= 0xFFFF0000u;
+            if (!(from_bf16((uint16_t)(mw[u] >> 16)) > 0.0f)) *ww[u] &= 0x0000FFFFu;
+          }
+        }
+        *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(y) + p * ldy + co) = uint2{w01, w23};
+      }
+    }
+  } else {
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
     const int gy = y0 + 2 * wave + (m >> 1);
@@ -238,6 +296,7 @@ conv3x3_tiled_kernel(const uint16_t* __restrict__ x, int ldx, int N,
           reinterpret_cast<uint16_t*>(y)[p * ldy + co] = to_bf16(v);
       }
     }
+  }
   }
   // Optional 2x2 average pool of the stored bf16 outputs (H, W even): a
   // window is rows 2*wave, 2*wave + 1 (M tiles m and m + 2) and columns
