@@ -36,8 +36,15 @@ int32_t yoro_model_layout(int32_t* cin_pad, int32_t* cout_pad, int64_t* offset);
 size_t yoro_model_weights_bytes(void);
 
 /* FP32 masters (offset[18] floats, same layout) -> bf16 model weights
- * (round to nearest, ties to even). */
+ * (round to nearest, ties to even), all layers in one launch. */
 int32_t yoro_model_pack(const float* master, void* weights, void* hip_stream);
+
+/* The same, and, if weights_bwd is not NULL, the backward copies that the
+ * input gradient runs on: layer i at the same offsets as [9][cin_pad]
+ * [cout_pad] with the taps flipped (tap 8 - t), as yoro_nn_pack_weights
+ * writes them.  For training, which refreshes both copies after each
+ * update. */
+int32_t yoro_model_pack_train(const float* master, void* weights, void* weights_bwd, void* hip_stream);
 
 /* Workspace for n images of h x w (h, w multiples of 8, n*h*w < 2^31). */
 size_t yoro_model_workspace_bytes(int32_t n, int32_t h, int32_t w);

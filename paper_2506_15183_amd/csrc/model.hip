@@ -157,14 +157,20 @@ int32_t yoro_model_layout(int32_t* cin_pad, int32_t* cout_pad, int64_t* offset) 
 size_t yoro_model_weights_bytes(void) { return (size_t)layer_offset(YORO_MODEL_LAYERS) * 2; }
 
 int32_t yoro_model_pack(const float* master, void* weights, void* hip_stream) {
+  return yoro_model_pack_train(master, weights, nullptr, hip_stream);
+}
+
+int32_t yoro_model_pack_train(const float* master, void* weights, void* weights_bwd, void* hip_stream) {
   const char* who = "yoro_model_pack";
-  if (!master || !weights || !al4(master) || !al16(weights))
+  if (!master || !weights || !al4(master) || !al16(weights) || (weights_bwd && !al16(weights_bwd)))
     return model_fail(YORO_ERR_INVALID_ARG, "%s: null or misaligned pointer", who);
-  hipError_t e = hipSuccess;
-  for (int i = 0; i < YORO_MODEL_LAYERS && e == hipSuccess; ++i)
-    e = yoro::nn_pack_weights(master + layer_offset(i), kLayers[i].cin, kLayers[i].cout,
-                              static_cast<uint16_t*>(weights) + layer_offset(i), nullptr, (hipStream_t)hip_stream);
-  return launched(e, who);
+  long long off[YORO_MODEL_LAYERS + 1];
+  int cin[YORO_MODEL_LAYERS], cout[YORO_MODEL_LAYERS];
+  for (int i = 0; i < YORO_MODEL_LAYERS; ++i) cin[i] = kLayers[i].cin, cout[i] = kLayers[i].cout;
+  for (int i = 0; i <= YORO_MODEL_LAYERS; ++i) off[i] = layer_offset(i);
+  return launched(yoro::nn_pack_model(master, off, cin, cout, YORO_MODEL_LAYERS, static_cast<uint16_t*>(weights),
+                                      static_cast<uint16_t*>(weights_bwd), (hipStream_t)hip_stream),
+                  who);
 }
 
 size_t yoro_model_workspace_bytes(int32_t n, int32_t h, int32_t w) {

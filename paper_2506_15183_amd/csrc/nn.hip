@@ -547,6 +547,32 @@ __global__ void pack_weights_kernel(const float* __restrict__ w, int cin, int co
   }
 }
 
+// All layers of a model in one launch: element i of the concatenated FP32
+// masters belongs to the layer whose [off[l], off[l + 1]) holds it, and is
+// packed as pack_weights_kernel packs it.
+struct PackTable {
+  long long off[kPackMaxLayers + 1];
+  int cin[kPackMaxLayers], cout[kPackMaxLayers];
+  int layers;
+};
+
+__global__ void pack_model_kernel(const float* __restrict__ w, PackTable tab, uint16_t* __restrict__ wf,
+                                  uint16_t* __restrict__ wb) {
+  const long long n = tab.off[tab.layers];
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    int l = 0;
+    while (l + 1 < tab.layers && tab.off[l + 1] <= i) ++l;
+    const int cin = tab.cin[l], cout = tab.cout[l];
+    const long long j = i - tab.off[l];
+    const int t = (int)(j / ((long long)cin * cout));
+    const int rem = (int)(j - (long long)t * cin * cout);
+    const int co = rem / cin, ci = rem % cin;
+    const uint16_t h = to_bf16(w[i]);
+    wf[i] = h;
+    if (wb) wb[tab.off[l] + ((long long)(8 - t) * cin + ci) * cout + co] = h;
+  }
+}
+
 // ------------------------------------------------------- pool / upsample --
 // h, w: the full-resolution size (pool input / upsample output).
 __global__ void avgpool2_kernel(const uint16_t* __restrict__ x, int ldx, int N, int h, int w, int c,
@@ -751,12 +777,34 @@ __global__ void unet_input_kernel(const uint32_t* __restrict__ rgba, const float
   }
 }
 
-__global__ void count_holes_kernel(const uint8_t* __restrict__ mask, long long npix, unsigned int* __restrict__ out) {
+// Hole pixels (mask != 0): 16 mask bytes per load (VEC, mask 16-byte
+// aligned), a block-wide sum, one atomic per block (integer: the order does
+// not matter).
+template <bool VEC>
+__global__ __launch_bounds__(256) void count_holes_kernel(const uint8_t* __restrict__ mask, long long npix,
+                                                          unsigned int* __restrict__ out) {
+  __shared__ unsigned int part[4];
   unsigned int c = 0;
-  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += (long long)gridDim.x * blockDim.x)
-    c += mask[p] != 0;
+  const long long nv = VEC ? npix >> 4 : 0;
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < nv; v += (long long)gridDim.x * blockDim.x) {
+    const u32x4 q = *reinterpret_cast<const u32x4*>(mask + (v << 4));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t w = q[k];
+      c += ((w & 0xFFu) != 0) + ((w & 0xFF00u) != 0) + ((w & 0xFF0000u) != 0) + ((w >> 24) != 0);
+    }
+  }
+  if (VEC) {
+    if (blockIdx.x == 0)
+      for (long long p = (nv << 4) + threadIdx.x; p < npix; p += blockDim.x) c += mask[p] != 0;
+  } else {
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < npix; p += (long long)gridDim.x * blockDim.x)
+      c += mask[p] != 0;
+  }
   for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off);
-  if ((threadIdx.x & 63) == 0) atomicAdd(out, c);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(out, part[0] + part[1] + part[2] + part[3]);
 }
 
 __global__ void zero_u32_kernel(unsigned int* p, int n) {
@@ -1065,6 +1113,17 @@ hipError_t nn_pack_weights(const float* w, int cin, int cout, uint16_t* wf, uint
   return hipGetLastError();
 }
 
+hipError_t nn_pack_model(const float* w, const long long* off, const int* cin, const int* cout, int layers,
+                         uint16_t* wf, uint16_t* wb, hipStream_t s) {
+  if (layers < 1 || layers > kPackMaxLayers) return hipErrorInvalidValue;
+  PackTable tab{};
+  for (int l = 0; l < layers; ++l) tab.cin[l] = cin[l], tab.cout[l] = cout[l];
+  for (int l = 0; l <= layers; ++l) tab.off[l] = off[l];
+  tab.layers = layers;
+  hipLaunchKernelGGL(pack_model_kernel, dim3(grid_1d(off[layers], 256)), dim3(256), 0, s, w, tab, wf, wb);
+  return hipGetLastError();
+}
+
 static bool v8(int c, const void* a, int lda, const void* b, int ldb) {
   return c % 8 == 0 && lda % 8 == 0 && ldb % 8 == 0 && ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b)) & 15u) == 0;
 }
@@ -1127,8 +1186,13 @@ hipError_t nn_l1_grad(const float* res, const uint32_t* rgba, const uint8_t* mas
   unsigned int* cnt = reinterpret_cast<unsigned int*>(ws);
   float* partial = ws + 16;
   hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, s, cnt, 1);
-  hipLaunchKernelGGL(count_holes_kernel, dim3(grid_1d(npix, 256) < 1024 ? grid_1d(npix, 256) : 1024), dim3(256), 0, s,
-                     mask, npix, cnt);
+  if ((reinterpret_cast<uintptr_t>(mask) & 15u) == 0) {
+    const int cb = grid_1d((npix >> 4) > 0 ? (npix >> 4) : 1, 256);
+    hipLaunchKernelGGL(count_holes_kernel<true>, dim3(cb < 256 ? cb : 256), dim3(256), 0, s, mask, npix, cnt);
+  } else {
+    const int cb = grid_1d(npix, 256);
+    hipLaunchKernelGGL(count_holes_kernel<false>, dim3(cb < 256 ? cb : 256), dim3(256), 0, s, mask, npix, cnt);
+  }
   const int nb = kLossBlocks;
   hipLaunchKernelGGL(l1_grad_kernel, dim3(nb), dim3(kLossThreads), 0, s, res, rgba, mask, target, npix, cnt, g,
                      partial);

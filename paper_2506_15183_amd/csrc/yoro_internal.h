@@ -103,6 +103,12 @@ void set_last_error(const char* msg);
 constexpr int kWgradGroups = 512;     // workgroups the weight gradient's split-K grid aims for
 constexpr int kWgradMaxChunks = 512;  // at most this many chunk partial sums
 constexpr int kLossBlocks = 512;      // blocks (and partial sums) of the L1 loss
+constexpr int kPackMaxLayers = 32;    // layers one nn_pack_model launch takes
+// FP32 masters of `layers` layers, layer l at elements [off[l], off[l + 1])
+// as [9][cout[l]][cin[l]], to bf16 copies: forward (same layout) and, if wb
+// is not null, backward ([9][cin][cout], taps flipped), in one launch.
+hipError_t nn_pack_model(const float* w, const long long* off, const int* cin, const int* cout, int layers,
+                         uint16_t* wf, uint16_t* wb, hipStream_t s);
 size_t nn_wgrad_chunks(long long N, int H, int W, int Cin, int Cout);
 hipError_t nn_conv3x3(const uint16_t* x, int ldx, int N, int H, int W, int Cin, const uint16_t* wgt, int Cout, void* y,
                       int ldy, int y_fp32, int cout_store, int epi, const uint16_t* msrc, int ldm, hipStream_t s);

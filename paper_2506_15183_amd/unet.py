@@ -70,6 +70,7 @@ def nnlib():
             "yoro_nn_composite_tiles": [vp, vp, i32, i32, i32, vp, vp, i32, i32, vp, vp],
             "yoro_model_layout": [vp, vp, vp],
             "yoro_model_pack": [vp, vp, vp],
+            "yoro_model_pack_train": [vp, vp, vp, vp],
             "yoro_model_residual": [vp, vp, vp, vp, i32, i32, i32, vp, vp, sz, vp],
             "yoro_model_fill": [vp, vp, vp, vp, i32, i32, i32, vp, vp, sz, vp],
             "yoro_model_fill_tiles": [vp, vp, vp, vp, i32, i32, vp, i32, i32, i32, i32, vp, vp, sz, vp],
@@ -207,6 +208,10 @@ class UNet:
         sizes = [int(np.prod(s)) for s in self.shapes]
         self.offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
         n = int(self.offsets[-1])
+        lay = (ctypes.c_int64 * (len(ARCH) + 1))()
+        nnlib().yoro_model_layout(None, None, lay)
+        if list(lay) != [int(o) for o in self.offsets]:
+            raise RuntimeError("parameter layout differs from the library's model layout")
         f32 = dict(dtype=torch.float32, device=self.device)
         self.master = torch.zeros(n, **f32)
         self.grad = torch.zeros(n, **f32)
@@ -243,10 +248,9 @@ class UNet:
                 for i, (_, cin, cout) in enumerate(ARCH)]
 
     def pack(self, stream=None):
-        L, s = nnlib(), yoro._stream(stream)
-        for i, (_, cout_p, cin_p) in enumerate(self.shapes):
-            o = int(self.offsets[i])
-            _ok(L.yoro_nn_pack_weights(_p(self.master, o), cin_p, cout_p, _p(self.wf, o), _p(self.wb, o), s))
+        """Both bf16 copies of every layer from the FP32 masters (the masters'
+        layout is the model layout of yoro_model.h), in one launch."""
+        _ok(nnlib().yoro_model_pack_train(_p(self.master), _p(self.wf), _p(self.wb), yoro._stream(stream)))
 
     def buffers(self, n, h, w, train=False) -> Buffers:
         key = (n, h, w, train)

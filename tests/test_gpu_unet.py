@@ -133,6 +133,25 @@ def test_weight_gradient(cuda):
     assert rel_l2(dw.cpu().numpy().reshape(want.shape), want) < 1e-5
 
 
+def test_model_pack_equals_per_layer_pack(cuda):
+    """yoro_model_pack_train (all layers, one launch) writes the same forward
+    and backward copies as yoro_nn_pack_weights layer by layer."""
+    torch, G = _t()
+    L = G.nnlib()
+    net = G.UNet("cuda", params=G.init_params(4))
+    wf, wb = torch.zeros_like(net.wf), torch.zeros_like(net.wb)
+    for i, (_, cout_p, cin_p) in enumerate(net.shapes):
+        o = int(net.offsets[i])
+        G._ok(L.yoro_nn_pack_weights(G._p(net.master, o), cin_p, cout_p, G._p(wf, o), G._p(wb, o), None))
+    torch.cuda.synchronize()
+    assert torch.equal(wf.view(torch.int16), net.wf.view(torch.int16))
+    assert torch.equal(wb.view(torch.int16), net.wb.view(torch.int16))
+    only = torch.zeros_like(net.wf)
+    G._ok(L.yoro_model_pack(G._p(net.master), G._p(only), None))
+    torch.cuda.synchronize()
+    assert torch.equal(only.view(torch.int16), net.wf.view(torch.int16))
+
+
 def test_pool_upsample_and_grads(cuda):
     torch, G = _t()
     L = G.nnlib()
@@ -195,6 +214,15 @@ def test_input_loss_composite_adamw(cuda):
     assert abs(float(loss.item()) - wl) < 1e-5 * max(1.0, wl)
     gg = npf(g)
     assert close_frac(gg[:, :3], U.bf16(wg).reshape(P, 3)) >= 0.999 and not gg[:, 3:].any()
+    # A pixel count that is not a multiple of 16 and a mask that is not
+    # 16-byte aligned (the hole count's scalar path).
+    for start, cnt in ((1, P - 1), (0, P - 5)):
+        loss2 = torch.zeros(1, dtype=torch.float32, device="cuda")
+        G._ok(L.yoro_nn_l1_grad(G._p(res_d, 3 * start), G._p(rgba_d, 4 * start), G._p(mask_d, start),
+                                G._p(target_d, 4 * start), cnt, G._p(g), G._p(loss2), G._p(ws), None))
+        sl = lambda a: a.reshape((P,) + a.shape[3:])[start:start + cnt][None, None]  # noqa: E731
+        wl2, _ = U.masked_l1(sl(res.astype(np.float32).astype(np.float64)), sl(rgba), sl(mask), sl(target))
+        assert abs(float(loss2.item()) - wl2) < 1e-5 * max(1.0, wl2), (start, cnt)
     out = torch.empty_like(rgba_d)
     G._ok(L.yoro_nn_composite(G._p(res_d), G._p(rgba_d), G._p(mask_d), P, G._p(out), None))
     want = U.composite(res.astype(np.float32), rgba, mask)
