@@ -27,10 +27,13 @@ typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
 typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4;
 
 // float -> bfloat16 bits, round to nearest, ties to even (no NaN inputs here).
-__device__ __forceinline__ uint16_t to_bf16(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
+// Round to nearest, ties to even (gfx950 converts in hardware:
+// v_cvt_pk_bf16_f32, two values per instruction).
+__device__ __forceinline__ uint16_t to_bf16(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+__device__ __forceinline__ uint32_t to_bf16x2(float lo, float hi) {
+  typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+  const bf16x2_t v = {(__bf16)lo, (__bf16)hi};
+  return __builtin_bit_cast(uint32_t, v);
 }
 __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
@@ -236,10 +239,10 @@ conv3x3_tiled_kernel(const uint16_t* __restrict__ x, int ldx, int N,
       const long long p = img + (long long)(in ? gy : 0) * W + (in ? gx : 0);
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        uint32_t h[4];
+        float f[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) h[r] = to_bf16(epi == 1 ? fmaxf(acc[m][nb][r], 0.0f) : acc[m][nb][r]);
-        const uint32_t A = h[0] | (h[1] << 16), B = h[2] | (h[3] << 16);
+        for (int r = 0; r < 4; ++r) f[r] = epi == 1 ? fmaxf(acc[m][nb][r], 0.0f) : acc[m][nb][r];
+        const uint32_t A = to_bf16x2(f[0], f[1]), B = to_bf16x2(f[2], f[3]);
         // Lanes j and j ^ 2 swap pixel pairs: each keeps the pair holding
         // its own pixel, for its channel (own) and channel j ^ 2 (recv).
         const uint32_t own = (j & 2) ? B : A;
@@ -651,9 +654,7 @@ __global__ void upsample2_grad_kernel(const uint16_t* __restrict__ g, int ldg, i
 // the kernels above, used when channel counts and strides are multiples of 8.
 __device__ __forceinline__ float lo_bf(uint32_t v) { return __uint_as_float(v << 16); }
 __device__ __forceinline__ float hi_bf(uint32_t v) { return __uint_as_float(v & 0xFFFF0000u); }
-__device__ __forceinline__ uint32_t pack_bf(float a, float b) {
-  return (uint32_t)to_bf16(a) | ((uint32_t)to_bf16(b) << 16);
-}
+__device__ __forceinline__ uint32_t pack_bf(float a, float b) { return to_bf16x2(a, b); }
 
 __global__ void avgpool2_v8_kernel(const uint16_t* __restrict__ x, int ldx, int N, int h, int w, int c,
                                    uint16_t* __restrict__ y, int ldy) {
