@@ -411,6 +411,7 @@ def main():
             "traffic": traffic,
             "kernel": "warp_batch_kernel<9>",
             "launch_ms_avg": round(float(per_launch_ms.mean()), 4),
+            "launch_ms_median": round(float(np.median(per_launch_ms)), 4),
             "launch_ms_p10": round(float(np.percentile(per_launch_ms, 10)), 4),
             "launch_ms_p90": round(float(np.percentile(per_launch_ms, 90)), 4),
             "stream_gb_s": round(stream_gbs, 1),
