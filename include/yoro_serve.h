@@ -36,7 +36,9 @@
  * options->learned_stream (both of default priority).  A worker thread of
  * the call enqueues each refinement one layer of the network at a time and
  * keeps at most two layers queued, so a warp that shares a hardware queue
- * with the refinement waits for two layers' kernels at most.  The call returns
+ * with the refinement waits for two layers' kernels at most; the
+ * refinement's convolutions run one workgroup per output tile, so a warp on
+ * another queue gets compute units within a tile's time.  The call returns
  * when every admitted frame is final; it synchronises both streams at the
  * end.
  */

@@ -79,7 +79,10 @@ hipError_t forward(const uint16_t* wts, const uint8_t* rgba, const float* depth,
                    int w, const Acts& a, hipStream_t s, const std::function<hipError_t()>* pace = nullptr) {
   using namespace yoro;
   hipError_t e = hipSuccess;
-  // Every layer is one launch; the pacing call follows each.
+  // Every layer is one launch; the pacing call follows each.  A paced pass
+  // shares the GPU with latency-critical work: its convolutions run one
+  // workgroup per tile.
+  const bool persistent = !(pace && *pace);
   auto ok = [&](hipError_t r) {
     if (e == hipSuccess) e = r;
     if (e == hipSuccess && pace && *pace) e = (*pace)();
@@ -87,17 +90,18 @@ hipError_t forward(const uint16_t* wts, const uint8_t* rgba, const float* depth,
   auto conv = [&](int i, const uint16_t* x, int ldx, int lev, uint16_t* y, int ldy) {
     const Layer L = kLayers[i];
     ok(nn_conv3x3(x, ldx, n, h >> lev, w >> lev, L.cin, wts + layer_offset(i), L.cout, y, ldy, 0, L.cout, 1, nullptr,
-                  0, s));
+                  0, s, persistent));
   };
   // The first convolution packs the frame's channels itself (no packed copy).
   // The encoders' second convolutions also write the 2x2 average pool of
   // their output (the next level's input) in the same pass.
   auto conv_pool = [&](int i, const uint16_t* x, int ldx, int lev, uint16_t* y, int ldy, uint16_t* pool, int ldp) {
     const Layer L = kLayers[i];
-    ok(nn_conv3x3_pool(x, ldx, n, h >> lev, w >> lev, L.cin, wts + layer_offset(i), L.cout, y, ldy, 1, pool, ldp, s));
+    ok(nn_conv3x3_pool(x, ldx, n, h >> lev, w >> lev, L.cin, wts + layer_offset(i), L.cout, y, ldy, 1, pool, ldp, s,
+                       persistent));
   };
   ok(nn_conv3x3_input(reinterpret_cast<const uint32_t*>(rgba), depth, mask, n, h, w, wts + layer_offset(0),
-                      kLayers[0].cout, a.e0a, 32, 1, s));
+                      kLayers[0].cout, a.e0a, 32, 1, s, persistent));
   conv_pool(1, a.e0a, 32, 0, a.c0 + 32, 64, a.p1, 32);  // e0b -> the skip half of c0, and its pool
   conv(2, a.p1, 32, 1, a.e1a, 64);
   conv_pool(3, a.e1a, 64, 1, a.c1 + 64, 128, a.p2, 64);  // e1b
@@ -110,7 +114,7 @@ hipError_t forward(const uint16_t* wts, const uint8_t* rgba, const float* depth,
   auto conv_up = [&](int i, const uint16_t* xlo, int ldx, int lev, uint16_t* y, int ldy) {
     const Layer L = kLayers[i];
     ok(nn_conv3x3_up(xlo, ldx, n, h >> lev, w >> lev, L.cin, wts + layer_offset(i), L.cout, y, ldy, 0, L.cout, 1,
-                     nullptr, 0, s));
+                     nullptr, 0, s, persistent));
   };
   conv_up(8, a.e3b, 256, 2, a.c2, 256);  // d2a -> the decoder half of c2
   conv(9, a.c2, 256, 2, a.d2b, 128);
@@ -122,7 +126,7 @@ hipError_t forward(const uint16_t* wts, const uint8_t* rgba, const float* depth,
   conv(15, a.c0, 64, 0, a.d0b, 32);
   conv(16, a.d0b, 32, 0, a.d0c, 32);
   // Head: FP32 residual, the first 3 of its 32 padded outputs, no activation.
-  ok(nn_conv3x3(a.d0c, 32, n, h, w, 32, wts + layer_offset(17), 32, a.res, 3, 1, 3, 0, nullptr, 0, s));
+  ok(nn_conv3x3(a.d0c, 32, n, h, w, 32, wts + layer_offset(17), 32, a.res, 3, 1, 3, 0, nullptr, 0, s, persistent));
   return e;
 }
 

@@ -1003,18 +1003,20 @@ int conv_blocks_per_cu() {
 
 hipError_t conv3x3_launch(const uint16_t* x, int ldx, int N, int H, int W, int Cin, const uint16_t* wgt, int Cout,
                           void* y, int ldy, int y_fp32, int cout_store, int epi, const uint16_t* msrc, int ldm, int ups,
-                          hipStream_t s, uint16_t* pool = nullptr, int ldp = 0,
+                          hipStream_t s, bool persistent, uint16_t* pool = nullptr, int ldp = 0,
                           const uint32_t* raw_rgba = nullptr, const float* raw_depth = nullptr,
                           const uint8_t* raw_mask = nullptr) {
   const long long tiles = (long long)N * ((H + kTileH - 1) / kTileH) * ((W + kTileW - 1) / kTileW);
   if (tiles > 0x7FFFFFFFLL) return hipErrorInvalidValue;
   const int nt = (int)tiles;
-  // One workgroup per tile, or, with one input chunk (weights staged once per
-  // workgroup), a persistent grid of the workgroups that fit, a multiple of 8.
   // A persistent grid: the workgroups that fit at once (over the ny blocks of
   // output channels), a multiple of 8, each looping over tiles; its next
   // item's patch loads overlap the current item's MFMAs across tiles too.
+  // Otherwise one workgroup per tile: compute units then free up tile by
+  // tile, so kernels on other queues get them within a tile's time rather
+  // than at the end of the layer.
   auto grid_x = [&](int per_cu, int ny) -> unsigned {
+    if (!persistent) return (unsigned)nt;
     const long long g = ((long long)device_cus() * per_cu / ny) & ~7LL;
     return (unsigned)(g >= 8 && g < nt ? g : nt);
   };
@@ -1041,28 +1043,31 @@ hipError_t conv3x3_launch(const uint16_t* x, int ldx, int N, int H, int W, int C
 }  // namespace
 
 hipError_t nn_conv3x3(const uint16_t* x, int ldx, int N, int H, int W, int Cin, const uint16_t* wgt, int Cout, void* y,
-                      int ldy, int y_fp32, int cout_store, int epi, const uint16_t* msrc, int ldm, hipStream_t s) {
-  return conv3x3_launch(x, ldx, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi, msrc, ldm, 0, s);
+                      int ldy, int y_fp32, int cout_store, int epi, const uint16_t* msrc, int ldm, hipStream_t s,
+                      bool persistent) {
+  return conv3x3_launch(x, ldx, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi, msrc, ldm, 0, s, persistent);
 }
 
 hipError_t nn_conv3x3_input(const uint32_t* rgba, const float* depth, const uint8_t* mask, int N, int H, int W,
-                            const uint16_t* wgt, int Cout, uint16_t* y, int ldy, int relu, hipStream_t s) {
+                            const uint16_t* wgt, int Cout, uint16_t* y, int ldy, int relu, hipStream_t s,
+                            bool persistent) {
   if (!rgba || !depth || !mask) return hipErrorInvalidValue;
-  return conv3x3_launch(nullptr, 32, N, H, W, 32, wgt, Cout, y, ldy, 0, Cout, relu ? 1 : 0, nullptr, 0, 0, s, nullptr, 0,
-                        rgba, depth, mask);
+  return conv3x3_launch(nullptr, 32, N, H, W, 32, wgt, Cout, y, ldy, 0, Cout, relu ? 1 : 0, nullptr, 0, 0, s,
+                        persistent, nullptr, 0, rgba, depth, mask);
 }
 
 hipError_t nn_conv3x3_pool(const uint16_t* x, int ldx, int N, int H, int W, int Cin, const uint16_t* wgt, int Cout,
-                           uint16_t* y, int ldy, int relu, uint16_t* pool, int ldp, hipStream_t s) {
+                           uint16_t* y, int ldy, int relu, uint16_t* pool, int ldp, hipStream_t s, bool persistent) {
   if (H % 2 || W % 2 || !pool) return hipErrorInvalidValue;
-  return conv3x3_launch(x, ldx, N, H, W, Cin, wgt, Cout, y, ldy, 0, Cout, relu ? 1 : 0, nullptr, 0, 0, s, pool, ldp);
+  return conv3x3_launch(x, ldx, N, H, W, Cin, wgt, Cout, y, ldy, 0, Cout, relu ? 1 : 0, nullptr, 0, 0, s, persistent,
+                        pool, ldp);
 }
 
 hipError_t nn_conv3x3_up(const uint16_t* x, int ldx, int N, int H, int W, int Cin, const uint16_t* wgt, int Cout,
                          void* y, int ldy, int y_fp32, int cout_store, int epi, const uint16_t* msrc, int ldm,
-                         hipStream_t s) {
+                         hipStream_t s, bool persistent) {
   if (H % 2 || W % 2) return hipErrorInvalidValue;
-  return conv3x3_launch(x, ldx, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi, msrc, ldm, 1, s);
+  return conv3x3_launch(x, ldx, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi, msrc, ldm, 1, s, persistent);
 }
 
 int wgrad_tco(int Cout) { return Cout % 64 == 0 ? 64 : 32; }

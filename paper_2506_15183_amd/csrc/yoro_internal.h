@@ -110,12 +110,20 @@ constexpr int kPackMaxLayers = 32;    // layers one nn_pack_model launch takes
 hipError_t nn_pack_model(const float* w, const long long* off, const int* cin, const int* cout, int layers,
                          uint16_t* wf, uint16_t* wb, hipStream_t s);
 size_t nn_wgrad_chunks(long long N, int H, int W, int Cin, int Cout);
+// The convolutions below launch a persistent grid (the workgroups that fit,
+// each looping over output tiles) unless persistent is false: then one
+// workgroup per tile, which lets kernels on other queues take compute units
+// between tiles (for work that shares the GPU with latency-critical
+// launches).
 hipError_t nn_conv3x3(const uint16_t* x, int ldx, int N, int H, int W, int Cin, const uint16_t* wgt, int Cout, void* y,
-                      int ldy, int y_fp32, int cout_store, int epi, const uint16_t* msrc, int ldm, hipStream_t s);
+                      int ldy, int y_fp32, int cout_store, int epi, const uint16_t* msrc, int ldm, hipStream_t s,
+                      bool persistent = true);
 // yoro_model_fill_tiles with a host call after each layer of the network is
 // enqueued (each chunk of crops runs the 18 layers in turn): the caller may
 // wait there, e.g. for the layer before, so that work queued behind the fill
-// on the same hardware queue waits for a layer or two at most.  Same
+// on the same hardware queue waits for a layer or two at most.  With a pace,
+// the convolutions launch one workgroup per tile (not persistent), so work
+// on other queues also gets compute units within a tile's time.  Same
 // arguments, results and errors as yoro_model_fill_tiles otherwise; an empty
 // pace is that call.
 int32_t model_fill_tiles_paced(const void* weights, const uint8_t* rgba, const float* depth, const uint8_t* mask,
@@ -133,17 +141,19 @@ int32_t model_fill_bands_paced(const void* weights, const uint8_t* rgba, const f
 // frame's RGBA, depth and mask and packing them as nn_input does, in one
 // pass; equal to nn_input then nn_conv3x3.
 hipError_t nn_conv3x3_input(const uint32_t* rgba, const float* depth, const uint8_t* mask, int N, int H, int W,
-                            const uint16_t* wgt, int Cout, uint16_t* y, int ldy, int relu, hipStream_t s);
+                            const uint16_t* wgt, int Cout, uint16_t* y, int ldy, int relu, hipStream_t s,
+                            bool persistent = true);
 // The convolution (bf16 output, optional ReLU) followed by a 2x2 average
 // pool of its stored output into `pool` (H, W even), in one pass; equal to
 // nn_conv3x3 then nn_avgpool2.
 hipError_t nn_conv3x3_pool(const uint16_t* x, int ldx, int N, int H, int W, int Cin, const uint16_t* wgt, int Cout,
-                           uint16_t* y, int ldy, int relu, uint16_t* pool, int ldp, hipStream_t s);
+                           uint16_t* y, int ldy, int relu, uint16_t* pool, int ldp, hipStream_t s,
+                           bool persistent = true);
 // The same convolution applied to the nearest x2 upsampling of x (x is
 // N x H/2 x W/2; H, W even), read in place.
 hipError_t nn_conv3x3_up(const uint16_t* x, int ldx, int N, int H, int W, int Cin, const uint16_t* wgt, int Cout,
                          void* y, int ldy, int y_fp32, int cout_store, int epi, const uint16_t* msrc, int ldm,
-                         hipStream_t s);
+                         hipStream_t s, bool persistent = true);
 hipError_t nn_conv3x3_wgrad(const uint16_t* x, int ldx, const uint16_t* dy, int lddy, int N, int H, int W, int Cin,
                             int Cout, float* dw, float* ws, hipStream_t s);
 hipError_t nn_pack_weights(const float* w, int cin, int cout, uint16_t* wf, uint16_t* wb, hipStream_t s);
