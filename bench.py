@@ -409,7 +409,7 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": "warp_batch_kernel<9>",
+            "kernel": "warp_batch_kernel<9, false>",
             "launch_ms_avg": round(float(per_launch_ms.mean()), 4),
             "launch_ms_median": round(float(np.median(per_launch_ms)), 4),
             "launch_ms_p10": round(float(np.percentile(per_launch_ms, 10)), 4),

@@ -278,8 +278,20 @@ int32_t launch_batch(const void* dev_workspace, int32_t max_width, int64_t total
       return fail(YORO_ERR_INVALID_ARG, "%s: total_rows %lld out of range", who, (long long)total_rows);
     const auto* hdr = reinterpret_cast<const yoro::BatchHeader*>(dev_workspace);
     const auto* dj = reinterpret_cast<const yoro::DevJob*>(hdr + 1);
-    // One workgroup per kBatchRows rows, the grid covering the rows once.
-    hipError_t e = yoro::launch_warp_batch(hdr, dj, max_width, (uint32_t)total_rows, (hipStream_t)hip_stream);
+    // The grid covers the rows once.  A batch that fills the resident
+    // workgroups several times over takes kBatchRows rows per workgroup (the
+    // next row's loads in flight while one finishes).  A small batch's time
+    // is the length of its workgroups' row chains: one row per workgroup
+    // while the rows fit the one-row kernel's resident workgroups (10 % over
+    // still pays: the short second wave costs less than two-row chains), two
+    // while they fit twice the multi-row kernel's.  One 1832 x 1920 frame:
+    // 21.5 us with three rows per workgroup, 15.4 with one.
+    DeviceFacts f;
+    const long long cus = device_facts(&f) ? f.cus : 256;
+    const long long one = cus * yoro::warp_blocks_per_cu(max_width, yoro::kWarpBatchOneRow);
+    const long long multi = cus * yoro::warp_blocks_per_cu(max_width, yoro::kWarpBatch);
+    const int rows = total_rows * 10 <= one * 11 ? 1 : (total_rows * 10 <= multi * 22 ? 2 : yoro::kBatchRows);
+    hipError_t e = yoro::launch_warp_batch(hdr, dj, max_width, (uint32_t)total_rows, rows, (hipStream_t)hip_stream);
     if (e != hipSuccess)
       return fail(YORO_ERR_DEVICE, "%s: launch failed: %s", who, hipGetErrorString(e));
     return ok();
@@ -344,7 +356,7 @@ int32_t yoro_reproject(const uint8_t* src_rgba, const float* src_depth, int32_t 
                target_eye, patcher ? (int32_t)YORO_FILL_NONE : fill_mode};
     const int ppt = pick_ppt(width);
     if (ppt < 0) return fail(YORO_ERR_UNSUPPORTED, "yoro_reproject: width %d too wide", width);
-    const int grid = grid_for(height, yoro::warp_blocks_per_cu(width, false));
+    const int grid = grid_for(height, yoro::warp_blocks_per_cu(width, yoro::kWarpSingle));
     hipError_t e = yoro::launch_warp_single(make_job(j, 0), ppt, grid, (hipStream_t)hip_stream);
     if (e == hipSuccess && patcher)
       e = yoro::launch_fill(reinterpret_cast<uint32_t*>(dst_rgba), dst_depth, dst_mask, width, height, target_eye,
@@ -380,7 +392,7 @@ int32_t yoro_reproject_lowres(const uint8_t* src_rgba, const float* src_depth, i
     if (lg == 0) {
       // One texel per pixel samples its own shift: the direct path, with or
       // without interpolation (the shift is read at the texel itself).
-      const int grid = grid_for(height, yoro::warp_blocks_per_cu(width, false));
+      const int grid = grid_for(height, yoro::warp_blocks_per_cu(width, yoro::kWarpSingle));
       hipError_t e = yoro::launch_warp_single(make_job(j, 0), ppt, grid, (hipStream_t)hip_stream);
       if (e == hipSuccess && patcher)
         e = yoro::launch_fill(reinterpret_cast<uint32_t*>(dst_rgba), dst_depth, dst_mask, width, height, target_eye,
@@ -520,7 +532,7 @@ int32_t yoro_reproject_hybrid(const uint8_t* src_rgba, const float* src_depth, i
     yoro_job j{src_rgba, src_depth, dst_rgba, dst_depth, dst_mask, width, height, baseline_m, focal_px,
                target_eye, patcher ? (int32_t)YORO_FILL_NONE : fill_mode};
     hipStream_t s = (hipStream_t)hip_stream;
-    hipError_t e = yoro::launch_warp_single(make_job(j, 0), ppt, grid_for(height, yoro::warp_blocks_per_cu(width, false)),
+    hipError_t e = yoro::launch_warp_single(make_job(j, 0), ppt, grid_for(height, yoro::warp_blocks_per_cu(width, yoro::kWarpSingle)),
                                             s, true, near_m);
     if (e == hipSuccess && patcher)
       e = yoro::launch_fill(reinterpret_cast<uint32_t*>(dst_rgba), dst_depth, dst_mask, width, height, target_eye,

@@ -39,7 +39,10 @@
 //
 // HBM traffic per target pixel: 4 B depth + 4 B RGBA read, 4 B RGBA written
 // (+4 B depth, +1 B mask when asked for).
+#include <atomic>
+
 #include "row_common.h"
+#include "yoro.h"
 
 namespace yoro {
 namespace {
@@ -270,23 +273,26 @@ warp_single_kernel(DevJob J, int wl, float near_m) {
 }
 
 // The batch kernel covers the batch's flat row space once: workgroup b takes
-// the kBatchRows consecutive rows from b * kBatchRows, the next row's loads
-// in flight while the current one finishes.  Workgroups start in launch
-// order, so the rows in flight stay in one window of memory (a persistent
-// grid-stride loop measured 7 % slower: its workgroups drift apart).
-template <int PPT>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(warp_waves(PPT, 7)))) void
-warp_batch_kernel(BatchHeader* hdr, const DevJob* __restrict__ jobs, int wl) {
+// the `rows` consecutive rows from b * rows (1 <= rows <= kBatchRows), the
+// next row's loads in flight while the current one finishes.  Workgroups
+// start in launch order, so the rows in flight stay in one window of memory
+// (a persistent grid-stride loop measured 7 % slower: its workgroups drift
+// apart).  ONE: the instantiation for one row per workgroup, which holds no
+// next row (38 registers instead of 66-72, 8 waves per SIMD).
+template <int PPT, bool ONE>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(warp_waves(PPT, ONE ? 8 : 7)))) void
+warp_batch_kernel(BatchHeader* hdr, const DevJob* __restrict__ jobs, int wl, uint32_t rows_arg) {
   extern __shared__ __align__(16) unsigned char smem[];
+  const uint32_t rows = ONE ? 1u : rows_arg;
   const uint32_t n = hdr->n_jobs, total = hdr->total_rows;
-  const uint64_t first = (uint64_t)blockIdx.x * kBatchRows;
+  const uint64_t first = (uint64_t)blockIdx.x * rows;
   if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) {
-    const uint64_t covered = (uint64_t)gridDim.x * kBatchRows;
+    const uint64_t covered = (uint64_t)gridDim.x * rows;
     if (total > covered) atomicAdd(&hdr->errors, (uint32_t)(total - covered));  // rows the grid does not reach
   }
   if (first >= total) return;  // uniform per workgroup, before any barrier
   uint32_t r = (uint32_t)first;
-  const uint32_t rend = total - r < (uint32_t)kBatchRows ? total : r + kBatchRows;
+  const uint32_t rend = total - r < rows ? total : r + rows;
   // The job of row r: the last whose row_start <= r (binary search).
   uint32_t lo = 0, hi = n;
   while (hi - lo > 1) {
@@ -572,21 +578,27 @@ hipError_t launch_warp_single(const DevJob& job, int ppt, int grid, hipStream_t 
   }
 }
 
-hipError_t launch_warp_batch(const BatchHeader* hdr, const DevJob* jobs, int max_width, uint32_t total_rows,
+hipError_t launch_warp_batch(const BatchHeader* hdr, const DevJob* jobs, int max_width, uint32_t total_rows, int rows,
                              hipStream_t stream) {
-  const uint64_t groups = ((uint64_t)total_rows + kBatchRows - 1) / kBatchRows;
+  if (rows < 1 || rows > kBatchRows) return hipErrorInvalidValue;
+  const uint64_t groups = ((uint64_t)total_rows + rows - 1) / rows;
   const int grid = (int)(groups > 0 ? groups : 1);
   const int ppt = ppt_for(max_width);
   const int wl = lds_width(max_width);
   const size_t lds = warp_lds_bytes(wl);
   BatchHeader* h = const_cast<BatchHeader*>(hdr);
   switch (ppt) {
-#define X(P)                                                                                        \
-  case P: {                                                                                         \
-    hipError_t e = set_lds_limit((const void*)warp_batch_kernel<P>, lds);                           \
-    if (e != hipSuccess) return e;                                                                  \
-    hipLaunchKernelGGL(warp_batch_kernel<P>, dim3(grid), dim3(kThreads), lds, stream, h, jobs, wl); \
-    return hipGetLastError();                                                                       \
+#define X(P)                                                                                              \
+  case P: {                                                                                               \
+    const void* k = rows == 1 ? (const void*)warp_batch_kernel<P, true> : (const void*)warp_batch_kernel<P, false>; \
+    hipError_t e = set_lds_limit(k, lds);                                                                 \
+    if (e != hipSuccess) return e;                                                                        \
+    if (rows == 1)                                                                                        \
+      hipLaunchKernelGGL((warp_batch_kernel<P, true>), dim3(grid), dim3(kThreads), lds, stream, h, jobs, wl, 1u); \
+    else                                                                                                  \
+      hipLaunchKernelGGL((warp_batch_kernel<P, false>), dim3(grid), dim3(kThreads), lds, stream, h, jobs, wl,    \
+                         (uint32_t)rows);                                                                 \
+    return hipGetLastError();                                                                             \
   }
     YORO_PPT_CASES(X)
 #undef X
@@ -640,7 +652,18 @@ hipError_t launch_header(BatchHeader hdr, BatchHeader* dst, hipStream_t stream) 
   return hipGetLastError();
 }
 
-int warp_blocks_per_cu(int max_width, bool batch) {
+namespace {
+// Resident workgroups per CU of the warp kernels, by kernel and LDS row
+// width (a property of the kernel, queried once per combination).
+std::atomic<int> g_warp_occupancy[3][YORO_MAX_WIDTH / 64 + 1];
+}  // namespace
+
+int warp_blocks_per_cu(int max_width, int kind) {
+  const int wl = lds_width(max_width);
+  if (wl / 64 > YORO_MAX_WIDTH / 64 || kind < 0 || kind > 2) return 1;
+  std::atomic<int>& slot = g_warp_occupancy[kind][wl / 64];
+  const int cached = slot.load(std::memory_order_relaxed);
+  if (cached > 0) return cached;
   int nb = 0;
   const int ppt = ppt_for(max_width);
   const size_t lds = warp_lds_bytes(lds_width(max_width));
@@ -648,16 +671,25 @@ int warp_blocks_per_cu(int max_width, bool batch) {
   switch (ppt) {
 #define X(P)                                                                                                      \
   case P:                                                                                                         \
-    (void)set_lds_limit(batch ? (const void*)warp_batch_kernel<P> : (const void*)warp_single_kernel<P, false>, lds); \
-    e = batch ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, warp_batch_kernel<P>, kThreads, lds)            \
-              : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, warp_single_kernel<P, false>, kThreads, lds);   \
+    if (kind == kWarpSingle) {                                                                                    \
+      (void)set_lds_limit((const void*)warp_single_kernel<P, false>, lds);                                         \
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, warp_single_kernel<P, false>, kThreads, lds);          \
+    } else if (kind == kWarpBatch) {                                                                              \
+      (void)set_lds_limit((const void*)warp_batch_kernel<P, false>, lds);                                          \
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, warp_batch_kernel<P, false>, kThreads, lds);           \
+    } else {                                                                                                      \
+      (void)set_lds_limit((const void*)warp_batch_kernel<P, true>, lds);                                           \
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, warp_batch_kernel<P, true>, kThreads, lds);            \
+    }                                                                                                             \
     break;
     YORO_PPT_CASES(X)
 #undef X
     default:
       break;
   }
-  return (e == hipSuccess && nb > 0) ? nb : 1;
+  if (e != hipSuccess || nb <= 0) return 1;
+  slot.store(nb, std::memory_order_relaxed);
+  return nb;
 }
 
 int fill_blocks_per_cu(int width, int fill_mode) {

@@ -85,10 +85,11 @@ inline int lowres_texel_slots(int max_width, int lg) {
 // near: the near-object hybrid's far field (source depth < near_m skipped).
 hipError_t launch_warp_single(const DevJob& job, int ppt, int grid, hipStream_t stream, bool near = false,
                               float near_m = 0.0f);
-// The batch kernel's grid covers the flat row space once, kBatchRows
-// consecutive rows per workgroup (total_rows: the prepared batch's rows).
+// The batch kernel's grid covers the flat row space once, `rows`
+// consecutive rows per workgroup, 1 <= rows <= kBatchRows (total_rows: the
+// rows the grid is sized for).
 constexpr int kBatchRows = 3;
-hipError_t launch_warp_batch(const BatchHeader* hdr, const DevJob* jobs, int max_width, uint32_t total_rows,
+hipError_t launch_warp_batch(const BatchHeader* hdr, const DevJob* jobs, int max_width, uint32_t total_rows, int rows,
                              hipStream_t stream);
 hipError_t launch_upload(const UploadChunk& chunk, DevJob* dst, hipStream_t stream);
 hipError_t launch_header(BatchHeader hdr, BatchHeader* dst, hipStream_t stream);
@@ -178,7 +179,11 @@ hipError_t nn_composite_tiles(const float* res, const int* plan, int k, int crop
                               const uint32_t* rgba, const uint8_t* mask, uint32_t* out, hipStream_t s);
 
 // Occupancy-derived workgroups per CU for the row kernels.
-int warp_blocks_per_cu(int max_width, bool batch);
+// Resident workgroups per CU of a warp kernel laid out for max_width columns:
+// the single-frame kernel, the batch kernel, or its one-row-per-workgroup
+// instantiation.
+enum { kWarpSingle = 0, kWarpBatch = 1, kWarpBatchOneRow = 2 };
+int warp_blocks_per_cu(int max_width, int kind);
 int fill_blocks_per_cu(int width, int fill_mode);
 
 // The near-object hybrid (hybrid.hip): the near layer of a box-and-sphere

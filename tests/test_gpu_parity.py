@@ -5,6 +5,8 @@ oracle's on the same seeded inputs.
 """
 from __future__ import annotations
 
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -216,6 +218,29 @@ def test_batch_mixed_resolutions_matches_oracle(cuda):
     for s, (rgba, depth), d in zip(specs, frames, dev):
         o = orc.reproject(rgba, depth, s.baseline_m, s.focal_px, s.target_eye, 1, nthreads=0)
         assert_same((d[2].cpu().numpy(), d[3].cpu().numpy(), d[4].cpu().numpy()), o, f"{s.width}x{s.height}")
+
+
+@pytest.mark.parametrize("n_frames", [1, 2, 3, 6])
+def test_batch_rows_per_workgroup_regimes(cuda, n_frames):
+    """Batches of 1, 2, 3 and 6 frames of 1440 x 1600 (1600 to 9600 rows):
+    the launcher takes one, two or three rows per workgroup depending on how
+    the rows compare with the resident workgroups; every frame bit-exact,
+    both eyes, RGBA-only and full outputs."""
+    torch, yoro = _gpu()
+    specs = [dataclasses.replace(config2_frame(10 + i), width=1440, height=1600) for i in range(n_frames)]
+    frames, dev = _batch_inputs(specs)
+    for full in (True, False):
+        jobs = [yoro.make_job(d[0], d[1], d[2], d[3] if full else None, d[4] if full else None, s.baseline_m,
+                              s.focal_px, L if i % 2 else R, 1) for i, (s, d) in enumerate(zip(specs, dev))]
+        batch = yoro.StereoBatch(jobs)
+        batch.run()
+        torch.cuda.synchronize()
+        assert batch.errors() == 0
+        for i, (s, (rgba, depth), d) in enumerate(zip(specs, frames, dev)):
+            o = orc.reproject(rgba, depth, s.baseline_m, s.focal_px, L if i % 2 else R, 1, nthreads=0)
+            assert np.array_equal(d[2].cpu().numpy(), o[0]), (n_frames, i, full)
+            if full:
+                assert_same((d[2].cpu().numpy(), d[3].cpu().numpy(), d[4].cpu().numpy()), o, f"{n_frames}/{i}")
 
 
 def test_batch_graph_replay_and_order_independence(cuda):
