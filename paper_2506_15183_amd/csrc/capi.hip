@@ -180,6 +180,17 @@ yoro::DevJob make_job(const yoro_job& j, uint32_t row_start) {
   return d;
 }
 
+// Grid of the single-frame warp: one workgroup per row when the rows fit
+// the one-row kernel's resident workgroups (10 % over still pays), else a
+// persistent grid.
+int warp_grid(int width, int height) {
+  DeviceFacts f;
+  const long long cus = device_facts(&f) ? f.cus : 256;
+  const long long one = cus * yoro::warp_blocks_per_cu(width, yoro::kWarpSingleOneRow);
+  if ((long long)height * 10 <= one * 11) return height;
+  return (int)std::max<long long>(1, std::min<long long>(height, cus * yoro::warp_blocks_per_cu(width, yoro::kWarpSingle)));
+}
+
 int grid_for(int rows, int blocks_per_cu) {
   DeviceFacts f;
   const int cus = device_facts(&f) ? f.cus : 256;
@@ -356,8 +367,7 @@ int32_t yoro_reproject(const uint8_t* src_rgba, const float* src_depth, int32_t 
                target_eye, patcher ? (int32_t)YORO_FILL_NONE : fill_mode};
     const int ppt = pick_ppt(width);
     if (ppt < 0) return fail(YORO_ERR_UNSUPPORTED, "yoro_reproject: width %d too wide", width);
-    const int grid = grid_for(height, yoro::warp_blocks_per_cu(width, yoro::kWarpSingle));
-    hipError_t e = yoro::launch_warp_single(make_job(j, 0), ppt, grid, (hipStream_t)hip_stream);
+    hipError_t e = yoro::launch_warp_single(make_job(j, 0), ppt, warp_grid(width, height), (hipStream_t)hip_stream);
     if (e == hipSuccess && patcher)
       e = yoro::launch_fill(reinterpret_cast<uint32_t*>(dst_rgba), dst_depth, dst_mask, width, height, target_eye,
                             fill_mode, ppt, grid_for(height, yoro::fill_blocks_per_cu(width, fill_mode)),
@@ -392,8 +402,7 @@ int32_t yoro_reproject_lowres(const uint8_t* src_rgba, const float* src_depth, i
     if (lg == 0) {
       // One texel per pixel samples its own shift: the direct path, with or
       // without interpolation (the shift is read at the texel itself).
-      const int grid = grid_for(height, yoro::warp_blocks_per_cu(width, yoro::kWarpSingle));
-      hipError_t e = yoro::launch_warp_single(make_job(j, 0), ppt, grid, (hipStream_t)hip_stream);
+      hipError_t e = yoro::launch_warp_single(make_job(j, 0), ppt, warp_grid(width, height), (hipStream_t)hip_stream);
       if (e == hipSuccess && patcher)
         e = yoro::launch_fill(reinterpret_cast<uint32_t*>(dst_rgba), dst_depth, dst_mask, width, height, target_eye,
                               fill_mode, ppt, grid_for(height, yoro::fill_blocks_per_cu(width, fill_mode)),
@@ -532,8 +541,7 @@ int32_t yoro_reproject_hybrid(const uint8_t* src_rgba, const float* src_depth, i
     yoro_job j{src_rgba, src_depth, dst_rgba, dst_depth, dst_mask, width, height, baseline_m, focal_px,
                target_eye, patcher ? (int32_t)YORO_FILL_NONE : fill_mode};
     hipStream_t s = (hipStream_t)hip_stream;
-    hipError_t e = yoro::launch_warp_single(make_job(j, 0), ppt, grid_for(height, yoro::warp_blocks_per_cu(width, yoro::kWarpSingle)),
-                                            s, true, near_m);
+    hipError_t e = yoro::launch_warp_single(make_job(j, 0), ppt, warp_grid(width, height), s, true, near_m);
     if (e == hipSuccess && patcher)
       e = yoro::launch_fill(reinterpret_cast<uint32_t*>(dst_rgba), dst_depth, dst_mask, width, height, target_eye,
                             fill_mode, ppt, grid_for(height, yoro::fill_blocks_per_cu(width, fill_mode)), s);

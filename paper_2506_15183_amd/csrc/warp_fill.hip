@@ -245,8 +245,10 @@ constexpr int warp_waves(int ppt, int cap) {
   return ppt <= 9 ? cap : (fit < 1 ? 1 : (fit < cap ? fit : cap));
 }
 
-template <int PPT, bool NEAR>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(warp_waves(PPT, 6)))) void
+// ONE: one row per workgroup (the grid is the frame's height), no next row
+// held in registers, 8 waves per SIMD; otherwise a persistent grid.
+template <int PPT, bool NEAR, bool ONE>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(warp_waves(PPT, ONE ? 8 : 6)))) void
 warp_single_kernel(DevJob J, int wl, float near_m) {
   extern __shared__ __align__(16) unsigned char smem[];
   RowLds s(smem, wl);
@@ -264,9 +266,10 @@ warp_single_kernel(DevJob J, int wl, float near_m) {
     scatter_row<PPT, NEAR>(Jr, cur, s, wl, near_m);
     const int yn = y + gridDim.x;
     __builtin_amdgcn_s_setprio(3);
-    if (yn < Jr.height) load_row<PPT>(Jr, yn, cur);
+    if (!ONE && yn < Jr.height) load_row<PPT>(Jr, yn, cur);
     __syncthreads();
     finish_row<PPT>(Jr, y, s);
+    if (ONE) break;
     __builtin_amdgcn_s_setprio(0);
     __syncthreads();  // the next row reuses the LDS
   }
@@ -557,18 +560,29 @@ hipError_t set_lds_limit(const void* fn, size_t bytes) {
 hipError_t launch_warp_single(const DevJob& job, int ppt, int grid, hipStream_t stream, bool near, float near_m) {
   const int wl = lds_width(job.width);
   const size_t lds = warp_lds_bytes(wl);
+  // A grid of one workgroup per row runs the one-row instantiation.
+  const bool one = grid >= job.height;
   switch (ppt) {
 #define X(P)                                                                                                 \
   case P: {                                                                                                  \
-    const void* k = near ? (const void*)warp_single_kernel<P, true> : (const void*)warp_single_kernel<P, false>; \
+    const void* k = near ? (one ? (const void*)warp_single_kernel<P, true, true>                             \
+                                : (const void*)warp_single_kernel<P, true, false>)                           \
+                         : (one ? (const void*)warp_single_kernel<P, false, true>                            \
+                                : (const void*)warp_single_kernel<P, false, false>);                         \
     hipError_t e = set_lds_limit(k, lds);                                                                    \
     if (e != hipSuccess) return e;                                                                           \
-    if (near)                                                                                                \
-      hipLaunchKernelGGL((warp_single_kernel<P, true>), dim3(grid), dim3(kThreads), lds, stream, job, wl,    \
-                         near_m);                                                                            \
+    if (near && one)                                                                                         \
+      hipLaunchKernelGGL((warp_single_kernel<P, true, true>), dim3(job.height), dim3(kThreads), lds, stream, \
+                         job, wl, near_m);                                                                   \
+    else if (near)                                                                                           \
+      hipLaunchKernelGGL((warp_single_kernel<P, true, false>), dim3(grid), dim3(kThreads), lds, stream, job, \
+                         wl, near_m);                                                                        \
+    else if (one)                                                                                            \
+      hipLaunchKernelGGL((warp_single_kernel<P, false, true>), dim3(job.height), dim3(kThreads), lds, stream, \
+                         job, wl, 0.0f);                                                                     \
     else                                                                                                     \
-      hipLaunchKernelGGL((warp_single_kernel<P, false>), dim3(grid), dim3(kThreads), lds, stream, job, wl,   \
-                         0.0f);                                                                              \
+      hipLaunchKernelGGL((warp_single_kernel<P, false, false>), dim3(grid), dim3(kThreads), lds, stream, job, \
+                         wl, 0.0f);                                                                          \
     return hipGetLastError();                                                                                \
   }
     YORO_PPT_CASES(X)
@@ -655,12 +669,12 @@ hipError_t launch_header(BatchHeader hdr, BatchHeader* dst, hipStream_t stream) 
 namespace {
 // Resident workgroups per CU of the warp kernels, by kernel and LDS row
 // width (a property of the kernel, queried once per combination).
-std::atomic<int> g_warp_occupancy[3][YORO_MAX_WIDTH / 64 + 1];
+std::atomic<int> g_warp_occupancy[4][YORO_MAX_WIDTH / 64 + 1];
 }  // namespace
 
 int warp_blocks_per_cu(int max_width, int kind) {
   const int wl = lds_width(max_width);
-  if (wl / 64 > YORO_MAX_WIDTH / 64 || kind < 0 || kind > 2) return 1;
+  if (wl / 64 > YORO_MAX_WIDTH / 64 || kind < 0 || kind > 3) return 1;
   std::atomic<int>& slot = g_warp_occupancy[kind][wl / 64];
   const int cached = slot.load(std::memory_order_relaxed);
   if (cached > 0) return cached;
@@ -672,8 +686,11 @@ int warp_blocks_per_cu(int max_width, int kind) {
 #define X(P)                                                                                                      \
   case P:                                                                                                         \
     if (kind == kWarpSingle) {                                                                                    \
-      (void)set_lds_limit((const void*)warp_single_kernel<P, false>, lds);                                         \
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, warp_single_kernel<P, false>, kThreads, lds);          \
+      (void)set_lds_limit((const void*)warp_single_kernel<P, false, false>, lds);                                  \
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, warp_single_kernel<P, false, false>, kThreads, lds);   \
+    } else if (kind == kWarpSingleOneRow) {                                                                       \
+      (void)set_lds_limit((const void*)warp_single_kernel<P, false, true>, lds);                                   \
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, warp_single_kernel<P, false, true>, kThreads, lds);    \
     } else if (kind == kWarpBatch) {                                                                              \
       (void)set_lds_limit((const void*)warp_batch_kernel<P, false>, lds);                                          \
       e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, warp_batch_kernel<P, false>, kThreads, lds);           \

@@ -83,6 +83,8 @@ inline int lowres_texel_slots(int max_width, int lg) {
 
 // Launchers (defined in warp_fill.hip).  They return hipSuccess or the launch error.
 // near: the near-object hybrid's far field (source depth < near_m skipped).
+// grid >= the frame's height: one workgroup per row (the one-row kernel);
+// otherwise a persistent grid of `grid` workgroups.
 hipError_t launch_warp_single(const DevJob& job, int ppt, int grid, hipStream_t stream, bool near = false,
                               float near_m = 0.0f);
 // The batch kernel's grid covers the flat row space once, `rows`
@@ -180,9 +182,9 @@ hipError_t nn_composite_tiles(const float* res, const int* plan, int k, int crop
 
 // Occupancy-derived workgroups per CU for the row kernels.
 // Resident workgroups per CU of a warp kernel laid out for max_width columns:
-// the single-frame kernel, the batch kernel, or its one-row-per-workgroup
-// instantiation.
-enum { kWarpSingle = 0, kWarpBatch = 1, kWarpBatchOneRow = 2 };
+// the single-frame kernel, the batch kernel, or their one-row-per-workgroup
+// instantiations.
+enum { kWarpSingle = 0, kWarpBatch = 1, kWarpBatchOneRow = 2, kWarpSingleOneRow = 3 };
 int warp_blocks_per_cu(int max_width, int kind);
 int fill_blocks_per_cu(int width, int fill_mode);
 
