@@ -259,7 +259,7 @@ int32_t prepare_batch(const yoro_job* jobs, int32_t n_jobs, void* dev_workspace,
     h.total_rows = (uint32_t)rows;
     h.max_width = (uint32_t)max_w;
     h.errors = 0;
-    hipError_t e = yoro::launch_header(h, hdr, s);
+    hipError_t e = hipSuccess;
     uint32_t row = 0;
     for (int32_t first = 0; e == hipSuccess && first < n_jobs; first += yoro::kUploadChunk) {
       yoro::UploadChunk c{};
@@ -269,7 +269,7 @@ int32_t prepare_batch(const yoro_job* jobs, int32_t n_jobs, void* dev_workspace,
         c.jobs[k] = make_job(jobs[first + k], row);
         row += (uint32_t)jobs[first + k].height;
       }
-      e = yoro::launch_upload(c, dj, s);
+      e = yoro::launch_upload(c, dj, h, first == 0 ? hdr : nullptr, s);  // the first launch writes the header too
     }
     if (e != hipSuccess)
       return fail(YORO_ERR_DEVICE, "yoro_stereo_batch_prepare: upload failed: %s", hipGetErrorString(e));

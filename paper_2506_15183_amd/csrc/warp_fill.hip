@@ -538,13 +538,13 @@ __global__ __launch_bounds__(kThreads) void hole_sse_kernel(const uint32_t* __re
 }
 
 // ---------------------------------------------------------------------------
-__global__ void upload_kernel(UploadChunk chunk, DevJob* dst) {
+// Job records (and, with hdst, the batch header) carried in the kernel
+// arguments, written to the device table: a prepare takes one launch per 24
+// jobs and no host-to-device copy.
+__global__ void upload_kernel(UploadChunk chunk, DevJob* dst, BatchHeader h, BatchHeader* hdst) {
   const uint32_t t = threadIdx.x;
   if (t < chunk.count) dst[chunk.first + t] = chunk.jobs[t];
-}
-
-__global__ void header_kernel(BatchHeader h, BatchHeader* dst) {
-  if (threadIdx.x == 0) *dst = h;
+  if (hdst && t == 0) *hdst = h;
 }
 
 // ---------------------------------------------------------------------------
@@ -656,13 +656,9 @@ hipError_t launch_hole_sse(const uint32_t* rgba, const uint32_t* ref, const uint
   return hipGetLastError();
 }
 
-hipError_t launch_upload(const UploadChunk& chunk, DevJob* dst, hipStream_t stream) {
-  hipLaunchKernelGGL(upload_kernel, dim3(1), dim3(64), 0, stream, chunk, dst);
-  return hipGetLastError();
-}
-
-hipError_t launch_header(BatchHeader hdr, BatchHeader* dst, hipStream_t stream) {
-  hipLaunchKernelGGL(header_kernel, dim3(1), dim3(64), 0, stream, hdr, dst);
+hipError_t launch_upload(const UploadChunk& chunk, DevJob* dst, const BatchHeader& hdr, BatchHeader* hdst,
+                         hipStream_t stream) {
+  hipLaunchKernelGGL(upload_kernel, dim3(1), dim3(64), 0, stream, chunk, dst, hdr, hdst);
   return hipGetLastError();
 }
 

@@ -93,8 +93,10 @@ hipError_t launch_warp_single(const DevJob& job, int ppt, int grid, hipStream_t 
 constexpr int kBatchRows = 3;
 hipError_t launch_warp_batch(const BatchHeader* hdr, const DevJob* jobs, int max_width, uint32_t total_rows, int rows,
                              hipStream_t stream);
-hipError_t launch_upload(const UploadChunk& chunk, DevJob* dst, hipStream_t stream);
-hipError_t launch_header(BatchHeader hdr, BatchHeader* dst, hipStream_t stream);
+// Writes chunk.count job records at dst + chunk.first and, if hdst is not
+// null, hdr at hdst, from the kernel's arguments.
+hipError_t launch_upload(const UploadChunk& chunk, DevJob* dst, const BatchHeader& hdr, BatchHeader* hdst,
+                         hipStream_t stream);
 hipError_t launch_fill(uint32_t* rgba, float* depth, uint8_t* mask, int32_t width, int32_t height,
                        int32_t target_eye, int32_t fill_mode, int ppt, int grid, hipStream_t stream);
 hipError_t launch_hole_sse(const uint32_t* rgba, const uint32_t* ref, const uint8_t* mask, int64_t n,
