@@ -714,8 +714,19 @@ int32_t yoro_stereo_batch(const yoro_job* jobs, int32_t n_jobs, void* dev_worksp
             model->workspace_bytes < yoro_model_workspace_bytes(1, jobs[i].height, jobs[i].width))
           return fail(YORO_ERR_WORKSPACE_TOO_SMALL, "%s: job %d: model workspace too small", who, i);
     }
-    st = prepare_batch(jobs, n_jobs, dev_workspace, workspace_bytes, hip_stream, true);
-    if (st == YORO_OK) st = launch_batch(dev_workspace, max_w, rows, hip_stream, who);
+    if (n_jobs == 1) {
+      // One frame: the single-frame kernel warps it and writes the batch
+      // table itself (one launch instead of an upload and a batch launch);
+      // the workspace then holds the same one-job batch as after prepare.
+      const hipError_t e = yoro::launch_warp_single(make_job(jobs[0], 0), pick_ppt(jobs[0].width),
+                                                    warp_grid(jobs[0].width, jobs[0].height),
+                                                    (hipStream_t)hip_stream, false, 0.0f,
+                                                    reinterpret_cast<yoro::BatchHeader*>(dev_workspace));
+      st = e == hipSuccess ? YORO_OK : fail(YORO_ERR_DEVICE, "%s: launch failed: %s", who, hipGetErrorString(e));
+    } else {
+      st = prepare_batch(jobs, n_jobs, dev_workspace, workspace_bytes, hip_stream, true);
+      if (st == YORO_OK) st = launch_batch(dev_workspace, max_w, rows, hip_stream, who);
+    }
     if (st != YORO_OK || !any_learned) return st;
     for (int32_t i = 0; i < n_jobs && st == YORO_OK; ++i) {
       const yoro_job& j = jobs[i];

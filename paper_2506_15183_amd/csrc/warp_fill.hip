@@ -246,11 +246,21 @@ constexpr int warp_waves(int ppt, int cap) {
 }
 
 // ONE: one row per workgroup (the grid is the frame's height), no next row
-// held in registers, 8 waves per SIMD; otherwise a persistent grid.
+// held in registers, 8 waves per SIMD; otherwise a persistent grid.  table:
+// null, or a batch workspace that receives this frame as a one-job batch
+// (header and job record, written by one thread; no row is ever skipped).
 template <int PPT, bool NEAR, bool ONE>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(warp_waves(PPT, ONE ? 8 : 6)))) void
-warp_single_kernel(DevJob J, int wl, float near_m) {
+warp_single_kernel(DevJob J, int wl, float near_m, BatchHeader* table) {
   extern __shared__ __align__(16) unsigned char smem[];
+  if (table && blockIdx.x == 0 && threadIdx.x == 0) {
+    BatchHeader h{};
+    h.n_jobs = 1;
+    h.total_rows = (uint32_t)J.height;
+    h.max_width = (uint32_t)J.width;
+    *table = h;
+    *reinterpret_cast<DevJob*>(table + 1) = J;
+  }
   RowLds s(smem, wl);
   clear_keys(s, wl);
   RowIn<PPT> cur;
@@ -557,7 +567,8 @@ hipError_t set_lds_limit(const void* fn, size_t bytes) {
 
 }  // namespace
 
-hipError_t launch_warp_single(const DevJob& job, int ppt, int grid, hipStream_t stream, bool near, float near_m) {
+hipError_t launch_warp_single(const DevJob& job, int ppt, int grid, hipStream_t stream, bool near, float near_m,
+                              BatchHeader* table) {
   const int wl = lds_width(job.width);
   const size_t lds = warp_lds_bytes(wl);
   // A grid of one workgroup per row runs the one-row instantiation.
@@ -573,16 +584,16 @@ hipError_t launch_warp_single(const DevJob& job, int ppt, int grid, hipStream_t 
     if (e != hipSuccess) return e;                                                                           \
     if (near && one)                                                                                         \
       hipLaunchKernelGGL((warp_single_kernel<P, true, true>), dim3(job.height), dim3(kThreads), lds, stream, \
-                         job, wl, near_m);                                                                   \
+                         job, wl, near_m, table);                                                            \
     else if (near)                                                                                           \
       hipLaunchKernelGGL((warp_single_kernel<P, true, false>), dim3(grid), dim3(kThreads), lds, stream, job, \
-                         wl, near_m);                                                                        \
+                         wl, near_m, table);                                                                 \
     else if (one)                                                                                            \
       hipLaunchKernelGGL((warp_single_kernel<P, false, true>), dim3(job.height), dim3(kThreads), lds, stream, \
-                         job, wl, 0.0f);                                                                     \
+                         job, wl, 0.0f, table);                                                              \
     else                                                                                                     \
       hipLaunchKernelGGL((warp_single_kernel<P, false, false>), dim3(grid), dim3(kThreads), lds, stream, job, \
-                         wl, 0.0f);                                                                          \
+                         wl, 0.0f, table);                                                                   \
     return hipGetLastError();                                                                                \
   }
     YORO_PPT_CASES(X)

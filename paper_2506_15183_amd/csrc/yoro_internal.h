@@ -84,9 +84,10 @@ inline int lowres_texel_slots(int max_width, int lg) {
 // Launchers (defined in warp_fill.hip).  They return hipSuccess or the launch error.
 // near: the near-object hybrid's far field (source depth < near_m skipped).
 // grid >= the frame's height: one workgroup per row (the one-row kernel);
-// otherwise a persistent grid of `grid` workgroups.
+// otherwise a persistent grid of `grid` workgroups.  table: null, or a batch
+// workspace to receive the frame as a one-job batch (header, job record).
 hipError_t launch_warp_single(const DevJob& job, int ppt, int grid, hipStream_t stream, bool near = false,
-                              float near_m = 0.0f);
+                              float near_m = 0.0f, BatchHeader* table = nullptr);
 // The batch kernel's grid covers the flat row space once, `rows`
 // consecutive rows per workgroup, 1 <= rows <= kBatchRows (total_rows: the
 // rows the grid is sized for).

@@ -243,6 +243,37 @@ def test_batch_rows_per_workgroup_regimes(cuda, n_frames):
                 assert_same((d[2].cpu().numpy(), d[3].cpu().numpy(), d[4].cpu().numpy()), o, f"{n_frames}/{i}")
 
 
+def test_one_frame_batch_writes_its_table(cuda):
+    """yoro_stereo_batch with one job runs the single-frame kernel, which also
+    writes the one-job table: the workspace then holds the same header and
+    record as after yoro_stereo_batch_prepare, a later launch on it gives
+    the same frame, and no row is reported skipped."""
+    torch, yoro = _gpu()
+    spec = config2_frame(3)
+    frames, dev = _batch_inputs([spec])
+    d = dev[0]
+    job = yoro.make_job(d[0], d[1], d[2], d[3], d[4], spec.baseline_m, spec.focal_px, L, 1)
+    fast = yoro.StereoBatch([job])
+    fast.workspace.fill_(0xAB)
+    fast.run()
+    torch.cuda.synchronize()
+    assert fast.errors() == 0
+    o = orc.reproject(*frames[0], spec.baseline_m, spec.focal_px, L, 1, nthreads=0)
+    assert_same((d[2].cpu().numpy(), d[3].cpu().numpy(), d[4].cpu().numpy()), o, "one-job batch")
+    prepared = yoro.StereoBatch([job])
+    prepared.workspace.fill_(0xAB)
+    prepared.prepare()
+    torch.cuda.synchronize()
+    n = 64 + 72  # header and the one job record
+    assert torch.equal(fast.workspace[:n], prepared.workspace[:n])
+    for t in d[2:]:
+        t.zero_()
+    fast.launch()
+    torch.cuda.synchronize()
+    assert fast.errors() == 0
+    assert_same((d[2].cpu().numpy(), d[3].cpu().numpy(), d[4].cpu().numpy()), o, "relaunch")
+
+
 def test_batch_graph_replay_and_order_independence(cuda):
     torch, yoro = _gpu()
     specs = config3_frames(n_per_size=1)
