@@ -78,8 +78,11 @@ __device__ __forceinline__ u32x4 input_channels(uint32_t c, float z, uint8_t m) 
 constexpr int conv_waves(int ct) { return ct <= 32 ? 3 : 2; }
 
 // RAW: the first layer, whose input is the frame itself (raw_rgba, ...).
-template <int CT, bool RAW>
-__global__ __launch_bounds__(kConvThreads) __attribute__((amdgpu_waves_per_eu(conv_waves(CT)))) void
+// NW: input chunks whose weights stay in LDS for every item (1, or 2 for the
+// 64-input-channel layers of a 32-channel tile, which then stage no weights
+// per item).
+template <int CT, bool RAW, int NW = 1>
+__global__ __launch_bounds__(kConvThreads) __attribute__((amdgpu_waves_per_eu(NW > 1 ? 2 : conv_waves(CT)))) void
 conv3x3_tiled_kernel(const uint16_t* __restrict__ x, int ldx, int N,
                                                                      int H, int W, int Cin,
                                                                      const uint16_t* __restrict__ wgt, int Cout,
@@ -97,23 +100,27 @@ conv3x3_tiled_kernel(const uint16_t* __restrict__ x, int ldx, int N,
                     ((reinterpret_cast<uintptr_t>(y) | reinterpret_cast<uintptr_t>(msrc)) & 7u) == 0;
   __shared__ __align__(16) uint16_t patch[kPatchH * kPatchW * kPatchStride];
   // The chunk's weights for all nine taps: [tap][output channel][32 + 8 pad].
-  __shared__ __align__(16) uint16_t wlds[9 * CT * kPatchStride];
+  __shared__ __align__(16) uint16_t wlds[NW * 9 * CT * kPatchStride];
   const int tiles_x = (W + kTileW - 1) / kTileW, tiles_y = (H + kTileH - 1) / kTileH;
   const int co0 = blockIdx.y * CT;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int kg = (lane >> 4) * 8;
+  // Chunk ci0's weights go to slot (ci0 / 32) % NW.
   auto stage_weights = [&](int ci0) {
+    uint16_t* slot = wlds + ((ci0 >> 5) % NW) * (9 * CT * kPatchStride);
     for (int e = threadIdx.x; e < 9 * CT * 4; e += kConvThreads) {
       const int tc = e >> 2, part = e & 3;  // tc = tap * CT + output channel
       const int t = tc / CT, co = tc - t * CT;
-      *reinterpret_cast<u32x4*>(wlds + tc * kPatchStride + part * 8) =
+      *reinterpret_cast<u32x4*>(slot + tc * kPatchStride + part * 8) =
           *reinterpret_cast<const u32x4*>(wgt + ((long long)t * Cout + co0 + co) * Cin + ci0 + part * 8);
     }
   };
-  // With one input chunk the weights stay in LDS for every tile this
-  // workgroup takes; otherwise each chunk of each tile stages its own.
-  const bool one_chunk = Cin == 32;
-  if (one_chunk) stage_weights(0);
+  // When every input chunk's weights fit (Cin = 32 NW) they stay in LDS for
+  // every tile this workgroup takes; otherwise each chunk of each tile
+  // stages its own.
+  const bool one_chunk = Cin == 32 * NW;
+  if (one_chunk)
+    for (int c = 0; c < NW; ++c) stage_weights(32 * c);
   // Tiles v = blockIdx.x, + gridDim.x, ... in an XCD-aware order: workgroup
   // w runs on XCD w % 8 (gridDim.x is a multiple of 8 or the whole tile
   // count), and each XCD takes one contiguous range of tiles, so tiles that
@@ -202,7 +209,8 @@ conv3x3_tiled_kernel(const uint16_t* __restrict__ x, int ldx, int N,
       u32x4 bcur[NB];
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb)
-        bcur[nb] = *reinterpret_cast<const u32x4*>(wlds + (t * CT + nb * 16 + (lane & 15)) * kPatchStride + kg);
+        bcur[nb] = *reinterpret_cast<const u32x4*>(wlds + ((ci0 >> 5) % NW) * (9 * CT * kPatchStride) +
+                                                   (t * CT + nb * 16 + (lane & 15)) * kPatchStride + kg);
       const int ky = t / 3, kx = t % 3;
 #pragma unroll
       for (int m = 0; m < 4; ++m) {
@@ -990,11 +998,11 @@ int device_cus() {
   return c;
 }
 
-template <int CT, bool RAW>
+template <int CT, bool RAW, int NW = 1>
 int conv_blocks_per_cu() {
   static const int nb = [] {
     int v = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, conv3x3_tiled_kernel<CT, RAW>, kConvThreads, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, conv3x3_tiled_kernel<CT, RAW, NW>, kConvThreads, 0) != hipSuccess)
       v = 0;
     return v > 0 ? v : 1;
   }();
@@ -1033,6 +1041,11 @@ hipError_t conv3x3_launch(const uint16_t* x, int ldx, int N, int H, int W, int C
     hipLaunchKernelGGL((conv3x3_tiled_kernel<64, false>), dim3(grid_x(conv_blocks_per_cu<64, false>(), Cout / 64), Cout / 64),
                        dim3(kConvThreads), 0, s, x, ldx, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi,
                        msrc, ldm, ups, nt, pool, ldp, raw_rgba, raw_depth, raw_mask);
+  } else if (Cin == 64) {  // both input chunks' weights resident
+    hipLaunchKernelGGL((conv3x3_tiled_kernel<32, false, 2>),
+                       dim3(grid_x(conv_blocks_per_cu<32, false, 2>(), Cout / 32), Cout / 32), dim3(kConvThreads), 0,
+                       s, x, ldx, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi, msrc, ldm, ups, nt, pool,
+                       ldp, raw_rgba, raw_depth, raw_mask);
   } else {
     hipLaunchKernelGGL((conv3x3_tiled_kernel<32, false>), dim3(grid_x(conv_blocks_per_cu<32, false>(), Cout / 32), Cout / 32),
                        dim3(kConvThreads), 0, s, x, ldx, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi,
