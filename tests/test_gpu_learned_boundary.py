@@ -55,16 +55,19 @@ def test_fill_holes_learned_equals_plain_then_model_fill(cuda):
         assert (got[~hits] != plain[0][~hits]).any()                 # holes refined
 
 
-def test_stereo_batch_mixes_plain_and_learned_jobs(cuda):
+@pytest.mark.parametrize("n_frames", [4, 1])
+def test_stereo_batch_mixes_plain_and_learned_jobs(cuda, n_frames):
+    """A batch of plain and learned jobs; with one frame, a single learned
+    job (the one-launch path for one-frame batches, then the network)."""
     torch, yoro, unet, train = _t()
     net = _net(unet, train)
-    specs = config3_frames(n_per_size=1)
+    specs = config3_frames(n_per_size=1)[4 - n_frames:]
     frames = [s.render_source() for s in specs]
     src = [(torch.from_numpy(r).cuda(), torch.from_numpy(d).cuda()) for r, d in frames]
     outs = [(torch.empty((s.height, s.width, 4), dtype=torch.uint8, device="cuda"),
              torch.empty((s.height, s.width), dtype=torch.float32, device="cuda"),
              torch.empty((s.height, s.width), dtype=torch.uint8, device="cuda")) for s in specs]
-    modes = [yoro.FILL_LEARNED if i % 2 else yoro.FILL_NEAREST_BG for i in range(len(specs))]
+    modes = [yoro.FILL_LEARNED if (i % 2 or len(specs) == 1) else yoro.FILL_NEAREST_BG for i in range(len(specs))]
     jobs = [yoro.make_job(a, b, *o, s.baseline_m, s.focal_px, s.target_eye, md)
             for s, (a, b), o, md in zip(specs, src, outs, modes)]
     big = max((s for s, md in zip(specs, modes) if md == yoro.FILL_LEARNED), key=lambda s: s.pixels)
