@@ -342,6 +342,8 @@ def main():
     ap.add_argument("--learned-interval-ms", type=float, default=0.0)
     ap.add_argument("--progressive", action="store_true",
                     help="learned policy: release frames at the warp, refine them in place afterwards")
+    ap.add_argument("--band", type=int, default=Config.band,
+                    help="learned policy: refine full-width bands of this many rows (0: 128-pixel hole tiles)")
     a = ap.parse_args()
     log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
     hs = config5_headsets(a.headsets, a.seed)
@@ -351,7 +353,7 @@ def main():
 
         model = unet.UNet("cuda", params=train.load_weights(a.weights or train.DEFAULT_WEIGHTS))
     cfg = Config(budget_bytes=int(a.budget_gb * 1e9), learned_min_interval_ms=a.learned_interval_ms,
-                 progressive=a.progressive)
+                 progressive=a.progressive, band=a.band)
     srv = Server(hs, cfg, pool_renderer(sparse=a.sparse), model=model, log=log)
     trace = make_trace(hs, a.seconds, cfg.n_sources, seed=a.seed)
     log(f"{len(trace)} arrivals over {a.seconds} s")
