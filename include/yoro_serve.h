@@ -19,7 +19,8 @@
  * holes; the others keep the plain fill.  A frame whose headset's previous counted frame was above the
  * threshold is released as soon as its warp is done (fallback predicted, no
  * wait for its own count), and while a headset falls back its holes are
- * counted on every 8th frame only (holes = -1 in the results of the others).
+ * counted on every 8th frame only, every 64th while its last count was above
+ * twice the threshold (holes = -1 in the results of the others).
  * Refinements start at least learned_min_interval_ns apart (a GPU-time
  * budget); a frame that comes sooner, or while a refinement runs, keeps the
  * plain fill (path BUSY) and is released as soon as its warp is done.  One refinement runs at a time; a frame that

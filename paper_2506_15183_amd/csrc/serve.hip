@@ -88,8 +88,10 @@ struct Batch {
 };
 
 // While a headset's frames fall back, its hole fraction is re-counted on
-// every kRecount-th frame only (a frame that may be refined is always counted).
+// every kRecount-th frame only, every kRecountFar-th while its last count was
+// above twice the threshold (a frame that may be refined is always counted).
 constexpr int kRecount = 8;
+constexpr int kRecountFar = 64;
 
 }  // namespace
 
@@ -443,7 +445,8 @@ int32_t yoro_serve_run(const yoro_serve_headset* headsets, int32_t n_headsets, c
           results[k].path = YORO_PATH_PLAIN, results[k].done_ns = tn;
         } else if (last_frac[h] > (double)O.learned_max_hole_fraction) {
           results[k].path = YORO_PATH_FALLBACK, results[k].done_ns = tn;
-          if (++since_count[h] >= kRecount) B.counted[i] = 1, since_count[h] = 0;
+          const int every = last_frac[h] > 2.0 * (double)O.learned_max_hole_fraction ? kRecountFar : kRecount;
+          if (++since_count[h] >= every) B.counted[i] = 1, since_count[h] = 0;
         } else if (l_active || (l_started >= 0 && tn - l_started < O.learned_min_interval_ns)) {
           // No refinement could start now: the plain fill is final.
           results[k].path = YORO_PATH_BUSY, results[k].done_ns = tn;
