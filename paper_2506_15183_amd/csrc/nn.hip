@@ -36,6 +36,16 @@ __device__ __forceinline__ uint32_t to_bf16x2(float lo, float hi) {
   return __builtin_bit_cast(uint32_t, v);
 }
 __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+// Signed 16-bit max of two packed bf16 values with the halves of `floor`
+// (one v_pk_max_i16).
+__device__ __forceinline__ uint32_t relu_bf16x2(uint32_t v, uint32_t floor) {
+  typedef short short2_t __attribute__((ext_vector_type(2)));
+  // (Opaque to the compiler: otherwise it splits a packed conversion that
+  // feeds this max into two single ones and a permute.)
+  asm("" : "+v"(v));
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(short2_t, v),
+                                                                __builtin_bit_cast(short2_t, floor)));
+}
 
 __device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
 
@@ -96,8 +106,18 @@ conv3x3_tiled_kernel(const uint16_t* __restrict__ x, int ldx, int N,
   constexpr int NB = CT / 16;
   // 8-byte output stores: bf16 output, channel groups of 4 whole, and 8-byte
   // aligned rows (the launcher checks the base pointers).
-  const bool wide = !y_fp32 && (cout_store & 3) == 0 && (ldy & 3) == 0 && (epi != 2 || (ldm & 3) == 0) &&
+  // Offsets inside a tile's rows of every buffer fit 32 bits (the usual
+  // case): interior tiles then load their patch, and the 8-byte path stores
+  // its outputs, through one base address per tile and 32-bit per-lane byte
+  // offsets (no 64-bit address arithmetic per lane).
+  const long long ld_max = max(max(ldx, ldy), max(ldm, ldp));
+  const bool small = 2LL * (kPatchH + 1) * W * ld_max < (1LL << 31);
+  const bool wide = small && !y_fp32 && (cout_store & 3) == 0 && (ldy & 3) == 0 && (epi != 2 || (ldm & 3) == 0) &&
                     ((reinterpret_cast<uintptr_t>(y) | reinterpret_cast<uintptr_t>(msrc)) & 7u) == 0;
+  // ReLU on two packed bf16 values: a signed 16-bit max with 0 zeroes the
+  // negative ones (as max(v, 0) before rounding would); with -32768 it
+  // changes nothing.
+  const uint32_t relu_floor = epi == 1 ? 0u : 0x80008000u;
   __shared__ __align__(16) uint16_t patch[kPatchH * kPatchW * kPatchStride];
   // The chunk's weights for all nine taps: [tap][output channel][32 + 8 pad].
   __shared__ __align__(16) uint16_t wlds[NW * 9 * CT * kPatchStride];
@@ -150,6 +170,37 @@ conv3x3_tiled_kernel(const uint16_t* __restrict__ x, int ldx, int N,
     int x0, y0, n;
     origin(v, x0, y0, n);
     const long long img = (long long)n * H * W;
+    if (small && x0 >= 1 && y0 >= 1 && x0 + kPatchW - 1 <= W && y0 + kPatchH - 1 <= H) {
+      // An interior tile: the patch lies inside the frame, so no clamping,
+      // and every element sits at a fixed offset from the patch's top-left
+      // pixel (y0 - 1, x0 - 1); an upsampled input reads the
+      // half-resolution pixel under it, (y0 / 2 - 1, x0 / 2 - 1) on.
+      const long long base = ups ? (img >> 2) + (long long)((y0 >> 1) - 1) * (W >> 1) + ((x0 >> 1) - 1)
+                                 : img + (long long)(y0 - 1) * W + (x0 - 1);
+      inside_bits = ~0u;
+      // The per-lane offsets are recomputed for each tile (a few
+      // instructions) rather than held in registers across the loop.
+      int tid = threadIdx.x;
+      asm volatile("" : "+v"(tid));
+#pragma unroll
+      for (int k = 0; k < kPatchLoads; ++k) {
+        const int e = tid + k * kConvThreads;
+        // Entries past the patch (skipped when stored) read its first pixel.
+        const int pix = e < kPatchH * kPatchW * 4 ? e >> 2 : 0;
+        const int py = pix / kPatchW, px = pix - py * kPatchW;
+        const uint32_t rel = ups ? (uint32_t)(((py + 1) >> 1) * (W >> 1) + ((px + 1) >> 1)) : (uint32_t)(py * W + px);
+        if (RAW) {
+          const char* rb = reinterpret_cast<const char*>(raw_rgba + base);
+          const char* db = reinterpret_cast<const char*>(raw_depth + base);
+          pre[k] = u32x4{*reinterpret_cast<const uint32_t*>(rb + rel * 4u),
+                         *reinterpret_cast<const uint32_t*>(db + rel * 4u), (uint32_t)(raw_mask + base)[rel], 0u};
+        } else {
+          const char* xb = reinterpret_cast<const char*>(x + (base * ldx + ci0));
+          pre[k] = *reinterpret_cast<const u32x4*>(xb + (rel * (uint32_t)ldx + (uint32_t)(e & 3) * 8u) * 2u);
+        }
+      }
+      return;
+    }
     inside_bits = 0;
 #pragma unroll
     for (int k = 0; k < kPatchLoads; ++k) {
@@ -176,9 +227,15 @@ conv3x3_tiled_kernel(const uint16_t* __restrict__ x, int ldx, int N,
 #pragma unroll
     for (int k = 0; k < kPatchLoads; ++k) {
       const int e = threadIdx.x + k * kConvThreads;
+      u32x4 v = pre[k];
+      // Every lane takes its loaded value here, also where it stores none,
+      // so the wait for the load is not left pending on one branch (a
+      // pending load makes the compiler wait for every outstanding memory
+      // operation, the previous tile's stores included, before the next
+      // loads).
+      asm volatile("" : : "v"(v));
       if (e >= kPatchH * kPatchW * 4) continue;
       const bool inside = (inside_bits >> k) & 1u;
-      u32x4 v = pre[k];
       // The first layer: its packed input (Cin 32) built channel by channel
       // as the input-packing kernel does, in the first 8 channels.
       if (RAW) v = (e & 3) == 0 ? input_channels(v[0], __uint_as_float(v[1]), (uint8_t)v[2]) : u32x4{0u, 0u, 0u, 0u};
@@ -239,42 +296,48 @@ conv3x3_tiled_kernel(const uint16_t* __restrict__ x, int ldx, int N,
     // DPP exchanges) gives lane j = lane%4 pixel 4*(lane/16) + j's four
     // channels 4q..4q+3, stored as one 8-byte write instead of four 2-byte
     // ones.  The values are those of the per-element path below.
-    const int j = lane & 3, q = (lane >> 2) & 3, g = lane >> 4;
+    // Per-lane offsets and selectors are recomputed for each tile rather
+    // than held in registers across the loop (the opaque copy of the lane
+    // index keeps the compiler from hoisting them).
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
+    const int j = ln & 3, q = (ln >> 2) & 3, g = ln >> 4;
+    // v_perm byte selectors (result byte i = byte sel[i] of the pair
+    // {first operand: bytes 4..7, second: bytes 0..3}).
+    const uint32_t sel_s = (j & 1) ? 0x05040100u : 0x07060302u;
+    const uint32_t sel_lo = j == 0 ? 0x05040100u : j == 1 ? 0x03020504u : j == 2 ? 0x07060100u : 0x03020706u;
+    const uint32_t sel_hi = j == 0 ? 0x07060100u : j == 1 ? 0x03020706u : j == 2 ? 0x05040100u : 0x03020504u;
+    char* yb = reinterpret_cast<char*>(y) + 2 * ((img + (long long)y0 * W + x0) * ldy + co0);
+    const char* mb =
+        epi == 2 ? reinterpret_cast<const char*>(msrc) + 2 * ((img + (long long)y0 * W + x0) * ldm + co0) : nullptr;
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
-      const int gy = y0 + 2 * wave + (m >> 1), gx = x0 + (m & 1) * 16 + g * 4 + j;
-      const bool in = gy < H && gx < W;
-      const long long p = img + (long long)(in ? gy : 0) * W + (in ? gx : 0);
+      const int row = 2 * wave + (m >> 1), col = (m & 1) * 16 + g * 4 + j;
+      const bool in = y0 + row < H && x0 + col < W;
+      const uint32_t po = (uint32_t)(row * W + col);
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        float f[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) f[r] = epi == 1 ? fmaxf(acc[m][nb][r], 0.0f) : acc[m][nb][r];
-        const uint32_t A = to_bf16x2(f[0], f[1]), B = to_bf16x2(f[2], f[3]);
-        // Lanes j and j ^ 2 swap pixel pairs: each keeps the pair holding
-        // its own pixel, for its channel (own) and channel j ^ 2 (recv).
+        // A: pixels 4g, 4g + 1 of channel 4q + j; B: pixels 4g + 2, 4g + 3.
+        const uint32_t A = relu_bf16x2(to_bf16x2(acc[m][nb][0], acc[m][nb][1]), relu_floor);
+        const uint32_t B = relu_bf16x2(to_bf16x2(acc[m][nb][2], acc[m][nb][3]), relu_floor);
+        // Lanes j and j ^ 2 swap pixel pairs: own is the pair holding pixel
+        // 4g + j in channel j, recv the same pair in channel j ^ 2.
         const uint32_t own = (j & 2) ? B : A;
         const uint32_t recv = (uint32_t)__builtin_amdgcn_mov_dpp((int)((j & 2) ? A : B), 0x4E, 0xF, 0xF, true);
-        // Lanes j and j ^ 1 swap the halves for each other's pixel.
-        const int sh_mine = (j & 1) * 16, sh_other = 16 - sh_mine;
-        const uint32_t S = ((own >> sh_other) & 0xFFFFu) | (((recv >> sh_other) & 0xFFFFu) << 16);
+        // Lanes j and j ^ 1 swap the pair's other pixel in both channels: R
+        // holds pixel 4g + j in channels j ^ 1 (low half) and j ^ 3 (high).
+        const uint32_t S = __builtin_amdgcn_perm(recv, own, sel_s);
         const uint32_t R = (uint32_t)__builtin_amdgcn_mov_dpp((int)S, 0xB1, 0xF, 0xF, true);
-        // Channels j, j ^ 1, j ^ 2, j ^ 3 of pixel j; channel c is entry c ^ j.
-        uint32_t w01 = ((own >> sh_mine) & 0xFFFFu) | ((R & 0xFFFFu) << 16);  // entries 0, 1
-        uint32_t w23 = ((recv >> sh_mine) & 0xFFFFu) | (R & 0xFFFF0000u);     // entries 2, 3
-        if (j & 2) {
-          const uint32_t t = w01;
-          w01 = w23;
-          w23 = t;
-        }
-        if (j & 1) {
-          w01 = (w01 >> 16) | (w01 << 16);
-          w23 = (w23 >> 16) | (w23 << 16);
-        }
-        const int co = co0 + nb * 16 + 4 * q;
-        if (!in || co >= cout_store) continue;
+        // Channels 4q, 4q + 1 from R and the word holding the even channel
+        // of j's pair {j, j ^ 2}; channels 4q + 2, 4q + 3 from R and the other.
+        const uint32_t even = (j & 2) ? recv : own, odd = (j & 2) ? own : recv;
+        uint32_t w01 = __builtin_amdgcn_perm(R, even, sel_lo);
+        uint32_t w23 = __builtin_amdgcn_perm(R, odd, sel_hi);
+        const int co = nb * 16 + 4 * q;
+        if (!in || co0 + co >= cout_store) continue;
+        const uint32_t off = (po * (uint32_t)ldy + (uint32_t)co) * 2u;
         if (epi == 2) {  // ReLU derivative: zero where the forward activation was not positive
-          const uint2 mk = *reinterpret_cast<const uint2*>(msrc + p * ldm + co);
+          const uint2 mk = *reinterpret_cast<const uint2*>(mb + (po * (uint32_t)ldm + (uint32_t)co) * 2u);
           const uint32_t mw[2] = {mk.x, mk.y};
           uint32_t* ww[2] = {&w01, &w23};
 #pragma unroll
@@ -283,7 +346,7 @@ conv3x3_tiled_kernel(const uint16_t* __restrict__ x, int ldx, int N,
             if (!(from_bf16((uint16_t)(mw[u] >> 16)) > 0.0f)) *ww[u] &= 0x0000FFFFu;
           }
         }
-        *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(y) + p * ldy + co) = uint2{w01, w23};
+        *reinterpret_cast<uint2*>(yb + off) = uint2{w01, w23};
       }
     }
   } else {
@@ -312,7 +375,38 @@ conv3x3_tiled_kernel(const uint16_t* __restrict__ x, int ldx, int N,
   // Optional 2x2 average pool of the stored bf16 outputs (H, W even): a
   // window is rows 2*wave, 2*wave + 1 (M tiles m and m + 2) and columns
   // r, r + 1 (r even) of one lane, summed as the pooling kernel sums them.
-  if (pool) {
+  if (pool && small) {
+    // The same sums from the rounded, rectified values as packed words, at
+    // 32-bit offsets from the tile's first pooled pixel.
+    const int Ho = H >> 1, Wo = W >> 1;
+    const long long imgo = (long long)n * Ho * Wo;
+    const int yo = (y0 >> 1) + wave;
+    char* pb = reinterpret_cast<char*>(pool) + 2 * ((imgo + (long long)(y0 >> 1) * Wo + (x0 >> 1)) * ldp + co0);
+    // (Recomputed rather than kept from the stores above: holding those
+    // words until here would cost registers.)
+    uint32_t floor = relu_floor;
+    asm volatile("" : "+s"(floor));
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int co = nb * 16 + (ln & 15);
+#pragma unroll
+        for (int r = 0; r < 4; r += 2) {
+          const int xr = ((m & 1) * 16 + (ln >> 4) * 4 + r) >> 1;
+          if (yo >= Ho || (x0 >> 1) + xr >= Wo || co0 + co >= cout_store) continue;
+          const uint32_t T = relu_bf16x2(to_bf16x2(acc[m][nb][r], acc[m][nb][r + 1]), floor);
+          const uint32_t U = relu_bf16x2(to_bf16x2(acc[m + 2][nb][r], acc[m + 2][nb][r + 1]), floor);
+          const float sum = (__uint_as_float(T << 16) + __uint_as_float(T & 0xFFFF0000u)) +
+                            (__uint_as_float(U << 16) + __uint_as_float(U & 0xFFFF0000u));
+          const uint32_t off = ((uint32_t)(wave * Wo + xr) * (uint32_t)ldp + (uint32_t)co) * 2u;
+          *reinterpret_cast<uint16_t*>(pb + off) = to_bf16(sum * 0.25f);
+        }
+      }
+    }
+  } else if (pool) {
     const int Ho = H >> 1, Wo = W >> 1;
     const long long imgo = (long long)n * Ho * Wo;
     const int yo = (y0 >> 1) + wave;
