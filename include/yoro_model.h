@@ -53,10 +53,12 @@ size_t yoro_model_workspace_bytes(int32_t n, int32_t h, int32_t w);
  * in the workspace (read them after the call, e.g. to check each layer):
  * offsets[18] in bytes from the workspace's start, of NHWC bf16 buffers in
  * this order, with their channels per pixel (level l has (h >> l) x (w >> l)
- * pixels per image): e0a 32; c0 64 (d0a, then e0b); d0b 32; d0c 32; p1 32;
- * e1a 64; c1 128 (d1a, e1b); d1b 64; d1c 64; p2 64; e2a 128; c2 256 (d2a,
- * e2b); d2b 128; d2c 128; p3 128; e3a 256; e3b 256; and the FP32 residual,
- * 3 per pixel (yoro_model_residual writes the caller's res instead). */
+ * pixels per image): e0a 32; c0 64 (d0a, then e0b; held as two planes, all
+ * pixels' 32 channels of d0a, then all pixels' 32 channels of e0b); d0b 32;
+ * d0c 32; p1 32; e1a 64; c1 128 (d1a, e1b); d1b 64; d1c 64; p2 64; e2a 128;
+ * c2 256 (d2a, e2b); d2b 128; d2c 128; p3 128; e3a 256; e3b 256; and the
+ * FP32 residual, 3 per pixel (yoro_model_residual writes the caller's res
+ * instead). */
 #define YORO_MODEL_ACTIVATIONS 18
 int32_t yoro_model_workspace_layout(int32_t n, int32_t h, int32_t w, int64_t* offsets);
 

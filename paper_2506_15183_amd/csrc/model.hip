@@ -44,7 +44,11 @@ int32_t model_fail(int32_t status, const char* fmt, ...) {
 bool al16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 bool al4(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }
 
-// Activation buffers of one forward pass (bf16 NHWC; res FP32 [P0][3]).
+// Activation buffers of one forward pass (bf16 NHWC; res FP32 [P0][3]),
+// except c0, the full-resolution concatenation, which holds its two
+// 32-channel halves as planes ([2][P0][32]: d0a, then e0b): its writers
+// then store whole 64-byte pixel records, and its reader takes the second
+// input chunk from the second plane.
 struct Acts {
   uint16_t *e0a, *c0, *d0b, *d0c;
   uint16_t *p1, *e1a, *c1, *d1b, *d1c;
@@ -87,11 +91,12 @@ hipError_t forward(const uint16_t* wts, const uint8_t* rgba, const float* depth,
     if (e == hipSuccess) e = r;
     if (e == hipSuccess && pace && *pace) e = (*pace)();
   };
-  auto conv = [&](int i, const uint16_t* x, int ldx, int lev, uint16_t* y, int ldy) {
+  auto conv = [&](int i, const uint16_t* x, int ldx, int lev, uint16_t* y, int ldy, long long xcs = 32) {
     const Layer L = kLayers[i];
     ok(nn_conv3x3(x, ldx, n, h >> lev, w >> lev, L.cin, wts + layer_offset(i), L.cout, y, ldy, 0, L.cout, 1, nullptr,
-                  0, s, persistent));
+                  0, s, persistent, xcs));
   };
+  const long long plane0 = (long long)n * h * w * 32;  // one 32-channel plane of c0
   // The first convolution packs the frame's channels itself (no packed copy).
   // The encoders' second convolutions also write the 2x2 average pool of
   // their output (the next level's input) in the same pass.
@@ -102,7 +107,7 @@ hipError_t forward(const uint16_t* wts, const uint8_t* rgba, const float* depth,
   };
   ok(nn_conv3x3_input(reinterpret_cast<const uint32_t*>(rgba), depth, mask, n, h, w, wts + layer_offset(0),
                       kLayers[0].cout, a.e0a, 32, 1, s, persistent));
-  conv_pool(1, a.e0a, 32, 0, a.c0 + 32, 64, a.p1, 32);  // e0b -> the skip half of c0, and its pool
+  conv_pool(1, a.e0a, 32, 0, a.c0 + plane0, 32, a.p1, 32);  // e0b -> the skip plane of c0, and its pool
   conv(2, a.p1, 32, 1, a.e1a, 64);
   conv_pool(3, a.e1a, 64, 1, a.c1 + 64, 128, a.p2, 64);  // e1b
   conv(4, a.p2, 64, 2, a.e2a, 128);
@@ -122,8 +127,8 @@ hipError_t forward(const uint16_t* wts, const uint8_t* rgba, const float* depth,
   conv_up(11, a.d2c, 128, 1, a.c1, 128);  // d1a
   conv(12, a.c1, 128, 1, a.d1b, 64);
   conv(13, a.d1b, 64, 1, a.d1c, 64);
-  conv_up(14, a.d1c, 64, 0, a.c0, 64);  // d0a
-  conv(15, a.c0, 64, 0, a.d0b, 32);
+  conv_up(14, a.d1c, 64, 0, a.c0, 32);  // d0a -> the decoder plane of c0
+  conv(15, a.c0, 32, 0, a.d0b, 32, plane0);
   conv(16, a.d0b, 32, 0, a.d0c, 32);
   // Head: FP32 residual, the first 3 of its 32 padded outputs, no activation.
   ok(nn_conv3x3(a.d0c, 32, n, h, w, 32, wts + layer_offset(17), 32, a.res, 3, 1, 3, 0, nullptr, 0, s, persistent));

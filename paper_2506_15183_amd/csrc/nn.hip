@@ -93,7 +93,7 @@ constexpr int conv_waves(int ct) { return ct <= 32 ? 3 : 2; }
 // per item).
 template <int CT, bool RAW, int NW = 1>
 __global__ __launch_bounds__(kConvThreads) __attribute__((amdgpu_waves_per_eu(NW > 1 ? 2 : conv_waves(CT)))) void
-conv3x3_tiled_kernel(const uint16_t* __restrict__ x, int ldx, int N,
+conv3x3_tiled_kernel(const uint16_t* __restrict__ x, int ldx, long long xcs, int N,
                                                                      int H, int W, int Cin,
                                                                      const uint16_t* __restrict__ wgt, int Cout,
                                                                      void* __restrict__ y, int ldy, int y_fp32,
@@ -195,7 +195,7 @@ conv3x3_tiled_kernel(const uint16_t* __restrict__ x, int ldx, int N,
           pre[k] = u32x4{*reinterpret_cast<const uint32_t*>(rb + rel * 4u),
                          *reinterpret_cast<const uint32_t*>(db + rel * 4u), (uint32_t)(raw_mask + base)[rel], 0u};
         } else {
-          const char* xb = reinterpret_cast<const char*>(x + (base * ldx + ci0));
+          const char* xb = reinterpret_cast<const char*>(x + (base * ldx + (ci0 >> 5) * xcs));
           pre[k] = *reinterpret_cast<const u32x4*>(xb + (rel * (uint32_t)ldx + (uint32_t)(e & 3) * 8u) * 2u);
         }
       }
@@ -219,7 +219,7 @@ conv3x3_tiled_kernel(const uint16_t* __restrict__ x, int ldx, int N,
         // x2 upsampling, read in place.
         const long long src = ups ? (img >> 2) + (long long)(cy >> 1) * (W >> 1) + (cx >> 1)
                                   : img + (long long)cy * W + cx;
-        pre[k] = *reinterpret_cast<const u32x4*>(x + src * ldx + ci0 + part * 8);
+        pre[k] = *reinterpret_cast<const u32x4*>(x + src * ldx + (ci0 >> 5) * xcs + part * 8);
       }
     }
   };
@@ -1107,7 +1107,7 @@ hipError_t conv3x3_launch(const uint16_t* x, int ldx, int N, int H, int W, int C
                           void* y, int ldy, int y_fp32, int cout_store, int epi, const uint16_t* msrc, int ldm, int ups,
                           hipStream_t s, bool persistent, uint16_t* pool = nullptr, int ldp = 0,
                           const uint32_t* raw_rgba = nullptr, const float* raw_depth = nullptr,
-                          const uint8_t* raw_mask = nullptr) {
+                          const uint8_t* raw_mask = nullptr, long long xcs = 32) {
   const long long tiles = (long long)N * ((H + kTileH - 1) / kTileH) * ((W + kTileW - 1) / kTileW);
   if (tiles > 0x7FFFFFFFLL) return hipErrorInvalidValue;
   const int nt = (int)tiles;
@@ -1125,24 +1125,24 @@ hipError_t conv3x3_launch(const uint16_t* x, int ldx, int N, int H, int W, int C
   if (raw_rgba) {  // the first layer (Cin 32, Cout a multiple of 32)
     if (Cin != 32 || Cout % 32 != 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL((conv3x3_tiled_kernel<32, true>), dim3(grid_x(conv_blocks_per_cu<32, true>(), Cout / 32), Cout / 32),
-                       dim3(kConvThreads), 0, s, x, ldx, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi,
+                       dim3(kConvThreads), 0, s, x, ldx, xcs, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi,
                        msrc, ldm, ups, nt, pool, ldp, raw_rgba, raw_depth, raw_mask);
   } else if (cout_store <= 16) {  // e.g. the 3-channel head: only the first 16 outputs are computed
     hipLaunchKernelGGL((conv3x3_tiled_kernel<16, false>), dim3(grid_x(conv_blocks_per_cu<16, false>(), 1), 1),
-                       dim3(kConvThreads), 0, s, x, ldx, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi,
+                       dim3(kConvThreads), 0, s, x, ldx, xcs, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi,
                        msrc, ldm, ups, nt, pool, ldp, raw_rgba, raw_depth, raw_mask);
   } else if (Cout % 64 == 0) {
     hipLaunchKernelGGL((conv3x3_tiled_kernel<64, false>), dim3(grid_x(conv_blocks_per_cu<64, false>(), Cout / 64), Cout / 64),
-                       dim3(kConvThreads), 0, s, x, ldx, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi,
+                       dim3(kConvThreads), 0, s, x, ldx, xcs, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi,
                        msrc, ldm, ups, nt, pool, ldp, raw_rgba, raw_depth, raw_mask);
   } else if (Cin == 64) {  // both input chunks' weights resident
     hipLaunchKernelGGL((conv3x3_tiled_kernel<32, false, 2>),
                        dim3(grid_x(conv_blocks_per_cu<32, false, 2>(), Cout / 32), Cout / 32), dim3(kConvThreads), 0,
-                       s, x, ldx, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi, msrc, ldm, ups, nt, pool,
+                       s, x, ldx, xcs, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi, msrc, ldm, ups, nt, pool,
                        ldp, raw_rgba, raw_depth, raw_mask);
   } else {
     hipLaunchKernelGGL((conv3x3_tiled_kernel<32, false>), dim3(grid_x(conv_blocks_per_cu<32, false>(), Cout / 32), Cout / 32),
-                       dim3(kConvThreads), 0, s, x, ldx, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi,
+                       dim3(kConvThreads), 0, s, x, ldx, xcs, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi,
                        msrc, ldm, ups, nt, pool, ldp, raw_rgba, raw_depth, raw_mask);
   }
   return hipGetLastError();
@@ -1151,8 +1151,10 @@ hipError_t conv3x3_launch(const uint16_t* x, int ldx, int N, int H, int W, int C
 
 hipError_t nn_conv3x3(const uint16_t* x, int ldx, int N, int H, int W, int Cin, const uint16_t* wgt, int Cout, void* y,
                       int ldy, int y_fp32, int cout_store, int epi, const uint16_t* msrc, int ldm, hipStream_t s,
-                      bool persistent) {
-  return conv3x3_launch(x, ldx, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi, msrc, ldm, 0, s, persistent);
+                      bool persistent, long long xcs) {
+  if (xcs < 32 || xcs % 8 != 0) return hipErrorInvalidValue;
+  return conv3x3_launch(x, ldx, N, H, W, Cin, wgt, Cout, y, ldy, y_fp32, cout_store, epi, msrc, ldm, 0, s, persistent,
+                        nullptr, 0, nullptr, nullptr, nullptr, xcs);
 }
 
 hipError_t nn_conv3x3_input(const uint32_t* rgba, const float* depth, const uint8_t* mask, int N, int H, int W,

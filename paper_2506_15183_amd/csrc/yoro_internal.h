@@ -121,9 +121,12 @@ size_t nn_wgrad_chunks(long long N, int H, int W, int Cin, int Cout);
 // workgroup per tile, which lets kernels on other queues take compute units
 // between tiles (for work that shares the GPU with latency-critical
 // launches).
+// xcs: elements from one 32-channel input chunk to the next (32 for NHWC
+// x; larger when x keeps its channel chunks in separate planes, each
+// [pixels][ldx]).
 hipError_t nn_conv3x3(const uint16_t* x, int ldx, int N, int H, int W, int Cin, const uint16_t* wgt, int Cout, void* y,
                       int ldy, int y_fp32, int cout_store, int epi, const uint16_t* msrc, int ldm, hipStream_t s,
-                      bool persistent = true);
+                      bool persistent = true, long long xcs = 32);
 // yoro_model_fill_tiles with a host call after each layer of the network is
 // enqueued (each chunk of crops runs the 18 layers in turn): the caller may
 // wait there, e.g. for the layer before, so that work queued behind the fill

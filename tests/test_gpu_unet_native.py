@@ -86,7 +86,10 @@ def test_native_forward_per_layer_and_end_to_end(cuda):
         h, w = H >> lev, W >> lev
         o = int(offs[k])
         bits = host[o:o + h * w * c * 2].view(np.uint16).astype(np.uint32) << 16
-        act[nm] = bits.view(np.float32).astype(np.float64).reshape(1, h, w, c)
+        v = bits.view(np.float32).astype(np.float64)
+        if nm == "c0":  # two planes of 32 channels (d0a, then e0b)
+            v = v.reshape(2, h * w, 32).transpose(1, 0, 2)
+        act[nm] = v.reshape(1, h, w, c)
     relu = lambda v: np.maximum(v, 0.0)  # noqa: E731
     x = U.bf16(U.make_input(rgba[None], depth[None], mask[None]))
     checks = [
