@@ -135,6 +135,32 @@ conv3x3_tiled_kernel(const uint16_t* __restrict__ x, int ldx, long long xcs, int
           *reinterpret_cast<const u32x4*>(wgt + ((long long)t * Cout + co0 + co) * Cin + ci0 + part * 8);
     }
   };
+  // 64-channel tiles: the next item's chunk weights (nine 16-byte pieces
+  // per thread) are loaded into registers with its patch and written to LDS
+  // at its start, so their load overlaps this item's MFMAs like the patch's.
+  // Narrower tiles load and stage them at the item's start.
+  constexpr bool kPreW = CT == 64;
+  constexpr int kWLoads = 9 * CT * 4 / kConvThreads;
+  u32x4 wpre[kPreW ? kWLoads : 1];
+  auto load_weights = [&](int ci0) {
+    int tid = threadIdx.x;  // (recomputed per item rather than held across the loop)
+    asm volatile("" : "+v"(tid));
+#pragma unroll
+    for (int k = 0; k < kWLoads; ++k) {
+      const int e = tid + k * kConvThreads;
+      const int tc = e >> 2, part = e & 3;
+      const int t = tc / CT, co = tc - t * CT;
+      wpre[k] = *reinterpret_cast<const u32x4*>(wgt + ((long long)t * Cout + co0 + co) * Cin + ci0 + part * 8);
+    }
+  };
+  auto store_weights = [&](int ci0) {
+    uint16_t* slot = wlds + ((ci0 >> 5) % NW) * (9 * CT * kPatchStride);
+#pragma unroll
+    for (int k = 0; k < kWLoads; ++k) {
+      const int e = threadIdx.x + k * kConvThreads;
+      *reinterpret_cast<u32x4*>(slot + (e >> 2) * kPatchStride + (e & 3) * 8) = wpre[k];
+    }
+  };
   // When every input chunk's weights fit (Cin = 32 NW) they stay in LDS for
   // every tile this workgroup takes; otherwise each chunk of each tile
   // stages its own.
@@ -249,18 +275,29 @@ conv3x3_tiled_kernel(const uint16_t* __restrict__ x, int ldx, long long xcs, int
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[m][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
   int v = blockIdx.x, ci0 = 0;
-  if (v < ntiles) load_patch(v, 0);
+  if (v < ntiles) {
+    load_patch(v, 0);
+    if (kPreW && !one_chunk) load_weights(0);
+  }
   while (v < ntiles) {
     __syncthreads();  // the previous item's readers are done with the patch (and the weights)
     store_patch();
-    if (!one_chunk) stage_weights(ci0);
+    if (!one_chunk) {
+      if (kPreW)
+        store_weights(ci0);
+      else
+        stage_weights(ci0);
+    }
     int vn = v, cn = ci0 + 32;
     if (cn == Cin) {
       vn = v + gridDim.x;
       cn = 0;
     }
     __syncthreads();
-    if (vn < ntiles) load_patch(vn, cn);
+    if (vn < ntiles) {
+      load_patch(vn, cn);
+      if (kPreW && !one_chunk) load_weights(cn);
+    }
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
       u32x4 bcur[NB];
