@@ -111,7 +111,7 @@ conv3x3_tiled_kernel(const uint16_t* __restrict__ x, int ldx, long long xcs, int
   // its outputs, through one base address per tile and 32-bit per-lane byte
   // offsets (no 64-bit address arithmetic per lane).
   const long long ld_max = max(max(ldx, ldy), max(ldm, ldp));
-  const bool small = 2LL * (kPatchH + 1) * W * ld_max < (1LL << 31);
+  const bool small = 4LL * (kPatchH + 1) * W * ld_max < (1LL << 31);
   const bool wide = small && !y_fp32 && (cout_store & 3) == 0 && (ldy & 3) == 0 && (epi != 2 || (ldm & 3) == 0) &&
                     ((reinterpret_cast<uintptr_t>(y) | reinterpret_cast<uintptr_t>(msrc)) & 7u) == 0;
   // ReLU on two packed bf16 values: a signed 16-bit max with 0 zeroes the
@@ -384,6 +384,27 @@ conv3x3_tiled_kernel(const uint16_t* __restrict__ x, int ldx, long long xcs, int
           }
         }
         *reinterpret_cast<uint2*>(yb + off) = uint2{w01, w23};
+      }
+    }
+  } else if (y_fp32 && small && epi != 2) {
+    // FP32 outputs (the head's residual): the per-element stores below, at
+    // 32-bit offsets from the tile's first output.
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
+    char* yb = reinterpret_cast<char*>(y) + 4 * ((img + (long long)y0 * W + x0) * ldy + co0);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int row = 2 * wave + (m >> 1);
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const int co = nb * 16 + (ln & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int col = (m & 1) * 16 + (ln >> 4) * 4 + r;
+          if (y0 + row >= H || x0 + col >= W || co0 + co >= cout_store) continue;
+          const float v = epi == 1 ? fmaxf(acc[m][nb][r], 0.0f) : acc[m][nb][r];
+          *reinterpret_cast<float*>(yb + ((uint32_t)(row * W + col) * (uint32_t)ldy + (uint32_t)co) * 4u) = v;
+        }
       }
     }
   } else {
