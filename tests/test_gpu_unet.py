@@ -97,6 +97,41 @@ def test_conv_fp32_head_with_store_limit(cuda):
     assert rel_l2(y.cpu().numpy(), want) < 1e-5
 
 
+def test_conv_with_strides_beyond_32_bit_tile_offsets(cuda):
+    """A pixel stride so large that a tile's rows no longer fit 32-bit byte
+    offsets sends the kernel to its general path (clamped 64-bit addresses,
+    per-element stores); its outputs equal those of the same convolution on a
+    compact input, and the oracle's."""
+    torch, G = _t()
+    L = G.nnlib()
+    rng = np.random.default_rng(5)
+    n, h, w, cin, cout = 1, 10, 40, 32, 32      # ragged: 2 tile rows, 2 tile columns
+    # elements per input pixel record: 4-byte offsets over 11 rows of w
+    # pixels exceed 2^31 (a multiple of 8, as the call requires)
+    ldx = ((1 << 31) // (44 * w) // 8 + 8) * 8
+    assert 44 * w * ldx >= 1 << 31
+    x = U.bf16(rng.normal(size=(n, h, w, cin)))
+    wt = U.bf16(rng.normal(0, np.sqrt(2 / (9 * cin)), size=(9, cout, cin)))
+    wf = torch.empty(9 * cout * cin, dtype=torch.bfloat16, device="cuda")
+    wb = torch.empty_like(wf)
+    G._ok(L.yoro_nn_pack_weights(G._p(torch.from_numpy(wt.astype(np.float32)).cuda()), cin, cout, G._p(wf),
+                                 G._p(wb), None))
+    xd = bf(x.reshape(-1, cin))
+    big = torch.empty((n * h * w, ldx), dtype=torch.bfloat16, device="cuda")  # about 1 GB; 32 per row set
+    big[:, :cin] = xd
+    y_ref = torch.empty((n * h * w, cout), dtype=torch.bfloat16, device="cuda")
+    y_big = torch.full_like(y_ref, 3.0)
+    G._ok(L.yoro_nn_conv3x3(G._p(xd), cin, n, h, w, cin, G._p(wf), cout, G._p(y_ref), cout, 0, cout, 1, None, 0,
+                            None))
+    G._ok(L.yoro_nn_conv3x3(G._p(big), ldx, n, h, w, cin, G._p(wf), cout, G._p(y_big), cout, 0, cout, 1, None, 0,
+                            None))
+    torch.cuda.synchronize()
+    assert np.array_equal(npf(y_big), npf(y_ref))
+    want = U.bf16(np.maximum(U.conv3x3(x, wt), 0)).reshape(-1, cout)
+    assert close_frac(npf(y_big), want) >= 0.999
+    del big
+
+
 def test_weight_gradient(cuda):
     torch, G = _t()
     L = G.nnlib()
