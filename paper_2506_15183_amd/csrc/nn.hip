@@ -36,15 +36,15 @@ __device__ __forceinline__ uint32_t to_bf16x2(float lo, float hi) {
   return __builtin_bit_cast(uint32_t, v);
 }
 __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-// Signed 16-bit max of two packed bf16 values with the halves of `floor`
+// Signed 16-bit max of two packed bf16 values with the halves of `lo`
 // (one v_pk_max_i16).
-__device__ __forceinline__ uint32_t relu_bf16x2(uint32_t v, uint32_t floor) {
+__device__ __forceinline__ uint32_t relu_bf16x2(uint32_t v, uint32_t lo) {
   typedef short short2_t __attribute__((ext_vector_type(2)));
   // (Opaque to the compiler: otherwise it splits a packed conversion that
   // feeds this max into two single ones and a permute.)
   asm("" : "+v"(v));
   return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(short2_t, v),
-                                                                __builtin_bit_cast(short2_t, floor)));
+                                                                __builtin_bit_cast(short2_t, lo)));
 }
 
 __device__ __forceinline__ bf16x8 as_bf16x8(u32x4 v) { return __builtin_bit_cast(bf16x8, v); }
@@ -442,8 +442,8 @@ conv3x3_tiled_kernel(const uint16_t* __restrict__ x, int ldx, long long xcs, int
     char* pb = reinterpret_cast<char*>(pool) + 2 * ((imgo + (long long)(y0 >> 1) * Wo + (x0 >> 1)) * ldp + co0);
     // (Recomputed rather than kept from the stores above: holding those
     // words until here would cost registers.)
-    uint32_t floor = relu_floor;
-    asm volatile("" : "+s"(floor));
+    uint32_t lo = relu_floor;
+    asm volatile("" : "+s"(lo));
     int ln = lane;
     asm volatile("" : "+v"(ln));
 #pragma unroll
@@ -455,8 +455,8 @@ conv3x3_tiled_kernel(const uint16_t* __restrict__ x, int ldx, long long xcs, int
         for (int r = 0; r < 4; r += 2) {
           const int xr = ((m & 1) * 16 + (ln >> 4) * 4 + r) >> 1;
           if (yo >= Ho || (x0 >> 1) + xr >= Wo || co0 + co >= cout_store) continue;
-          const uint32_t T = relu_bf16x2(to_bf16x2(acc[m][nb][r], acc[m][nb][r + 1]), floor);
-          const uint32_t U = relu_bf16x2(to_bf16x2(acc[m + 2][nb][r], acc[m + 2][nb][r + 1]), floor);
+          const uint32_t T = relu_bf16x2(to_bf16x2(acc[m][nb][r], acc[m][nb][r + 1]), lo);
+          const uint32_t U = relu_bf16x2(to_bf16x2(acc[m + 2][nb][r], acc[m + 2][nb][r + 1]), lo);
           const float sum = (__uint_as_float(T << 16) + __uint_as_float(T & 0xFFFF0000u)) +
                             (__uint_as_float(U << 16) + __uint_as_float(U & 0xFFFF0000u));
           const uint32_t off = ((uint32_t)(wave * Wo + xr) * (uint32_t)ldp + (uint32_t)co) * 2u;
