@@ -63,6 +63,7 @@ constexpr int kTileH = 8, kTileW = 32;
 constexpr int kPatchH = kTileH + 2, kPatchW = kTileW + 2;
 constexpr int kPatchStride = 40;
 constexpr int kPatchLoads = (kPatchH * kPatchW * 4 + kConvThreads - 1) / kConvThreads;  // 16-byte loads per thread
+constexpr int kRawLoads = (kPatchH * kPatchW + kConvThreads - 1) / kConvThreads;  // first layer: pixels per thread
 
 constexpr float kLogZmin = -1.2039728043259361f;  // log(0.3)
 constexpr float kLogZmax = 3.912023005428146f;    // log(50)
@@ -208,6 +209,20 @@ conv3x3_tiled_kernel(const uint16_t* __restrict__ x, int ldx, long long xcs, int
       // instructions) rather than held in registers across the loop.
       int tid = threadIdx.x;
       asm volatile("" : "+v"(tid));
+      if (RAW) {  // one lane per pixel
+        const char* rb = reinterpret_cast<const char*>(raw_rgba + base);
+        const char* db = reinterpret_cast<const char*>(raw_depth + base);
+#pragma unroll
+        for (int k = 0; k < kRawLoads; ++k) {
+          const int e = tid + k * kConvThreads;
+          const int pix = e < kPatchH * kPatchW ? e : 0;
+          const int py = pix / kPatchW, px = pix - py * kPatchW;
+          const uint32_t rel = (uint32_t)(py * W + px);
+          pre[k] = u32x4{*reinterpret_cast<const uint32_t*>(rb + rel * 4u),
+                         *reinterpret_cast<const uint32_t*>(db + rel * 4u), (uint32_t)(raw_mask + base)[rel], 0u};
+        }
+        return;
+      }
 #pragma unroll
       for (int k = 0; k < kPatchLoads; ++k) {
         const int e = tid + k * kConvThreads;
@@ -215,19 +230,25 @@ conv3x3_tiled_kernel(const uint16_t* __restrict__ x, int ldx, long long xcs, int
         const int pix = e < kPatchH * kPatchW * 4 ? e >> 2 : 0;
         const int py = pix / kPatchW, px = pix - py * kPatchW;
         const uint32_t rel = ups ? (uint32_t)(((py + 1) >> 1) * (W >> 1) + ((px + 1) >> 1)) : (uint32_t)(py * W + px);
-        if (RAW) {
-          const char* rb = reinterpret_cast<const char*>(raw_rgba + base);
-          const char* db = reinterpret_cast<const char*>(raw_depth + base);
-          pre[k] = u32x4{*reinterpret_cast<const uint32_t*>(rb + rel * 4u),
-                         *reinterpret_cast<const uint32_t*>(db + rel * 4u), (uint32_t)(raw_mask + base)[rel], 0u};
-        } else {
-          const char* xb = reinterpret_cast<const char*>(x + (base * ldx + (ci0 >> 5) * xcs));
-          pre[k] = *reinterpret_cast<const u32x4*>(xb + (rel * (uint32_t)ldx + (uint32_t)(e & 3) * 8u) * 2u);
-        }
+        const char* xb = reinterpret_cast<const char*>(x + (base * ldx + (ci0 >> 5) * xcs));
+        pre[k] = *reinterpret_cast<const u32x4*>(xb + (rel * (uint32_t)ldx + (uint32_t)(e & 3) * 8u) * 2u);
       }
       return;
     }
     inside_bits = 0;
+    if (RAW) {  // one lane per pixel, clamped into the frame
+#pragma unroll
+      for (int k = 0; k < kRawLoads; ++k) {
+        const int e = threadIdx.x + k * kConvThreads;
+        const int py = e / kPatchW, px = e - py * kPatchW;
+        const int gy = y0 + py - 1, gx = x0 + px - 1;
+        const bool inside = e < kPatchH * kPatchW && gy >= 0 && gy < H && gx >= 0 && gx < W;
+        inside_bits |= (uint32_t)inside << k;
+        const long long q = img + (long long)min(max(gy, 0), H - 1) * W + min(max(gx, 0), W - 1);
+        pre[k] = u32x4{raw_rgba[q], __float_as_uint(raw_depth[q]), (uint32_t)raw_mask[q], 0u};
+      }
+      return;
+    }
 #pragma unroll
     for (int k = 0; k < kPatchLoads; ++k) {
       const int e = threadIdx.x + k * kConvThreads;
@@ -237,19 +258,30 @@ conv3x3_tiled_kernel(const uint16_t* __restrict__ x, int ldx, long long xcs, int
       const bool inside = e < kPatchH * kPatchW * 4 && gy >= 0 && gy < H && gx >= 0 && gx < W;
       inside_bits |= (uint32_t)inside << k;
       const int cy = min(max(gy, 0), H - 1), cx = min(max(gx, 0), W - 1);
-      if (RAW) {
-        const long long q = img + (long long)cy * W + cx;
-        pre[k] = u32x4{raw_rgba[q], __float_as_uint(raw_depth[q]), (uint32_t)raw_mask[q], 0u};
-      } else {
-        // ups: x is the half-resolution image and the input is its nearest
-        // x2 upsampling, read in place.
-        const long long src = ups ? (img >> 2) + (long long)(cy >> 1) * (W >> 1) + (cx >> 1)
-                                  : img + (long long)cy * W + cx;
-        pre[k] = *reinterpret_cast<const u32x4*>(x + src * ldx + (ci0 >> 5) * xcs + part * 8);
-      }
+      // ups: x is the half-resolution image and the input is its nearest x2
+      // upsampling, read in place.
+      const long long src = ups ? (img >> 2) + (long long)(cy >> 1) * (W >> 1) + (cx >> 1)
+                                : img + (long long)cy * W + cx;
+      pre[k] = *reinterpret_cast<const u32x4*>(x + src * ldx + (ci0 >> 5) * xcs + part * 8);
     }
   };
   auto store_patch = [&]() {
+    if (RAW) {
+      // The first layer: each pixel's packed input (built channel by channel
+      // as the input-packing kernel does) in its first 8 channels; the other
+      // 24 stay zero from the start.
+#pragma unroll
+      for (int k = 0; k < kRawLoads; ++k) {
+        const int e = threadIdx.x + k * kConvThreads;
+        const u32x4 v = pre[k];
+        asm volatile("" : : "v"(v));  // (as below)
+        if (e >= kPatchH * kPatchW) continue;
+        const u32x4 c = ((inside_bits >> k) & 1u) ? input_channels(v[0], __uint_as_float(v[1]), (uint8_t)v[2])
+                                                  : u32x4{0u, 0u, 0u, 0u};
+        *reinterpret_cast<u32x4*>(patch + e * kPatchStride) = c;
+      }
+      return;
+    }
 #pragma unroll
     for (int k = 0; k < kPatchLoads; ++k) {
       const int e = threadIdx.x + k * kConvThreads;
@@ -262,9 +294,6 @@ conv3x3_tiled_kernel(const uint16_t* __restrict__ x, int ldx, long long xcs, int
       asm volatile("" : : "v"(v));
       if (e >= kPatchH * kPatchW * 4) continue;
       const bool inside = (inside_bits >> k) & 1u;
-      // The first layer: its packed input (Cin 32) built channel by channel
-      // as the input-packing kernel does, in the first 8 channels.
-      if (RAW) v = (e & 3) == 0 ? input_channels(v[0], __uint_as_float(v[1]), (uint8_t)v[2]) : u32x4{0u, 0u, 0u, 0u};
       if (!inside) v = u32x4{0u, 0u, 0u, 0u};
       *reinterpret_cast<u32x4*>(patch + (e >> 2) * kPatchStride + (e & 3) * 8) = v;
     }
@@ -274,6 +303,9 @@ conv3x3_tiled_kernel(const uint16_t* __restrict__ x, int ldx, long long xcs, int
   for (int m = 0; m < 4; ++m)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) acc[m][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+  if (RAW)  // channels 8..31 of the first layer's patch stay zero
+    for (int e = threadIdx.x; e < kPatchH * kPatchW * 4; e += kConvThreads)
+      *reinterpret_cast<u32x4*>(patch + (e >> 2) * kPatchStride + (e & 3) * 8) = u32x4{0u, 0u, 0u, 0u};
   int v = blockIdx.x, ci0 = 0;
   if (v < ntiles) {
     load_patch(v, 0);
