@@ -615,41 +615,63 @@ __global__ __launch_bounds__(256) void conv3x3_wgrad_kernel(const uint16_t* __re
   };
   // dy[y0 + r][x0 + c][co0 + ch] -> sdy[ch][r][c]; x[y0 - 1 + rr][x0 - 1 + pc]
   // [ci0 + ch] -> sx[s][ch][rr][pc - s] for the shifts s = 0, 1, 2 whose
-  // column pc - s lies in [0, 32).  Pixels run fastest across lanes, so a
-  // wave's 16-bit stores fill rows.
+  // column pc - s lies in [0, 32).  Lanes 2i and 2i + 1 hold two neighbouring
+  // pixels of one row (the rows' widths are even) with the same 8 channels;
+  // they swap half their channels (one DPP exchange per 2 words) so that
+  // each holds 4 channels of both pixels, written as 4-byte pixel pairs
+  // (shifts 0 and 2, whose pairs start on even columns; shift 1 keeps
+  // 2-byte stores of the lane's own pixel).
+  static_assert(kDyItems % 256 == 0, "every dy item of a tile is in use");
+  const int odd = threadIdx.x & 1;
+  auto pair_up = [&](const u32x4& v, bool ok, uint32_t (&o)[4]) {
+    // o[i]: channel 4 * odd + i of the pixel pair (even pixel in the low half)
+    const uint32_t w0 = ok ? v[0] : 0u, w1 = ok ? v[1] : 0u, w2 = ok ? v[2] : 0u, w3 = ok ? v[3] : 0u;
+    const uint32_t r0 = (uint32_t)__builtin_amdgcn_mov_dpp((int)(odd ? w0 : w2), 0xB1, 0xF, 0xF, true);
+    const uint32_t r1 = (uint32_t)__builtin_amdgcn_mov_dpp((int)(odd ? w1 : w3), 0xB1, 0xF, 0xF, true);
+    const uint32_t a0 = odd ? r0 : w0, b0 = odd ? w2 : r0, a1 = odd ? r1 : w1, b1 = odd ? w3 : r1;
+    o[0] = __builtin_amdgcn_perm(b0, a0, 0x05040100u);
+    o[1] = __builtin_amdgcn_perm(b0, a0, 0x07060302u);
+    o[2] = __builtin_amdgcn_perm(b1, a1, 0x05040100u);
+    o[3] = __builtin_amdgcn_perm(b1, a1, 0x07060302u);
+  };
   auto store_tile = [&]() {
 #pragma unroll
     for (int k = 0; k < kDyPer; ++k) {
       const int e = threadIdx.x + 256 * k;
-      if (e >= kDyItems) continue;
       const int px = e % (kWgRows * kWgCols), c8 = (e / (kWgRows * kWgCols)) * 8;
-      const bool ok = (okdy >> k) & 1u;
-      uint16_t* d = sdy + c8 * kWgDyStride + (px / kWgCols) * kWgRowStride + px % kWgCols;
+      uint32_t o[4];
+      pair_up(vdy[k], (okdy >> k) & 1u, o);
+      const int pe = px & ~1;
+      uint16_t* d = sdy + (c8 + 4 * odd) * kWgDyStride + (pe / kWgCols) * kWgRowStride + pe % kWgCols;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const uint32_t w = ok ? vdy[k][j] : 0u;
-        d[(2 * j) * kWgDyStride] = (uint16_t)(w & 0xFFFFu);
-        d[(2 * j + 1) * kWgDyStride] = (uint16_t)(w >> 16);
-      }
+      for (int i = 0; i < 4; ++i) *reinterpret_cast<uint32_t*>(d + i * kWgDyStride) = o[i];
     }
 #pragma unroll
     for (int k = 0; k < kXPer; ++k) {
       const int e = threadIdx.x + 256 * k;
-      if (e >= kXItems) continue;
       const int px = e % kXPix, c8 = (e / kXPix) * 8;
       const int rr = px / (kWgCols + 2), pc = px % (kWgCols + 2);
       const bool ok = (okx >> k) & 1u;
+      uint32_t o[4];
+      pair_up(vx[k], ok, o);  // (all lanes, before any skip)
+      if (e >= kXItems) continue;
+      const int pe = pc & ~1;
 #pragma unroll
-      for (int sh = 0; sh < 3; ++sh) {
-        const int c = pc - sh;
+      for (int sh = 0; sh < 3; sh += 2) {
+        const int c = pe - sh;
         if (c < 0 || c >= kWgCols) continue;
-        uint16_t* d = sx + (sh * kWgTci + c8) * kWgXStride + rr * kWgRowStride + c;
+        uint16_t* d = sx + (sh * kWgTci + c8 + 4 * odd) * kWgXStride + rr * kWgRowStride + c;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const uint32_t w = ok ? vx[k][j] : 0u;
-          d[(2 * j) * kWgXStride] = (uint16_t)(w & 0xFFFFu);
-          d[(2 * j + 1) * kWgXStride] = (uint16_t)(w >> 16);
-        }
+        for (int i = 0; i < 4; ++i) *reinterpret_cast<uint32_t*>(d + i * kWgXStride) = o[i];
+      }
+      const int c = pc - 1;
+      if (c < 0 || c >= kWgCols) continue;
+      uint16_t* d = sx + (kWgTci + c8) * kWgXStride + rr * kWgRowStride + c;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t w = ok ? vx[k][j] : 0u;
+        d[(2 * j) * kWgXStride] = (uint16_t)(w & 0xFFFFu);
+        d[(2 * j + 1) * kWgXStride] = (uint16_t)(w >> 16);
       }
     }
   };
